@@ -6,10 +6,11 @@ eta = sigma * d + sigma' (row-major), for which vec(A rho B) = (A kron B^T) vec(
 A Kraus map rho -> sum_k K rho K^dagger therefore has superoperator sum_k K kron conj(K).
 
 Circuit model (Sec. IV, Eq. (tfim_model); noise of Sec. II): a layer is
-    Ising phase blocks exp(-i gamma Z(x)Z) on even bonds, then on odd bonds, each block
-    followed by a |1> -> |r> leak on both of its atoms;
+    Ising phase blocks exp(-i gamma Z(x)Z) on even bonds (left to right), then on odd
+    bonds (right to left), each block followed by a |1> -> |r> leak on both its atoms;
     then exp(-i beta X) on every atom;
     then qubit dephasing on every atom; then Rydberg decay on every atom.
+(see ``circuit_ops`` for where the single-atom maps sit relative to later blocks).
 Z and X act on the qubit levels {0,1} only and are zero on |r> (and on the lost level),
 so the rotations are the identity there.
 """
@@ -162,26 +163,36 @@ def circuit_ops(spec):
     """The circuit of a CircuitSpec as an ordered list of Kraus operations.
 
     Each item is ("k2", i, kraus) for a map on atoms (i, i+1), or ("k1", j, kraus).
-    Layer order: even bonds left to right, odd bonds left to right, mixer, dephasing,
-    decay (all per atom).
+    Layer k: Ising blocks on even bonds left to right, then on odd bonds right to left;
+    then, on every atom, exp(-i beta_k X), dephasing and decay.  The single-atom maps of
+    layer k commute with every operation of layer k+1 that does not touch their atom, so
+    they are listed right before the first block of layer k+1 that acts on that atom (the
+    ones of the last layer close the list).  As a channel this is exactly "noise after
+    each layer"; the listed order fixes when each bond truncation sees that noise.
     """
     n, d = spec.n, spec.d
     ops = []
+    pending = [[] for _ in range(n)]
+
+    def flush(j):
+        for kraus in pending[j]:
+            ops.append(("k1", j, kraus))
+        pending[j] = []
+
     for k in range(spec.p):
         g2 = gate_kraus_2site(spec.gamma[k], spec.p_leak, d)
-        for i in range(0, n - 1, 2):
-            ops.append(("k2", i, g2))
-        for i in range(1, n - 1, 2):
+        bonds = list(range(0, n - 1, 2)) + list(range(1, n - 1, 2))[::-1]
+        for i in bonds:
+            flush(i)
+            flush(i + 1)
             ops.append(("k2", i, g2))
         ux = [u_x(spec.beta[k], d)]
         deph = kraus_dephasing(spec.p_deph, d)
         dec = kraus_decay(spec.p_decay, d)
         for j in range(n):
-            ops.append(("k1", j, ux))
-        for j in range(n):
-            ops.append(("k1", j, deph))
-        for j in range(n):
-            ops.append(("k1", j, dec))
+            pending[j] = [ux, deph, dec]
+    for j in range(n):
+        flush(j)
     return ops
 
 
