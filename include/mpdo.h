@@ -1,0 +1,161 @@
+/*
+ * mpdo.h -- C ABI of libmpdo: the two-site update of a vectorised density-operator MPO
+ * with Purity-Preserving Truncation, on one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: "Simulating Large One-Dimensional Neutral Atom Quantum Systems" (arXiv 2309.08572).
+ *
+ * State (Sec. III, Eq. (MPO) and "MPO form of the noisy CZ gate"): rho over N atoms of d
+ * levels is a chain of site tensors A_j[l][eta][r], complex, row-major, l slowest, with the
+ * vectorised physical index eta = sigma*d + sigma' (D2 = d*d values) and bond dimensions
+ * chi_l, chi_r <= chi_max.  Superoperators act on eta: a Kraus map rho -> sum K rho K^+
+ * is sum K (x) conj(K) in this basis.
+ *
+ * Conventions for every call
+ *  - Host arrays are copied before the call returns; the caller keeps ownership.
+ *  - Complex numbers are interleaved pairs of doubles (re, im), row-major.
+ *  - Device state belongs to the context.  Work is enqueued on the context's HIP stream;
+ *    calls that return host data (expect, trace, a non-null info, bond_dims, get_site)
+ *    synchronise that stream.
+ *  - Every call returns a status and never throws.  mpdo_last_error() returns the message
+ *    of the last failure.  After MPDO_E_NUMERIC or MPDO_E_DEVICE the context is poisoned
+ *    and later calls return MPDO_E_STATE.  An infeasible PPT cut is not an error: it falls
+ *    back to theta = 0 (end of Sec. III.D) and is reported in mpdo_trunc_info.
+ *  - A context is not re-entrant; use one context per stream.
+ */
+#ifndef MPDO_H
+#define MPDO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpdo_ctx_s* mpdo_ctx;
+
+typedef enum {
+    MPDO_OK = 0,
+    MPDO_E_ARG = 1,         /* bad index, size, pointer, non-finite or non-CPTP input   */
+    MPDO_E_STATE = 2,       /* context poisoned or not initialised                       */
+    MPDO_E_NOMEM = 3,       /* device allocation failed or workspace too small          */
+    MPDO_E_DEVICE = 4,      /* a HIP call failed                                         */
+    MPDO_E_NUMERIC = 5,     /* NaN/Inf in a merged tensor or the eigensolver diverged   */
+    MPDO_E_UNSUPPORTED = 6  /* a size beyond the compiled limits                         */
+} mpdo_status;
+
+typedef enum {
+    MPDO_FP64 = 0,          /* every contraction and Gram product in FP64 (MFMA f64)     */
+    MPDO_FP32 = 1           /* contractions and Gram products on FP32 MFMA with FP32
+                               accumulation; eigensolve, PPT and observables in FP64     */
+} mpdo_precision;
+
+typedef struct {
+    int n_sites;            /* N >= 2                                                    */
+    int d;                  /* levels per atom, 2..4 (D2 = d*d <= 16)                    */
+    int chi_max;            /* bond-dimension cap, 1..1024                               */
+    int precision;          /* mpdo_precision                                            */
+    double cutoff_rel;      /* drop Schmidt values below cutoff_rel * largest; 0 -> 1e-14
+                               (MPDO_FP64) or 1e-6 (MPDO_FP32)                        */
+    int ppt;                /* 1: Purity-Preserving Truncation (Sec. III.D); 0: plain cut */
+    int renorm_trace;       /* 1: rescale the cut spectrum so tr(rho) is unchanged       */
+    void* hip_stream;       /* hipStream_t to enqueue on; NULL = the null stream         */
+} mpdo_config;
+
+typedef struct {
+    int bond;               /* left site of the updated pair                             */
+    int chi_l, chi_mid, chi_r;  /* bond dimensions around the pair before the update     */
+    int kept;               /* new bond dimension                                        */
+    int path;               /* 0: theta formed explicitly; 1: factored through the gate's
+                               operator-Schmidt decomposition                            */
+    int eig_calls;          /* Hermitian eigensolves this update made                    */
+    int ppt_feasible;       /* 0 when |T'| < |T| cos(phi) and theta = 0 was used         */
+    double trace_before;    /* tr(rho) = sum T_i Lambda_i before the cut                 */
+    double trace_after;     /* tr(rho) after the cut and PPT                             */
+    double xi_before;       /* tr(rho^2)/tr(rho)^2 before the cut                        */
+    double xi_after;        /* the same after the cut and PPT                            */
+    double ppt_theta;       /* angle theta of Eq. (xiformula)                            */
+    double discarded_weight;/* 1 - sum_kept Lambda^2 / |Lambda|^2                        */
+    double max_abs_imag_t;  /* largest |Im T'_i Lambda'_i| relative to |tr rho|          */
+    double sigma_max;       /* largest Schmidt value                                     */
+    double sigma_min_kept;  /* smallest kept Schmidt value                               */
+} mpdo_trunc_info;
+
+/* Create a context for a chain described by cfg.  Allocates nothing on the device until
+ * mpdo_bind_workspace or mpdo_init_product_state (which allocates with hipMalloc when no
+ * workspace is bound).  E_ARG for sizes out of range. */
+mpdo_status mpdo_create(const mpdo_config* cfg, mpdo_ctx* out);
+
+/* Release the context and any device memory it allocated itself. */
+mpdo_status mpdo_destroy(mpdo_ctx ctx);
+
+/* Device bytes the context needs for cfg (site tensors at chi_max plus scratch). */
+size_t mpdo_workspace_bytes(const mpdo_config* cfg);
+
+/* Hand the context a caller-owned device buffer of `bytes` (>= mpdo_workspace_bytes) that
+ * stays alive until mpdo_destroy.  Must precede mpdo_init_product_state.  E_NOMEM if too
+ * small, E_STATE if device memory is already in use. */
+mpdo_status mpdo_bind_workspace(mpdo_ctx ctx, void* device_ptr, size_t bytes);
+
+/* Initial product state rho = (x)_j rho_j (Sec. IV: |+_X> on every atom).
+ * rho_sites: n_sites * d * d complex (host), rho_j row-major.  Each site becomes a
+ * 1 x D2 x 1 tensor; the canonical centre is site 0.  Clears pending channels. */
+mpdo_status mpdo_init_product_state(mpdo_ctx ctx, const double* rho_sites);
+
+/* Two-site update (Sec. III.A "MPO form of the noisy CZ gate"; Fig. (ansatzes)c;
+ * Fig. (mpo_mpdo_update_comparisons)a): apply the channel `superop` to atoms
+ * (site, site+1), split the merged tensor, cut to chi_max and apply PPT (Sec. III.D,
+ * Eqs. (xiformula), (ppt)).  superop: D2^2 x D2^2 complex (host), row index
+ * eta_site*D2 + eta_{site+1}.  Channels queued on the two atoms by mpdo_apply_channel act
+ * first.  info may be NULL.  E_ARG for site outside [0, N-2] or non-finite entries. */
+mpdo_status mpdo_apply_gate(mpdo_ctx ctx, int site, const double* superop,
+                            mpdo_trunc_info* info);
+
+/* As mpdo_apply_gate, for a two-atom Kraus map: kraus holds n_kraus operators of
+ * d^2 x d^2 complex (host) on the index sigma_site*d + sigma_{site+1}.  E_ARG if
+ * sum K^+ K differs from the identity by more than 1e-10. */
+mpdo_status mpdo_apply_gate_kraus(mpdo_ctx ctx, int site, int n_kraus, const double* kraus,
+                                  mpdo_trunc_info* info);
+
+/* Single-atom channel (Sec. II noise; Sec. IV mixer): n_kraus operators of d x d complex
+ * (host).  The map is queued on the atom and enters the next two-site update that touches
+ * it (maps on different atoms commute), or the next expectation.  E_ARG if not trace
+ * preserving within 1e-10. */
+mpdo_status mpdo_apply_channel(mpdo_ctx ctx, int site, int n_kraus, const double* kraus);
+
+/* Cut bond (bond, bond+1) to at most chi (<= chi_max) with PPT: the two-site update with
+ * the identity superoperator.  Queued channels on the two atoms are applied first. */
+mpdo_status mpdo_truncate(mpdo_ctx ctx, int bond, int chi, mpdo_trunc_info* info);
+
+/* Linear observables by transfer matrices (Sec. III.E; Eq. (tfim_hamiltonian)):
+ * term t is the product of n_sites_in_term[t] single-atom operators on consecutive atoms
+ * starting at first_site[t]; ops holds all of them concatenated, d x d complex each (host).
+ * out[2t], out[2t+1] = re, im of tr(rho O_t), divided by tr(rho) when normalize != 0.
+ * Queued channels are applied to the operators (Heisenberg picture). */
+mpdo_status mpdo_expect(mpdo_ctx ctx, int n_terms, const int* first_site,
+                        const int* n_sites_in_term, const double* ops, int normalize,
+                        double* out);
+
+/* tr(rho): out[0], out[1] = re, im. */
+mpdo_status mpdo_trace(mpdo_ctx ctx, double* out);
+
+/* Current bond dimensions: out[j] for bond (j, j+1), j < N-1. */
+mpdo_status mpdo_bond_dims(mpdo_ctx ctx, int* out);
+
+/* Copy site tensor j to the host as complex128 [chi_l][D2][chi_r] (queued channels not
+ * applied); shape[0..2] receives its dimensions.  out may be NULL to query the shape. */
+mpdo_status mpdo_get_site(mpdo_ctx ctx, int site, double* out, int* shape);
+
+/* Block until all work of the context has finished. */
+mpdo_status mpdo_synchronize(mpdo_ctx ctx);
+
+/* Message of the last failed call on ctx (or of mpdo_create when ctx is NULL). */
+const char* mpdo_last_error(mpdo_ctx ctx);
+
+/* Library build string (compiler, target). */
+const char* mpdo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPDO_H */

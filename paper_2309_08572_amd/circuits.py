@@ -1,0 +1,126 @@
+"""QAOA circuits on the GPU MPO: Kraus inputs and the driver loop.
+
+Circuit (Sec. IV, Eq. (tfim_model); noise model of Sec. II as discrete maps):
+layer k = exp(-i gamma_k Z(x)Z) blocks on even bonds left to right, then odd bonds right to
+left, each followed by a |1> -> |r> leak on both atoms; then exp(-i beta_k X), qubit
+dephasing and Rydberg decay on every atom.  The single-atom maps are queued in the library
+and enter the next block that touches the atom (they commute with everything else), which
+fixes the order of truncations; the last layer's maps act on the observables.
+Measured: TFIM energy H = -sum Z_i Z_{i+1} - g sum X_i (Eq. (tfim_hamiltonian), b = 0),
+per-atom level populations and the all-qubit probability (Sec. IV, qubit trace).
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Optional
+
+import numpy as np
+
+from .mpdo import MPDO, MPDO_FP32, MPDO_FP64
+
+# decay branching into |0>, |1>, dark (Fig. 1 caption)
+BRANCH = (1.0 / 16.0, 1.0 / 16.0, 7.0 / 8.0)
+
+
+def _e(d, a, b):
+    m = np.zeros((d, d), dtype=np.complex128)
+    m[a, b] = 1.0
+    return m
+
+
+def zz_gate(gamma: float, d: int) -> np.ndarray:
+    """exp(-i gamma Z(x)Z) with Z = |0><0| - |1><1| (zero on other levels): diagonal phases."""
+    z = np.zeros(d)
+    z[0], z[1] = 1.0, -1.0
+    ph = np.exp(-1j * gamma * np.outer(z, z).reshape(-1))
+    return np.diag(ph)
+
+
+def x_rotation(beta: float, d: int) -> np.ndarray:
+    """exp(-i beta X) with X = |0><1| + |1><0|: a rotation on {0,1}, identity elsewhere."""
+    u = np.eye(d, dtype=np.complex128)
+    u[0, 0] = u[1, 1] = math.cos(beta)
+    u[0, 1] = u[1, 0] = -1j * math.sin(beta)
+    return u
+
+
+def leak_kraus(p: float, d: int):
+    k0 = np.eye(d, dtype=np.complex128)
+    k0[1, 1] = math.sqrt(1.0 - p)
+    return [k0, math.sqrt(p) * _e(d, 2, 1)]
+
+
+def dephasing_kraus(p: float, d: int):
+    k0 = np.eye(d, dtype=np.complex128)
+    k0[0, 0] = k0[1, 1] = math.sqrt(1.0 - p)
+    k1 = np.zeros((d, d), dtype=np.complex128)
+    k1[0, 0], k1[1, 1] = math.sqrt(p), -math.sqrt(p)
+    return [k0, k1]
+
+
+def decay_kraus(p: float, d: int):
+    k0 = np.eye(d, dtype=np.complex128)
+    k0[2, 2] = math.sqrt(1.0 - p)
+    if d == 3:
+        return [k0, math.sqrt(p) * _e(d, 1, 2)]
+    return [k0] + [math.sqrt(p * b) * _e(d, j, 2) for j, b in zip((0, 1, 3), BRANCH)]
+
+
+def block_kraus(gamma: float, p_leak: float, d: int):
+    """Two-atom Kraus operators of one Ising block followed by the leak on both atoms."""
+    u = zz_gate(gamma, d)
+    lk = leak_kraus(p_leak, d)
+    return [np.kron(a, b) @ u for a in lk for b in lk]
+
+
+def plus_rho(d: int) -> np.ndarray:
+    v = np.zeros(d, dtype=np.complex128)
+    v[0] = v[1] = 1.0 / math.sqrt(2.0)
+    return np.outer(v, v.conj())
+
+
+def bond_order(n: int):
+    return list(range(0, n - 1, 2)) + list(range(1, n - 1, 2))[::-1]
+
+
+def run_circuit(spec, precision: int = MPDO_FP64, chi: Optional[int] = None, ppt: bool = True,
+                infos: Optional[list] = None, m: Optional[MPDO] = None) -> MPDO:
+    """Evolve |+><+|^N through the spec's circuit; returns the MPDO (state on the GPU)."""
+    n, d = spec.n, spec.d
+    chi = spec.chi if chi is None else chi
+    if m is None:
+        m = MPDO(n, d, chi, precision=precision, ppt=ppt)
+    m.init_product_state([plus_rho(d)] * n)
+    want_info = infos is not None
+    for k in range(spec.p):
+        kr = block_kraus(spec.gamma[k], spec.p_leak, d)
+        for i in bond_order(n):
+            inf = m.apply_gate_kraus(i, kr, info=want_info)
+            if want_info:
+                infos.append(inf)
+        ux = [x_rotation(spec.beta[k], d)]
+        dp = dephasing_kraus(spec.p_deph, d)
+        dc = decay_kraus(spec.p_decay, d)
+        for j in range(n):
+            m.apply_channel(j, ux)
+            m.apply_channel(j, dp)
+            m.apply_channel(j, dc)
+    return m
+
+
+def observables(m: MPDO, g: float = 1.0) -> dict:
+    n, d = m.n, m.d
+    Z = np.zeros((d, d), dtype=np.complex128)
+    Z[0, 0], Z[1, 1] = 1.0, -1.0
+    X = np.zeros((d, d), dtype=np.complex128)
+    X[0, 1] = X[1, 0] = 1.0
+    terms = [(i, [Z, Z]) for i in range(n - 1)] + [(i, [X]) for i in range(n)]
+    pops = [(j, [_e(d, a, a)]) for j in range(n) for a in range(d)]
+    pq = _e(d, 0, 0) + _e(d, 1, 1)
+    vals = m.expect(terms + pops + [(0, [pq] * n)], normalize=True)
+    nzz = n - 1
+    energy = -np.sum(vals[:nzz]).real - g * np.sum(vals[nzz:nzz + n]).real
+    popv = vals[nzz + n:nzz + n + n * d].real.reshape(n, d)
+    return {"trace": m.trace(), "energy_per_site": energy / n, "populations": popv,
+            "p_success": float(vals[-1].real)}

@@ -1,0 +1,1230 @@
+// libmpdo host side: the C ABI of include/mpdo.h and the orchestration of one two-site
+// update of the vectorised density-operator MPO with Purity-Preserving Truncation.
+//
+// Update of atoms (i, i+1) (Sec. III.A, Fig. (ansatzes)c; Sec. III.D):
+//  1. single-atom channels queued on i and i+1 are folded into the two-site superoperator;
+//  2. the canonical centre is moved onto {i, i+1} (every site left of i a left isometry,
+//     every site right of i+1 a right isometry) by orthonormal-basis moves;
+//  3. theta = S . (A_i A_{i+1}) is split.  When the gate's operator-Schmidt rank r makes
+//     r * chi_mid smaller than the side being orthonormalised, theta is never formed: the
+//     split works on the factor pair theta = M_L M_R, M_L = [X_k A_i], M_R = [Y_k A_{i+1}];
+//     otherwise theta is formed with two matrix-core products (merge, then gate);
+//  4. Schmidt vectors come from FP64 Hermitian eigensolves of Gram matrices with
+//     residual deflation levels, so values far below sqrt(eps) of the largest are resolved;
+//  5. the spectrum is cut to chi (and the relative cutoff) and PPT rescales the kept
+//     values on the device (Eqs. (xiformula), (ppt));
+//  6. the isometric factor and the rescaled centre factor become the new site tensors.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/mpdo.h"
+#include "common.h"
+#include "eig.h"
+#include "gemm.h"
+#include "kernels.h"
+
+using namespace mpdo;
+typedef std::complex<double> zc;
+
+namespace {
+
+constexpr double EPS64 = 2.220446049250313e-16;
+constexpr double EPS32 = 1.1920928955078125e-07;
+constexpr int MAX_FACTOR_RANK = 16;   // operator-Schmidt terms kept in LDS by phys_* kernels
+constexpr int EIG_MAX_SWEEPS = 40;
+
+struct Fail {
+    mpdo_status st;
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) throw Fail{MPDO_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+inline cd C1() { return cd{1.0, 0.0}; }
+inline cd C0() { return cd{0.0, 0.0}; }
+inline cd Cr(double x) { return cd{x, 0.0}; }
+
+uint64_t fnv1a(const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// ---------------------------------------------------------------------- device arena
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    template <typename X>
+    X* take(size_t count) {
+        size_t bytes = ((count * sizeof(X)) + 255) & ~(size_t)255;
+        if (used + bytes > cap) throw Fail{MPDO_E_NOMEM, "workspace exhausted"};
+        X* p = (X*)(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+// ---------------------------------------------------------------------- scratch of one precision
+template <typename T>
+struct Scratch {
+    int nmax = 0;        // largest matrix side handled
+    T *bA, *bB, *bT1, *bQ, *bK, *bC, *bR, *bU, *bB2, *bG, *bZ, *bW, *bVT;
+    double *Gd, *Vd, *evals, *sig, *inv, *st, *sums, *lvec, *rvec, *tl, *tr, *fac, *pout, *sc, *vtmp, *vtmp2;
+    int* cnt;
+    void* eigwork;
+
+    static size_t bytes(int nmax) {
+        const size_t n2 = (size_t)nmax * nmax * 2;
+        size_t b = 0;
+        b += 13 * (n2 * sizeof(T) + 256);
+        b += 2 * (n2 * sizeof(double) + 256);
+        b += 14 * ((size_t)nmax * 2 * sizeof(double) + 256) + 4096;
+        b += eigh_work_bytes(nmax) + 256;
+        return b;
+    }
+    void carve(Arena& a, int n) {
+        nmax = n;
+        const size_t n2 = (size_t)n * n * 2;
+        bA = a.take<T>(n2);
+        bB = a.take<T>(n2);
+        bT1 = a.take<T>(n2);
+        bQ = a.take<T>(n2);
+        bK = a.take<T>(n2);
+        bC = a.take<T>(n2);
+        bR = a.take<T>(n2);
+        bU = a.take<T>(n2);
+        bB2 = a.take<T>(n2);
+        bG = a.take<T>(n2);
+        bZ = a.take<T>(n2);
+        bW = a.take<T>(n2);
+        Gd = a.take<double>(n2);
+        Vd = a.take<double>(n2);
+        bVT = std::is_same<T, double>::value ? (T*)Vd : a.take<T>(n2);
+        evals = a.take<double>((size_t)n * 2);
+        sig = a.take<double>((size_t)n * 2);
+        inv = a.take<double>((size_t)n * 2);
+        lvec = a.take<double>((size_t)n * 2);
+        rvec = a.take<double>((size_t)n * 2);
+        tl = a.take<double>((size_t)n * 2);
+        tr = a.take<double>((size_t)n * 2);
+        fac = a.take<double>((size_t)n * 2);
+        vtmp = a.take<double>((size_t)n * 2);
+        vtmp2 = a.take<double>((size_t)n * 2);
+        st = a.take<double>(64);
+        sums = a.take<double>(64);
+        pout = a.take<double>(64);
+        sc = a.take<double>(64);
+        cnt = a.take<int>(64);
+        eigwork = (void*)a.take<char>(eigh_work_bytes(n));
+    }
+};
+
+struct GateFactor {
+    int r = 0;
+    double* X = nullptr;   // r x D2 x D2 (device)
+    double* Y = nullptr;
+};
+
+}  // namespace
+
+// ====================================================================== context
+struct mpdo_ctx_s {
+    mpdo_config cfg{};
+    int N = 0, d = 0, D2 = 0, chi = 0;
+    bool fp32 = false;
+    double cutoff = 1e-14;
+    hipStream_t st = nullptr;
+    std::string err;
+    bool poisoned = false;
+    bool ready = false;
+
+    // memory
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    Arena arena;
+
+    // chain
+    std::vector<void*> site;      // N site buffers (T), capacity chi*D2*chi
+    std::vector<void*> spare;     // 2 spare buffers
+    std::vector<int> dims;        // dims[j]: bond between j-1 and j; dims[0] = dims[N] = 1
+    int centre = 0;
+    int dir = 1;
+    std::vector<std::vector<zc>> pending;   // D2 x D2 superoperator queued per atom
+    std::vector<char> pend_id;
+    double* ovec = nullptr;       // N x D2 complex: trace vector of each atom
+    double* Lv = nullptr;         // (N+1) x chi complex
+    double* Rv = nullptr;
+    int lvalid = 0, rvalid = 0;
+    double* Sdev = nullptr;       // D2^2 x D2^2 superoperator (FP64)
+    void* SdevT = nullptr;        // same in the working precision
+    double* hbuf = nullptr;       // pinned host buffer
+    int* hint = nullptr;
+
+    Scratch<double> sd;           // FP64 scratch (all work in FP64 mode; eigen/PPT always)
+    Scratch<float> sf;            // FP32 scratch (FP32 mode)
+    Scratch<double> sg;           // small FP64 scratch for gate factorisation (D2^2)
+    std::unordered_map<uint64_t, GateFactor> gcache;
+    std::vector<uint64_t> gorder;
+    std::vector<double*> gslots;  // free device slots for operator-Schmidt factors
+    double* obuf = nullptr;       // operator vectors of one expectation term (N x D2)
+
+    size_t site_cap() const { return (size_t)chi * D2 * chi * 2; }  // in T elements
+    size_t tsize() const { return fp32 ? sizeof(float) : sizeof(double); }
+};
+
+static thread_local std::string g_create_err;
+
+namespace {
+
+// ====================================================================== generic helpers
+template <typename T>
+CView<T> V(T* p, long rs, long cs, int conj = 0) {
+    return view<T>(p, rs, cs, conj);
+}
+
+template <typename T>
+struct Engine {
+    mpdo_ctx_s& c;
+    Scratch<T>& s;
+    hipStream_t st;
+    int eig_calls = 0;
+
+    Engine(mpdo_ctx_s& ctx, Scratch<T>& sc) : c(ctx), s(sc), st(ctx.st) {}
+
+    T* site(int j) { return (T*)c.site[j]; }
+    double eps() const { return std::is_same<T, double>::value ? EPS64 : EPS32; }
+
+    void sync() { HIPCHK(hipStreamSynchronize(st)); }
+
+    int read_int(const int* dp) {
+        HIPCHK(hipMemcpyAsync(c.hint, dp, sizeof(int), hipMemcpyDeviceToHost, st));
+        sync();
+        return c.hint[0];
+    }
+    void read_doubles(const double* dp, int n, double* out) {
+        HIPCHK(hipMemcpyAsync(c.hbuf, dp, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        memcpy(out, c.hbuf, n * sizeof(double));
+    }
+
+    void gemm(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_) {
+        HIPCHK(cgemm<T>(st, M, N, K, a, A, B, b, C_));
+    }
+
+    // Gram G = F^H F (c x c) of the n x c view F, into the FP64 eigen buffer (dense, ld c)
+    void gram_cols(CView<T> F, int n, int cc) {
+        if (std::is_same<T, double>::value) {
+            HIPCHK(cgemm<T>(st, cc, cc, n, C1(), adj(F), F, C0(), V<T>((T*)s.Gd, cc, 1)));
+        } else {
+            HIPCHK(cgemm<T>(st, cc, cc, n, C1(), adj(F), F, C0(), V<T>(s.bG, cc, 1)));
+            HIPCHK((geam<T, double>(st, cc, cc, C1(), V<T>(s.bG, cc, 1), C0(), V<double>(s.Gd, cc, 1))));
+        }
+    }
+
+    // eigen-decomposition of the Gram in s.Gd (order n): s.evals, s.Vd (ld n); s.bVT gets
+    // the eigenvectors in T
+    void eig(int n) {
+        int sw = 0;
+        HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, &sw, c.hint));
+        ++eig_calls;
+        if (sw >= EIG_MAX_SWEEPS) throw Fail{MPDO_E_NUMERIC, "Jacobi eigensolver did not converge"};
+        if (!std::is_same<T, double>::value)
+            HIPCHK((geam<double, T>(st, n, n, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));
+    }
+
+    // Newton-Schulz: make the n x q columns of Q (view, dense storage in buffer with ld) orthonormal
+    void ns_orth(T* Q, long ldq, int n, int q, int iters) {
+        for (int it = 0; it < iters; ++it) {
+            gemm(q, q, n, C1(), adj(V<T>(Q, ldq, 1)), V<T>(Q, ldq, 1), C0(), V<T>(s.bG, q, 1));
+            HIPCHK(ns_prep<T>(st, s.bG, q, s.bZ));
+            gemm(n, q, q, C1(), V<T>(Q, ldq, 1), V<T>(s.bZ, q, 1), C0(), V<T>(s.bW, q, 1));
+            HIPCHK((geam<T, T>(st, n, q, C1(), V<T>(s.bW, q, 1), C0(), V<T>(Q, ldq, 1))));
+        }
+    }
+
+    // Orthonormal basis of range(F) for the n x cc view F (two Gram levels).
+    // Q: n x q written to Qb (ld cc); K = Q^H F: q x cc written to Kb (ld cc).  Uses bT1.
+    int orth2(CView<T> F, int n, int cc, T* Qb, T* Kb) {
+        const double e = eps();
+        gram_cols(F, n, cc);
+        eig(cc);
+        // level 0: lambda > 1e-10 lambda_max (FP64) / 1e-5 (FP32)
+        const double tau0 = std::is_same<T, double>::value ? 1e-10 : 1e-5;
+        HIPCHK(spectrum_cut(st, s.evals, cc, 0, 0.0, 64.0 * e, tau0, cc, s.st, s.cnt, nullptr, s.inv));
+        const int q1 = read_int(s.cnt);
+        if (q1 == 0) return 0;
+        // Q1 = F W diag(lambda^-1/2)
+        gemm(n, q1, cc, C1(), F, V<T>(s.bVT, cc, 1), C0(), V<T>(Qb, cc, 1));
+        HIPCHK(scale_cols<T>(st, V<T>(Qb, cc, 1), n, q1, s.inv));
+        ns_orth(Qb, cc, n, q1, 3);
+        // K1 = Q1^H F
+        gemm(q1, cc, n, C1(), adj(V<T>(Qb, cc, 1)), F, C0(), V<T>(Kb, cc, 1));
+        // residual Fr = F - Q1 K1
+        HIPCHK((geam<T, T>(st, n, cc, C1(), F, C0(), V<T>(s.bT1, cc, 1))));
+        gemm(n, cc, q1, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(Kb, cc, 1), C1(), V<T>(s.bT1, cc, 1));
+        HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums));
+        double sums[2], st0[1];
+        read_doubles(s.sums, 2, sums);
+        read_doubles(s.st, 1, st0);
+        const double lam0 = st0[0];
+        // nothing left above the cutoff: done
+        if (!(sums[0] > c.cutoff * c.cutoff * lam0) || q1 >= n) return q1;
+        CView<T> Fr = V<T>(s.bT1, cc, 1);
+        gram_cols(Fr, n, cc);
+        eig(cc);
+        // level 1: lambda > max(cutoff^2 lambda_max, 4096 eps lambda_max(level))
+        const int cap = std::min(cc, n) - q1;
+        HIPCHK(spectrum_cut(st, s.evals, cc, 1, c.cutoff * c.cutoff, 4096.0 * e, 0.0, cap, s.st, s.cnt, nullptr,
+                            s.inv));
+        const int q2 = read_int(s.cnt);
+        if (q2 <= 0) return q1;
+        T* Q2 = Qb + 2 * q1;   // columns q1.. of Qb
+        gemm(n, q2, cc, C1(), Fr, V<T>(s.bVT, cc, 1), C0(), V<T>(Q2, cc, 1));
+        HIPCHK(scale_cols<T>(st, V<T>(Q2, cc, 1), n, q2, s.inv));
+        // Q2 -= Q1 (Q1^H Q2)
+        gemm(q1, q2, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(Q2, cc, 1), C0(), V<T>(s.bG, q2, 1));
+        gemm(n, q2, q1, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bG, q2, 1), C1(), V<T>(Q2, cc, 1));
+        ns_orth(Q2, cc, n, q2, 3);
+        gemm(q2, cc, n, C1(), adj(V<T>(Q2, cc, 1)), F, C0(), V<T>(Kb + 2 * (long)q1 * cc, cc, 1));
+        return q1 + q2;
+    }
+
+    // Left split of the a x b view F: U (a x kept) into Ub (ld chi_cap), Schmidt values in
+    // s.sig, B = U^H F (kept x b) into Bb (ld b).  Up to three deflation levels.
+    int split_left(CView<T> F, int a, int b, int chi, T* Ub, long ldu, T* Bb) {
+        const double e = eps();
+        int kacc = 0;
+        CView<T> R = F;
+        for (int lev = 0; lev < 3; ++lev) {
+            // H = R R^H (a x a)
+            if (std::is_same<T, double>::value) {
+                gemm(a, a, b, C1(), R, adj(R), C0(), V<T>((T*)s.Gd, a, 1));
+            } else {
+                gemm(a, a, b, C1(), R, adj(R), C0(), V<T>(s.bG, a, 1));
+                HIPCHK((geam<T, double>(st, a, a, C1(), V<T>(s.bG, a, 1), C0(), V<double>(s.Gd, a, 1))));
+            }
+            eig(a);
+            const double tau = (lev == 0) ? 1e-4 : 0.0;
+            const double noise = 64.0 * e;
+            HIPCHK(spectrum_cut(st, s.evals, a, lev, c.cutoff * c.cutoff, noise, tau, chi - kacc, s.st, s.cnt,
+                                s.sig + kacc, nullptr));
+            const int acc = read_int(s.cnt);
+            if (acc <= 0) break;
+            T* Vn = Ub + 2 * kacc;   // columns kacc.. of U
+            HIPCHK((geam<T, T>(st, a, acc, C1(), V<T>(s.bVT, a, 1), C0(), V<T>(Vn, ldu, 1))));
+            if (kacc > 0) {
+                gemm(kacc, acc, a, C1(), adj(V<T>(Ub, ldu, 1)), V<T>(Vn, ldu, 1), C0(), V<T>(s.bG, acc, 1));
+                gemm(a, acc, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Vn, ldu, 1));
+                ns_orth(Vn, ldu, a, acc, 3);
+            }
+            kacc += acc;
+            if (kacc >= chi || kacc >= a || lev == 2) break;
+            // residual R = F - U (U^H F)
+            gemm(kacc, b, a, C1(), adj(V<T>(Ub, ldu, 1)), F, C0(), V<T>(Bb, b, 1));
+            HIPCHK((geam<T, T>(st, a, b, C1(), F, C0(), V<T>(s.bR, b, 1))));
+            gemm(a, b, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(Bb, b, 1), C1(), V<T>(s.bR, b, 1));
+            HIPCHK(sumsq<T>(st, V<T>(s.bR, b, 1), a, b, s.sums));
+            double sums[2], st0[1];
+            read_doubles(s.sums, 2, sums);
+            read_doubles(s.st, 1, st0);
+            if (!(sums[0] > c.cutoff * c.cutoff * st0[0])) break;
+            R = V<T>(s.bR, b, 1);
+        }
+        if (kacc == 0) return 0;
+        gemm(kacc, b, a, C1(), adj(V<T>(Ub, ldu, 1)), F, C0(), V<T>(Bb, b, 1));
+        return kacc;
+    }
+
+    // ------------------------------------------------------------ trace vectors
+    double* Lv(int j) { return c.Lv + (size_t)j * c.chi * 2; }
+    double* Rv(int j) { return c.Rv + (size_t)j * c.chi * 2; }
+
+    void ensureL(int i) {
+        for (int j = c.lvalid; j < i; ++j)
+            HIPCHK(transfer_left<T>(st, site(j), c.dims[j], c.D2, c.dims[j + 1], Lv(j), c.ovec + 2 * j * c.D2,
+                                    Lv(j + 1)));
+        if (i > c.lvalid) c.lvalid = i;
+    }
+    void ensureR(int i) {
+        for (int j = c.rvalid - 1; j >= i; --j)
+            HIPCHK(transfer_right<T>(st, site(j), c.dims[j], c.D2, c.dims[j + 1], Rv(j + 1), c.ovec + 2 * j * c.D2,
+                                     Rv(j)));
+        if (i < c.rvalid) c.rvalid = i;
+    }
+    void site_changed(int j) {
+        c.lvalid = std::min(c.lvalid, j);
+        c.rvalid = std::max(c.rvalid, j + 1);
+    }
+
+    // ------------------------------------------------------------ canonical moves
+    void swap_site(int j, int spare_idx) { std::swap(c.site[j], c.spare[spare_idx]); }
+
+    void move_right(int j) {
+        const int cl = c.dims[j], cr = c.dims[j + 1], cr2 = c.dims[j + 2];
+        const int n = cl * c.D2;
+        CView<T> F = V<T>(site(j), cr, 1);
+        const int q = orth2(F, n, cr, s.bQ, s.bK);
+        if (q <= 0) throw Fail{MPDO_E_NUMERIC, "zero site tensor"};
+        T* nq = (T*)c.spare[0];
+        HIPCHK((geam<T, T>(st, n, q, C1(), V<T>(s.bQ, cr, 1), C0(), V<T>(nq, q, 1))));
+        T* nx = (T*)c.spare[1];
+        const int m2 = c.D2 * cr2;
+        gemm(q, m2, cr, C1(), V<T>(s.bK, cr, 1), V<T>(site(j + 1), m2, 1), C0(), V<T>(nx, m2, 1));
+        swap_site(j, 0);
+        swap_site(j + 1, 1);
+        c.dims[j + 1] = q;
+        site_changed(j);
+        site_changed(j + 1);
+        c.centre = j + 1;
+    }
+
+    void move_left(int j) {
+        const int cl = c.dims[j], cr = c.dims[j + 1], cl0 = c.dims[j - 1];
+        const int m = c.D2 * cr;
+        // site_j^H = Q K  (m x cl view of the adjoint)
+        CView<T> F = adj(V<T>(site(j), m, 1));
+        const int q = orth2(F, m, cl, s.bQ, s.bK);
+        if (q <= 0) throw Fail{MPDO_E_NUMERIC, "zero site tensor"};
+        T* nq = (T*)c.spare[0];
+        HIPCHK((geam<T, T>(st, q, m, C1(), adj(V<T>(s.bQ, cl, 1)), C0(), V<T>(nq, m, 1))));
+        T* nx = (T*)c.spare[1];
+        const int n0 = cl0 * c.D2;
+        gemm(n0, q, cl, C1(), V<T>(site(j - 1), cl, 1), adj(V<T>(s.bK, cl, 1)), C0(), V<T>(nx, q, 1));
+        swap_site(j, 0);
+        swap_site(j - 1, 1);
+        c.dims[j] = q;
+        site_changed(j);
+        site_changed(j - 1);
+        c.centre = j - 1;
+    }
+
+    // ------------------------------------------------------------ the two-site update
+    void update(int i, const GateFactor* gf, int chi, mpdo_trunc_info* info) {
+        eig_calls = 0;
+        const int D2 = c.D2;
+        if (c.centre < i) c.dir = 1;
+        else if (c.centre > i + 1) c.dir = -1;
+        while (c.centre < i) move_right(c.centre);
+        while (c.centre > i + 1) move_left(c.centre);
+        const int dir = c.dir;
+        const int cl = c.dims[i], cm = c.dims[i + 1], cr = c.dims[i + 2];
+        const int nL = cl * D2, nR = D2 * cr;
+        ensureL(i);
+        ensureR(i + 2);
+        // trace vectors over the two sides: lvec = L_i (x) vec(I), rvec = vec(I) (x) R_{i+2}
+        // (the atoms' queued maps were folded into the gate, so their trace vector is vec(I))
+        HIPCHK(kron_vec(st, Lv(i), cl, c.ovec + 2 * (size_t)c.N * D2, D2, s.lvec));
+        HIPCHK(kron_vec(st, c.ovec + 2 * (size_t)c.N * D2, D2, Rv(i + 2), cr, s.rvec));
+
+        const int na = dir > 0 ? nL : nR;
+        const int nb = dir > 0 ? nR : nL;
+        const int r = gf ? gf->r : 0;
+        const bool factored = gf && r <= MAX_FACTOR_RANK && (long)r * cm < (long)na;
+        T* Ut = s.bU;        // a-side isometry before placement (ld = chi cap)
+        const long ldu = c.chi;
+        int kept = 0;
+        double tr_re = 0.0, tr_im = 0.0, n2 = 0.0;
+        T* Left = nullptr;   // new site i  (nL x kept), unscaled
+        T* Right = nullptr;  // new site i+1 (kept x nR), unscaled
+        T* outL = (T*)c.spare[0];
+        T* outR = (T*)c.spare[1];
+        if (factored) {
+            const int k = r * cm;
+            // M_L (nL x k) in bA, M_R (k x nR) in bB
+            HIPCHK(phys_left<T>(st, site(i), cl, D2, cm, gf->X, r, s.bA));
+            HIPCHK(phys_right<T>(st, site(i + 1), cm, D2, cr, gf->Y, r, s.bB));
+            CView<T> ML = V<T>(s.bA, k, 1), MR = V<T>(s.bB, nR, 1);
+            // tr rho = (lvec^T M_L)(M_R rvec)
+            HIPCHK(gemv_left<T>(st, ML, nL, k, s.lvec, s.vtmp));
+            HIPCHK(gemv_left<T>(st, trans(MR), nR, k, s.rvec, s.vtmp2));
+            HIPCHK(dot(st, s.vtmp, s.vtmp2, k, s.sc));
+            CView<T> Fa = dir > 0 ? ML : adj(MR);
+            CView<T> Fb = dir > 0 ? MR : adj(ML);
+            const int q = orth2(Fa, na, k, s.bQ, s.bK);
+            if (q <= 0) throw Fail{MPDO_E_NUMERIC, "merged tensor vanished"};
+            // core C = K Fb (q x nb)
+            gemm(q, nb, k, C1(), V<T>(s.bK, k, 1), Fb, C0(), V<T>(s.bC, nb, 1));
+            HIPCHK(sumsq<T>(st, V<T>(s.bC, nb, 1), q, nb, s.sums));
+            double sums[2];
+            read_doubles(s.sums, 2, sums);
+            if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
+            n2 = sums[0];
+            kept = split_left(V<T>(s.bC, nb, 1), q, nb, chi, Ut, ldu, s.bB2);
+            if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
+            if (dir > 0) {
+                gemm(nL, kept, q, C1(), V<T>(s.bQ, k, 1), V<T>(Ut, ldu, 1), C0(), V<T>(outL, kept, 1));
+                HIPCHK((geam<T, T>(st, kept, nR, C1(), V<T>(s.bB2, nR, 1), C0(), V<T>(outR, nR, 1))));
+            } else {
+                // new site i+1 = U^H = Uc^H Q^H ; new site i = B^H
+                gemm(kept, nR, q, C1(), adj(V<T>(Ut, ldu, 1)), adj(V<T>(s.bQ, k, 1)), C0(), V<T>(outR, nR, 1));
+                HIPCHK((geam<T, T>(st, nL, kept, C1(), adj(V<T>(s.bB2, nL, 1)), C0(), V<T>(outL, kept, 1))));
+            }
+        } else {
+            // explicit theta: merge then gate
+            const int m2 = D2 * D2;
+            gemm(nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(), V<T>(s.bT1, nR, 1));
+            HIPCHK(cgemm<T>(st, m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(),
+                            V<T>(s.bA, cr, 1), cl, 0, (long)m2 * cr, (long)m2 * cr));
+            CView<T> Th = V<T>(s.bA, nR, 1);
+            HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
+            HIPCHK(dot(st, s.lvec, s.vtmp, nL, s.sc));
+            HIPCHK(sumsq<T>(st, Th, nL, nR, s.sums));
+            double sums[2];
+            read_doubles(s.sums, 2, sums);
+            if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
+            n2 = sums[0];
+            CView<T> Fa = dir > 0 ? Th : adj(Th);
+            kept = split_left(Fa, na, nb, chi, Ut, ldu, s.bB2);
+            if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
+            if (dir > 0) {
+                HIPCHK((geam<T, T>(st, nL, kept, C1(), V<T>(Ut, ldu, 1), C0(), V<T>(outL, kept, 1))));
+                HIPCHK((geam<T, T>(st, kept, nR, C1(), V<T>(s.bB2, nR, 1), C0(), V<T>(outR, nR, 1))));
+            } else {
+                HIPCHK((geam<T, T>(st, kept, nR, C1(), adj(V<T>(Ut, ldu, 1)), C0(), V<T>(outR, nR, 1))));
+                HIPCHK((geam<T, T>(st, nL, kept, C1(), adj(V<T>(s.bB2, nL, 1)), C0(), V<T>(outL, kept, 1))));
+            }
+        }
+        Left = outL;
+        Right = outR;
+        // trace factors of the kept Schmidt pairs and PPT
+        HIPCHK(gemv_left<T>(st, V<T>(Left, kept, 1), nL, kept, s.lvec, s.tl));
+        HIPCHK(gemv_left<T>(st, trans(V<T>(Right, nR, 1)), nR, kept, s.rvec, s.tr));
+        // sc[0..1] holds tr(rho) from the dot; sc[2] = ||theta||^2
+        {
+            double h[2];
+            read_doubles(s.sc, 2, h);
+            tr_re = h[0];
+            tr_im = h[1];
+            double scv[4] = {tr_re, tr_im, n2, 0.0};
+            memcpy(c.hbuf, scv, sizeof(scv));
+            HIPCHK(hipMemcpyAsync(s.sc, c.hbuf, sizeof(scv), hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(ppt(st, s.sig, s.tl, s.tr, s.sc, kept, c.cfg.ppt, c.cfg.renorm_trace, s.fac, s.pout));
+        if (dir > 0)
+            HIPCHK(scale_rows<T>(st, Right, kept, nR, nR, s.fac));
+        else
+            HIPCHK(scale_cols<T>(st, V<T>(Left, kept, 1), nL, kept, s.fac));
+        swap_site(i, 0);
+        swap_site(i + 1, 1);
+        c.dims[i + 1] = kept;
+        site_changed(i);
+        site_changed(i + 1);
+        c.centre = dir > 0 ? i + 1 : i;
+        if (info) {
+            double po[16], sg[2];
+            read_doubles(s.pout, 13, po);
+            read_doubles(s.sig, 1, sg);
+            double smin = 0.0;
+            read_doubles(s.sig + (kept - 1), 1, &smin);
+            info->bond = i;
+            info->chi_l = cl;
+            info->chi_mid = cm;
+            info->chi_r = cr;
+            info->kept = kept;
+            info->path = factored ? 1 : 0;
+            info->eig_calls = eig_calls;
+            info->ppt_feasible = (int)po[3];
+            info->trace_before = po[0];
+            info->trace_after = po[10];
+            info->xi_before = po[1];
+            info->xi_after = po[11];
+            info->ppt_theta = po[2];
+            info->discarded_weight = n2 > 0.0 ? std::max(0.0, 1.0 - po[7] / n2) : 0.0;
+            info->max_abs_imag_t = po[0] != 0.0 ? po[6] / fabs(po[0]) : po[6];
+            info->sigma_max = sg[0];
+            info->sigma_min_kept = smin;
+        }
+    }
+};
+
+// ====================================================================== host math
+std::vector<zc> superop_from_kraus_2(const double* kraus, int nk, int d) {
+    const int D2 = d * d, m = D2 * D2;
+    std::vector<zc> S((size_t)m * m, zc(0, 0));
+    for (int q = 0; q < nk; ++q) {
+        const zc* K = (const zc*)(kraus + (size_t)q * 2 * D2 * D2);   // (d^2 x d^2) on (a,b),(s,t)
+        for (int a = 0; a < d; ++a)
+            for (int ap = 0; ap < d; ++ap)
+                for (int b = 0; b < d; ++b)
+                    for (int bp = 0; bp < d; ++bp) {
+                        const int row = (a * d + ap) * D2 + (b * d + bp);
+                        for (int s_ = 0; s_ < d; ++s_)
+                            for (int sp = 0; sp < d; ++sp)
+                                for (int t = 0; t < d; ++t)
+                                    for (int tp = 0; tp < d; ++tp) {
+                                        const int col = (s_ * d + sp) * D2 + (t * d + tp);
+                                        const zc k1 = K[(a * d + b) * D2 + (s_ * d + t)];
+                                        const zc k2 = K[(ap * d + bp) * D2 + (sp * d + tp)];
+                                        S[(size_t)row * m + col] += k1 * std::conj(k2);
+                                    }
+                    }
+    }
+    return S;
+}
+
+std::vector<zc> superop_from_kraus_1(const double* kraus, int nk, int d) {
+    const int D2 = d * d;
+    std::vector<zc> S((size_t)D2 * D2, zc(0, 0));
+    for (int q = 0; q < nk; ++q) {
+        const zc* K = (const zc*)(kraus + (size_t)q * 2 * d * d);
+        for (int a = 0; a < d; ++a)
+            for (int ap = 0; ap < d; ++ap)
+                for (int s_ = 0; s_ < d; ++s_)
+                    for (int sp = 0; sp < d; ++sp)
+                        S[(size_t)(a * d + ap) * D2 + (s_ * d + sp)] += K[a * d + s_] * std::conj(K[ap * d + sp]);
+    }
+    return S;
+}
+
+double cptp_defect(const double* kraus, int nk, int dim) {
+    std::vector<zc> acc((size_t)dim * dim, zc(0, 0));
+    for (int q = 0; q < nk; ++q) {
+        const zc* K = (const zc*)(kraus + (size_t)q * 2 * dim * dim);
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) {
+                zc sacc(0, 0);
+                for (int k = 0; k < dim; ++k) sacc += std::conj(K[k * dim + a]) * K[k * dim + b];
+                acc[(size_t)a * dim + b] += sacc;
+            }
+    }
+    double dmax = 0.0;
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) dmax = std::max(dmax, std::abs(acc[(size_t)a * dim + b] - zc(a == b ? 1 : 0, 0)));
+    return dmax;
+}
+
+bool all_finite(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// ====================================================================== context plumbing
+size_t workspace_for(const mpdo_config& cfg) {
+    const int D2 = cfg.d * cfg.d;
+    const int nmax = cfg.chi_max * D2;
+    const bool f32 = cfg.precision == MPDO_FP32;
+    const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+    size_t b = 0;
+    const size_t site = (size_t)cfg.chi_max * D2 * cfg.chi_max * 2 * tsz + 256;
+    b += (size_t)(cfg.n_sites + 2) * site;
+    b += (size_t)(cfg.n_sites + 1) * D2 * 2 * sizeof(double) + 256;          // ovec (+ vec(I))
+    b += 2 * ((size_t)(cfg.n_sites + 1) * cfg.chi_max * 2 * sizeof(double) + 256);  // Lv, Rv
+    b += (size_t)D2 * D2 * D2 * D2 * 2 * (sizeof(double) + tsz) + 512;       // superoperator
+    b += Scratch<double>::bytes(f32 ? 64 : nmax);
+    if (f32) b += Scratch<float>::bytes(nmax);
+    b += Scratch<double>::bytes(D2 * D2);
+    b += (size_t)128 * (MAX_FACTOR_RANK * D2 * D2 * 2 * sizeof(double) + 256);   // gate factor slots
+    b += (size_t)cfg.n_sites * D2 * 2 * sizeof(double) + 256;                       // expectation operators
+    return b + (1 << 20);
+}
+
+void set_err(mpdo_ctx ctx, const Fail& f) {
+    ctx->err = f.msg;
+    if (f.st == MPDO_E_DEVICE || f.st == MPDO_E_NUMERIC) ctx->poisoned = true;
+}
+
+void alloc_state(mpdo_ctx c) {
+    const size_t need = workspace_for(c->cfg);
+    if (!c->ws) {
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) throw Fail{MPDO_E_NOMEM, "hipMalloc of the workspace failed"};
+        c->ws = (char*)p;
+        c->ws_bytes = need;
+        c->own_ws = true;
+    }
+    c->arena.base = c->ws;
+    c->arena.cap = c->ws_bytes;
+    c->arena.used = 0;
+    const size_t tsz = c->tsize();
+    const size_t scap = c->site_cap();
+    c->site.resize(c->N);
+    for (int j = 0; j < c->N; ++j) c->site[j] = c->arena.take<char>(scap * tsz);
+    c->spare.resize(2);
+    for (int j = 0; j < 2; ++j) c->spare[j] = c->arena.take<char>(scap * tsz);
+    c->ovec = c->arena.take<double>((size_t)(c->N + 1) * c->D2 * 2);
+    c->Lv = c->arena.take<double>((size_t)(c->N + 1) * c->chi * 2);
+    c->Rv = c->arena.take<double>((size_t)(c->N + 1) * c->chi * 2);
+    const int m2 = c->D2 * c->D2;
+    c->Sdev = c->arena.take<double>((size_t)m2 * m2 * 2);
+    c->SdevT = c->fp32 ? (void*)c->arena.take<float>((size_t)m2 * m2 * 2) : (void*)c->Sdev;
+    const int nmax = c->chi * c->D2;
+    c->sd.carve(c->arena, c->fp32 ? 64 : nmax);
+    if (c->fp32) c->sf.carve(c->arena, nmax);
+    c->sg.carve(c->arena, m2);
+    c->gslots.clear();
+    c->gcache.clear();
+    c->gorder.clear();
+    for (int q = 0; q < 128; ++q) c->gslots.push_back(c->arena.take<double>((size_t)MAX_FACTOR_RANK * m2 * 2));
+    c->obuf = c->arena.take<double>((size_t)c->N * c->D2 * 2);
+    if (!c->hbuf) {
+        if (hipHostMalloc((void**)&c->hbuf, 1 << 16) != hipSuccess) throw Fail{MPDO_E_NOMEM, "pinned buffer"};
+        if (hipHostMalloc((void**)&c->hint, 256) != hipSuccess) throw Fail{MPDO_E_NOMEM, "pinned buffer"};
+    }
+    c->ready = true;
+}
+
+void upload(mpdo_ctx c, void* dst, const void* src, size_t bytes) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+}
+
+void set_ovec(mpdo_ctx c, int j) {
+    // trace vector of atom j: o = P_j^T vec(I)
+    const int D2 = c->D2, d = c->d;
+    std::vector<zc> o(D2, zc(0, 0));
+    for (int eta = 0; eta < D2; ++eta) {
+        zc acc(0, 0);
+        for (int a = 0; a < d; ++a) {
+            const int r = a * d + a;
+            acc += c->pend_id[j] ? zc(r == eta ? 1 : 0, 0) : c->pending[j][(size_t)r * D2 + eta];
+        }
+        o[eta] = acc;
+    }
+    upload(c, c->ovec + 2 * (size_t)j * D2, o.data(), D2 * sizeof(zc));
+}
+
+// operator-Schmidt factors of the (D2^2 x D2^2) superoperator S: S = sum_k X_k (x) Y_k
+GateFactor factorize(mpdo_ctx c, const std::vector<zc>& S) {
+    const int D2 = c->D2, m2 = D2 * D2;
+    const uint64_t h = fnv1a(S.data(), S.size() * sizeof(zc));
+    auto it = c->gcache.find(h);
+    if (it != c->gcache.end()) return it->second;
+    // reshuffle R[(a,c),(b,e)] = S[(a,b),(c,e)]
+    std::vector<zc> R((size_t)m2 * m2);
+    for (int a = 0; a < D2; ++a)
+        for (int b = 0; b < D2; ++b)
+            for (int cc = 0; cc < D2; ++cc)
+                for (int e = 0; e < D2; ++e)
+                    R[(size_t)(a * D2 + cc) * m2 + (b * D2 + e)] = S[(size_t)(a * D2 + b) * m2 + (cc * D2 + e)];
+    Scratch<double>& g = c->sg;
+    upload(c, g.bA, R.data(), R.size() * sizeof(zc));
+    Engine<double> E(*c, g);
+    const int r = E.orth2(V<double>(g.bA, m2, 1), m2, m2, g.bQ, g.bK);
+    GateFactor gf;
+    gf.r = r;
+    if (r > MAX_FACTOR_RANK || r <= 0) {
+        gf.X = gf.Y = nullptr;
+    } else {
+        // free the oldest cached factors until a slot pair is available
+        while (c->gslots.size() < 2 && !c->gorder.empty()) {
+            const uint64_t old = c->gorder.front();
+            c->gorder.erase(c->gorder.begin());
+            GateFactor o = c->gcache[old];
+            c->gcache.erase(old);
+            if (o.X) {
+                c->gslots.push_back(o.X);
+                c->gslots.push_back(o.Y);
+            }
+        }
+        if (c->gslots.size() < 2) throw Fail{MPDO_E_NOMEM, "no slot for gate factors"};
+        gf.X = c->gslots.back();
+        c->gslots.pop_back();
+        gf.Y = c->gslots.back();
+        c->gslots.pop_back();
+        // X[k][(a,c)] = Q[(a,c), k]   (Q: m2 x r, ld m2);  Y[k][(b,e)] = K[k][(b,e)]
+        HIPCHK((geam<double, double>(c->st, r, m2, C1(), trans(V<double>(g.bQ, m2, 1)), C0(),
+                                     V<double>(gf.X, m2, 1))));
+        HIPCHK((geam<double, double>(c->st, r, m2, C1(), V<double>(g.bK, m2, 1), C0(), V<double>(gf.Y, m2, 1))));
+    }
+    c->gcache[h] = gf;
+    c->gorder.push_back(h);
+    return gf;
+}
+
+template <typename T>
+void do_update(mpdo_ctx c, int i, const std::vector<zc>& S_in, int chi, mpdo_trunc_info* info) {
+    const int D2 = c->D2, m2 = D2 * D2;
+    // fold queued single-atom maps: S' = S (P_i (x) P_{i+1})
+    std::vector<zc> S = S_in;
+    if (!c->pend_id[i] || !c->pend_id[i + 1]) {
+        std::vector<zc> P((size_t)m2 * m2, zc(0, 0));
+        for (int a = 0; a < D2; ++a)
+            for (int b = 0; b < D2; ++b)
+                for (int cc = 0; cc < D2; ++cc)
+                    for (int e = 0; e < D2; ++e) {
+                        const zc pa = c->pend_id[i] ? zc(a == cc ? 1 : 0, 0) : c->pending[i][(size_t)a * D2 + cc];
+                        const zc pb =
+                            c->pend_id[i + 1] ? zc(b == e ? 1 : 0, 0) : c->pending[i + 1][(size_t)b * D2 + e];
+                        P[(size_t)(a * D2 + b) * m2 + (cc * D2 + e)] = pa * pb;
+                    }
+        std::vector<zc> out((size_t)m2 * m2, zc(0, 0));
+        for (int r = 0; r < m2; ++r)
+            for (int k = 0; k < m2; ++k) {
+                const zc sv = S[(size_t)r * m2 + k];
+                if (sv == zc(0, 0)) continue;
+                for (int col = 0; col < m2; ++col) out[(size_t)r * m2 + col] += sv * P[(size_t)k * m2 + col];
+            }
+        S.swap(out);
+        c->pend_id[i] = c->pend_id[i + 1] = 1;
+        set_ovec(c, i);
+        set_ovec(c, i + 1);
+        c->lvalid = std::min(c->lvalid, i);
+        c->rvalid = std::max(c->rvalid, i + 2);
+    }
+    GateFactor gf = factorize(c, S);
+    upload(c, c->Sdev, S.data(), S.size() * sizeof(zc));
+    if (c->fp32)
+        HIPCHK((geam<double, float>(c->st, m2, m2, C1(), V<double>(c->Sdev, m2, 1), C0(),
+                                    V<float>((float*)c->SdevT, m2, 1))));
+    if (c->fp32) {
+        Engine<float> E(*c, c->sf);
+        E.update(i, gf.X ? &gf : nullptr, chi, info);
+    } else {
+        Engine<double> E(*c, c->sd);
+        E.update(i, gf.X ? &gf : nullptr, chi, info);
+    }
+}
+
+mpdo_status guard(mpdo_ctx c) {
+    if (!c) return MPDO_E_ARG;
+    if (c->poisoned) {
+        c->err = "context poisoned by an earlier device or numeric failure";
+        return MPDO_E_STATE;
+    }
+    return MPDO_OK;
+}
+
+}  // namespace
+
+template <typename T>
+static Scratch<T>& scratch_of(mpdo_ctx c);
+template <>
+Scratch<double>& scratch_of<double>(mpdo_ctx c) {
+    return c->sd;
+}
+template <>
+Scratch<float>& scratch_of<float>(mpdo_ctx c) {
+    return c->sf;
+}
+
+template <typename T>
+static void expect_impl(mpdo_ctx c, int n_terms, const int* first, const int* len, const double* ops, int normalize,
+                        double* out) {
+    Scratch<T>& s = scratch_of<T>(c);
+    Engine<T> E(*c, s);
+    const int D2 = c->D2, d = c->d;
+    E.ensureL(c->N);
+    size_t opos = 0;
+    double* res = s.pout;   // 2 doubles per term, staged in chunks
+    std::vector<double> all((size_t)n_terms * 2);
+    int t0 = 0;
+    const int chunk = 16;
+    while (t0 < n_terms) {
+        const int t1 = std::min(n_terms, t0 + chunk);
+        for (int t = t0; t < t1; ++t) {
+            const int f = first[t], m = len[t];
+            // operator vectors o = P^T vec(O^T)
+            std::vector<zc> o((size_t)m * D2);
+            for (int u = 0; u < m; ++u) {
+                const zc* O = (const zc*)(ops + (opos + (size_t)u * d * d) * 2);
+                const int j = f + u;
+                for (int eta = 0; eta < D2; ++eta) {
+                    zc acc(0, 0);
+                    for (int a = 0; a < d; ++a)
+                        for (int b = 0; b < d; ++b) {
+                            const zc v = O[b * d + a];   // vec(O^T)[a d + b] = O[b][a]
+                            if (v == zc(0, 0)) continue;
+                            const int r = a * d + b;
+                            acc += (c->pend_id[j] ? zc(r == eta ? 1 : 0, 0) : c->pending[j][(size_t)r * D2 + eta]) * v;
+                        }
+                    o[(size_t)u * D2 + eta] = acc;
+                }
+            }
+            opos += (size_t)m * d * d;
+            HIPCHK(hipMemcpyAsync(c->obuf, o.data(), o.size() * sizeof(zc), hipMemcpyHostToDevice, c->st));
+            E.ensureR(f + m);
+            HIPCHK((geam<double, double>(c->st, 1, c->dims[f], C1(), V<double>(E.Lv(f), 0, 1), C0(),
+                                         V<double>(s.vtmp, 0, 1))));
+            double* x = s.vtmp;
+            double* y = s.vtmp2;
+            for (int u = 0; u < m; ++u) {
+                const int j = f + u;
+                HIPCHK(transfer_left<T>(c->st, E.site(j), c->dims[j], D2, c->dims[j + 1], x, c->obuf + 2 * (size_t)u * D2,
+                                        y));
+                std::swap(x, y);
+            }
+            HIPCHK(dot(c->st, x, E.Rv(f + m), c->dims[f + m], res + 2 * (t - t0)));
+            HIPCHK(hipStreamSynchronize(c->st));   // obuf is reused by the next term
+        }
+        E.read_doubles(res, 2 * (t1 - t0), all.data() + 2 * t0);
+        t0 = t1;
+    }
+    double trv[2] = {1.0, 0.0};
+    if (normalize) E.read_doubles(E.Lv(c->N), 2, trv);
+    for (int t = 0; t < n_terms; ++t) {
+        zc v(all[2 * t], all[2 * t + 1]);
+        if (normalize) v /= zc(trv[0], trv[1]);
+        out[2 * t] = v.real();
+        out[2 * t + 1] = v.imag();
+    }
+}
+
+// ====================================================================== C ABI
+extern "C" {
+
+mpdo_status mpdo_create(const mpdo_config* cfg, mpdo_ctx* out) {
+    if (!cfg || !out) {
+        g_create_err = "null argument";
+        return MPDO_E_ARG;
+    }
+    *out = nullptr;
+    if (cfg->n_sites < 2 || cfg->d < 2 || cfg->d > 4 || cfg->chi_max < 1 || cfg->chi_max > 1024 ||
+        (cfg->precision != MPDO_FP64 && cfg->precision != MPDO_FP32) || cfg->cutoff_rel < 0.0 ||
+        !(cfg->cutoff_rel < 1.0)) {
+        g_create_err = "config out of range";
+        return MPDO_E_ARG;
+    }
+    mpdo_ctx c = new mpdo_ctx_s();
+    c->cfg = *cfg;
+    c->N = cfg->n_sites;
+    c->d = cfg->d;
+    c->D2 = cfg->d * cfg->d;
+    c->chi = cfg->chi_max;
+    c->fp32 = cfg->precision == MPDO_FP32;
+    // default relative cutoff: the rounding floor of the working precision's products
+    c->cutoff = cfg->cutoff_rel > 0.0 ? cfg->cutoff_rel : (c->fp32 ? 1e-6 : 1e-14);
+    c->st = (hipStream_t)cfg->hip_stream;
+    c->dims.assign(c->N + 1, 1);
+    c->pending.assign(c->N, std::vector<zc>());
+    c->pend_id.assign(c->N, 1);
+    *out = c;
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_destroy(mpdo_ctx c) {
+    if (!c) return MPDO_E_ARG;
+    if (c->st || c->ready) (void)hipStreamSynchronize(c->st);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->hbuf) (void)hipHostFree(c->hbuf);
+    if (c->hint) (void)hipHostFree(c->hint);
+    delete c;
+    return MPDO_OK;
+}
+
+size_t mpdo_workspace_bytes(const mpdo_config* cfg) {
+    if (!cfg || cfg->d < 2 || cfg->d > 4 || cfg->chi_max < 1 || cfg->n_sites < 2) return 0;
+    return workspace_for(*cfg);
+}
+
+mpdo_status mpdo_bind_workspace(mpdo_ctx c, void* dev, size_t bytes) {
+    if (!c || !dev) return MPDO_E_ARG;
+    if (c->ws) {
+        c->err = "device memory already in use";
+        return MPDO_E_STATE;
+    }
+    if (bytes < workspace_for(c->cfg)) {
+        c->err = "workspace smaller than mpdo_workspace_bytes";
+        return MPDO_E_NOMEM;
+    }
+    c->ws = (char*)dev;
+    c->ws_bytes = bytes;
+    c->own_ws = false;
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_init_product_state(mpdo_ctx c, const double* rho_sites) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!rho_sites) {
+        c->err = "null rho_sites";
+        return MPDO_E_ARG;
+    }
+    const int d = c->d, D2 = c->D2;
+    if (!all_finite(rho_sites, (size_t)c->N * D2 * 2)) {
+        c->err = "non-finite rho entry";
+        return MPDO_E_ARG;
+    }
+    try {
+        if (!c->ready) alloc_state(c);
+        std::vector<double> norms(c->N);
+        double prod = 1.0;
+        for (int j = 0; j < c->N; ++j) {
+            double s2 = 0.0;
+            for (int e = 0; e < D2 * 2; ++e) s2 += rho_sites[(size_t)j * D2 * 2 + e] * rho_sites[(size_t)j * D2 * 2 + e];
+            norms[j] = sqrt(s2);
+            if (!(norms[j] > 0.0)) {
+                c->err = "zero site density matrix";
+                return MPDO_E_ARG;
+            }
+            if (j > 0) prod *= norms[j];
+        }
+        // sites j >= 1 normalised (right isometries); site 0 carries the norm (centre)
+        for (int j = 0; j < c->N; ++j) {
+            const double f = (j == 0) ? prod : 1.0 / norms[j];
+            std::vector<double> hostv(D2 * 2);
+            for (int e = 0; e < D2 * 2; ++e) hostv[e] = rho_sites[(size_t)j * D2 * 2 + e] * f;
+            if (c->fp32) {
+                std::vector<float> hf(D2 * 2);
+                for (int e = 0; e < D2 * 2; ++e) hf[e] = (float)hostv[e];
+                upload(c, c->site[j], hf.data(), hf.size() * sizeof(float));
+            } else {
+                upload(c, c->site[j], hostv.data(), hostv.size() * sizeof(double));
+            }
+        }
+        c->dims.assign(c->N + 1, 1);
+        c->centre = 0;
+        c->dir = 1;
+        c->pend_id.assign(c->N, 1);
+        c->pending.assign(c->N, std::vector<zc>());
+        // vec(I) per atom, plus one spare slot N holding vec(I)
+        std::vector<zc> o((size_t)(c->N + 1) * D2, zc(0, 0));
+        for (int j = 0; j <= c->N; ++j)
+            for (int a = 0; a < d; ++a) o[(size_t)j * D2 + a * d + a] = zc(1, 0);
+        upload(c, c->ovec, o.data(), o.size() * sizeof(zc));
+        std::vector<zc> one(1, zc(1, 0));
+        upload(c, c->Lv, one.data(), sizeof(zc));
+        upload(c, c->Rv + (size_t)c->N * c->chi * 2, one.data(), sizeof(zc));
+        c->lvalid = 0;
+        c->rvalid = c->N;
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+static mpdo_status gate_common(mpdo_ctx c, int site, const std::vector<zc>& S, int chi, mpdo_trunc_info* info) {
+    try {
+        if (c->fp32)
+            do_update<float>(c, site, S, chi, info);
+        else
+            do_update<double>(c, site, S, chi, info);
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_apply_gate(mpdo_ctx c, int site, const double* superop, mpdo_trunc_info* info) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready) {
+        c->err = "state not initialised";
+        return MPDO_E_STATE;
+    }
+    if (site < 0 || site > c->N - 2 || !superop) {
+        c->err = "site out of range or null superoperator";
+        return MPDO_E_ARG;
+    }
+    const int m2 = c->D2 * c->D2;
+    if (!all_finite(superop, (size_t)m2 * m2 * 2)) {
+        c->err = "non-finite superoperator entry";
+        return MPDO_E_ARG;
+    }
+    std::vector<zc> S((size_t)m2 * m2);
+    memcpy(S.data(), superop, S.size() * sizeof(zc));
+    return gate_common(c, site, S, c->chi, info);
+}
+
+mpdo_status mpdo_apply_gate_kraus(mpdo_ctx c, int site, int n_kraus, const double* kraus, mpdo_trunc_info* info) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready) {
+        c->err = "state not initialised";
+        return MPDO_E_STATE;
+    }
+    const int dim = c->d * c->d;
+    if (site < 0 || site > c->N - 2 || n_kraus < 1 || !kraus) {
+        c->err = "bad site or Kraus set";
+        return MPDO_E_ARG;
+    }
+    if (!all_finite(kraus, (size_t)n_kraus * dim * dim * 2)) {
+        c->err = "non-finite Kraus entry";
+        return MPDO_E_ARG;
+    }
+    if (cptp_defect(kraus, n_kraus, dim) > 1e-10) {
+        c->err = "Kraus set is not trace preserving";
+        return MPDO_E_ARG;
+    }
+    return gate_common(c, site, superop_from_kraus_2(kraus, n_kraus, c->d), c->chi, info);
+}
+
+mpdo_status mpdo_apply_channel(mpdo_ctx c, int site, int n_kraus, const double* kraus) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready) {
+        c->err = "state not initialised";
+        return MPDO_E_STATE;
+    }
+    if (site < 0 || site >= c->N || n_kraus < 1 || !kraus) {
+        c->err = "bad site or Kraus set";
+        return MPDO_E_ARG;
+    }
+    if (!all_finite(kraus, (size_t)n_kraus * c->d * c->d * 2)) {
+        c->err = "non-finite Kraus entry";
+        return MPDO_E_ARG;
+    }
+    if (cptp_defect(kraus, n_kraus, c->d) > 1e-10) {
+        c->err = "Kraus set is not trace preserving";
+        return MPDO_E_ARG;
+    }
+    const int D2 = c->D2;
+    std::vector<zc> S1 = superop_from_kraus_1(kraus, n_kraus, c->d);
+    if (c->pend_id[site]) {
+        c->pending[site] = S1;
+    } else {
+        std::vector<zc> out((size_t)D2 * D2, zc(0, 0));
+        for (int a = 0; a < D2; ++a)
+            for (int k = 0; k < D2; ++k)
+                for (int b = 0; b < D2; ++b)
+                    out[(size_t)a * D2 + b] += S1[(size_t)a * D2 + k] * c->pending[site][(size_t)k * D2 + b];
+        c->pending[site].swap(out);
+    }
+    c->pend_id[site] = 0;
+    try {
+        set_ovec(c, site);
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    c->lvalid = std::min(c->lvalid, site);
+    c->rvalid = std::max(c->rvalid, site + 1);
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_truncate(mpdo_ctx c, int bond, int chi, mpdo_trunc_info* info) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready) {
+        c->err = "state not initialised";
+        return MPDO_E_STATE;
+    }
+    if (bond < 0 || bond > c->N - 2 || chi < 1 || chi > c->chi) {
+        c->err = "bad bond or chi";
+        return MPDO_E_ARG;
+    }
+    const int m2 = c->D2 * c->D2;
+    std::vector<zc> S((size_t)m2 * m2, zc(0, 0));
+    for (int a = 0; a < m2; ++a) S[(size_t)a * m2 + a] = zc(1, 0);
+    return gate_common(c, bond, S, chi, info);
+}
+
+mpdo_status mpdo_expect(mpdo_ctx c, int n_terms, const int* first_site, const int* n_sites_in_term, const double* ops,
+                        int normalize, double* out) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready) {
+        c->err = "state not initialised";
+        return MPDO_E_STATE;
+    }
+    if (n_terms < 0 || (n_terms > 0 && (!first_site || !n_sites_in_term || !ops || !out))) {
+        c->err = "null argument";
+        return MPDO_E_ARG;
+    }
+    size_t nops = 0;
+    for (int t = 0; t < n_terms; ++t) {
+        if (n_sites_in_term[t] < 1 || first_site[t] < 0 || first_site[t] + n_sites_in_term[t] > c->N) {
+            c->err = "term out of range";
+            return MPDO_E_ARG;
+        }
+        nops += n_sites_in_term[t];
+    }
+    if (!all_finite(ops, nops * c->d * c->d * 2)) {
+        c->err = "non-finite operator entry";
+        return MPDO_E_ARG;
+    }
+    try {
+        if (c->fp32)
+            expect_impl<float>(c, n_terms, first_site, n_sites_in_term, ops, normalize, out);
+        else
+            expect_impl<double>(c, n_terms, first_site, n_sites_in_term, ops, normalize, out);
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_trace(mpdo_ctx c, double* out) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready || !out) {
+        c->err = "state not initialised or null output";
+        return c->ready ? MPDO_E_ARG : MPDO_E_STATE;
+    }
+    try {
+        if (c->fp32) {
+            Engine<float> E(*c, c->sf);
+            E.ensureL(c->N);
+            E.read_doubles(E.Lv(c->N), 2, out);
+        } else {
+            Engine<double> E(*c, c->sd);
+            E.ensureL(c->N);
+            E.read_doubles(E.Lv(c->N), 2, out);
+        }
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_bond_dims(mpdo_ctx c, int* out) {
+    if (!c || !out) return MPDO_E_ARG;
+    for (int j = 0; j < c->N - 1; ++j) out[j] = c->dims[j + 1];
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_get_site(mpdo_ctx c, int site, double* out, int* shape) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready || site < 0 || site >= c->N || !shape) {
+        c->err = "bad site";
+        return MPDO_E_ARG;
+    }
+    shape[0] = c->dims[site];
+    shape[1] = c->D2;
+    shape[2] = c->dims[site + 1];
+    if (!out) return MPDO_OK;
+    const size_t n = (size_t)shape[0] * shape[1] * shape[2] * 2;
+    try {
+        if (c->fp32) {
+            std::vector<float> tmp(n);
+            HIPCHK(hipMemcpyAsync(tmp.data(), c->site[site], n * sizeof(float), hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            for (size_t e = 0; e < n; ++e) out[e] = tmp[e];
+        } else {
+            HIPCHK(hipMemcpyAsync(out, c->site[site], n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+        }
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_synchronize(mpdo_ctx c) {
+    if (!c) return MPDO_E_ARG;
+    if (hipStreamSynchronize(c->st) != hipSuccess) {
+        c->err = "stream synchronisation failed";
+        c->poisoned = true;
+        return MPDO_E_DEVICE;
+    }
+    return MPDO_OK;
+}
+
+const char* mpdo_last_error(mpdo_ctx c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+const char* mpdo_version(void) { return "libmpdo 0.1 (HIP, gfx950)"; }
+
+}  // extern "C"

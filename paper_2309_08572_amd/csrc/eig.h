@@ -1,0 +1,18 @@
+// Host entry of the FP64 Hermitian block-Jacobi eigensolver (eig.hip).
+#pragma once
+
+#include "common.h"
+
+namespace mpdo {
+
+// Device scratch bytes eigh() needs for order n.
+size_t eigh_work_bytes(int n);
+
+// Eigen-decomposition of the Hermitian n x n complex matrix H (row-major, leading
+// dimension ldh, overwritten).  evals[0..n) receives the eigenvalues in descending order,
+// V (row-major, leading dimension ldv) the matching unit eigenvectors as columns.  Blocks
+// the host once per sweep (reads a convergence counter through host_pinned, a pinned int).
+hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, double* evals, void* work,
+                int max_sweeps, int* sweeps_used, int* host_pinned);
+
+}  // namespace mpdo

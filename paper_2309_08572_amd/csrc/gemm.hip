@@ -1,0 +1,286 @@
+// Complex GEMM on CDNA4 matrix cores (gfx950), FP64 and FP32.
+//
+//   C = alpha * op(A) * op(B) + beta * C
+//
+// op(A), op(B) and C are strided complex views (CView): transposes and conjugates are
+// expressed in the view, so theta, Gram products, projections and rebuilds all run through
+// this one kernel without materialising permuted copies.
+//
+// Complex products use four real MFMA products per k-step (re*re - im*im, re*im + im*re);
+// counted as 8 real flop per complex multiply-add, the same as the algorithm.
+// Block tile 64 x 64, k-step 16, 256 threads = 4 waves of 64 lanes, each wave owns a
+// 32 x 32 quadrant = 2 x 2 MFMA 16x16 tiles.  Tiles of A and B are staged through LDS as
+// separate real and imaginary planes; the global loader walks the contiguous dimension of
+// each view so loads coalesce whichever way the view is laid out.  Large-k products with a
+// small output (Gram matrices of tall factors) split k over blockIdx.z and accumulate with
+// FP64/FP32 atomics into a zeroed output.
+#include "common.h"
+#include "gemm.h"
+
+namespace mpdo {
+
+namespace {
+
+constexpr int BM = 64;
+constexpr int BN = 64;
+constexpr int BK = 16;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+    typedef v4d v;
+};
+template <>
+struct Acc<float> {
+    typedef v4f v;
+};
+
+// Output row of accumulator register r in lane group lk (= lane / 16) of a 16x16 tile:
+// the FP64 instruction interleaves rows (lk + 4 r), the FP32 one blocks them (4 lk + r).
+__device__ __forceinline__ int acc_row(double, int lk, int r) { return lk + 4 * r; }
+__device__ __forceinline__ int acc_row(float, int lk, int r) { return 4 * lk + r; }
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+struct GemmArgs {
+    int M, N, K;
+    int ksplit;        // number of k-chunks over blockIdx.z (>= 1)
+    int kchunk;        // k extent of one chunk (multiple of BK)
+    int batch;
+    CView<T> A, B, C;
+    long sA, sB, sC;   // batch strides in complex elements
+    double ar, ai, br, bi;
+    int atomic;        // 1: accumulate alpha*AB into C with atomics (beta ignored)
+};
+
+template <typename T>
+__device__ __forceinline__ void load_cplx(const T* p, long off, int conj, T& re, T& im) {
+    re = p[2 * off];
+    im = p[2 * off + 1];
+    if (conj) im = -im;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
+    __shared__ T sAr[BM][BK + 1];
+    __shared__ T sAi[BM][BK + 1];
+    __shared__ T sBr[BK][BN + 1];
+    __shared__ T sBi[BK][BN + 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1;
+    const int wc = wave & 1;
+    const int m0 = blockIdx.y * BM;
+    const int n0 = blockIdx.x * BN;
+    const int bz = blockIdx.z;
+    const int b = bz / g.ksplit;
+    const int kc = bz - b * g.ksplit;
+    const int kbeg = kc * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+
+    const T* Ap = g.A.p + 2 * (long)b * g.sA;
+    const T* Bp = g.B.p + 2 * (long)b * g.sB;
+    T* Cp = g.C.p + 2 * (long)b * g.sC;
+
+    typename Acc<T>::v cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            cr[i][j] = (typename Acc<T>::v){0, 0, 0, 0};
+            ci[i][j] = (typename Acc<T>::v){0, 0, 0, 0};
+        }
+
+    const bool a_kfast = (g.A.cs == 1);
+    const bool b_nfast = (g.B.cs == 1);
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        // ---- stage A tile (BM x BK) and B tile (BK x BN)
+#pragma unroll
+        for (int j = 0; j < (BM * BK) / 256; ++j) {
+            const int e = tid + 256 * j;
+            int m, k;
+            if (a_kfast) {
+                m = e >> 4;
+                k = e & 15;
+            } else {
+                m = e & 63;
+                k = e >> 6;
+            }
+            const int gm = m0 + m, gk = k0 + k;
+            T re = 0, im = 0;
+            if (gm < g.M && gk < kend) load_cplx(Ap, (long)gm * g.A.rs + (long)gk * g.A.cs, g.A.conj, re, im);
+            sAr[m][k] = re;
+            sAi[m][k] = im;
+        }
+#pragma unroll
+        for (int j = 0; j < (BN * BK) / 256; ++j) {
+            const int e = tid + 256 * j;
+            int n, k;
+            if (b_nfast) {
+                n = e & 63;
+                k = e >> 6;
+            } else {
+                n = e >> 4;
+                k = e & 15;
+            }
+            const int gn = n0 + n, gk = k0 + k;
+            T re = 0, im = 0;
+            if (gn < g.N && gk < kend) load_cplx(Bp, (long)gk * g.B.rs + (long)gn * g.B.cs, g.B.conj, re, im);
+            sBr[k][n] = re;
+            sBi[k][n] = im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ar[i] = sAr[wr * 32 + i * 16 + li][kk + lk];
+                ai[i] = sAi[wr * 32 + i * 16 + li][kk + lk];
+                nai[i] = -ai[i];
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                br[j] = sBr[kk + lk][wc * 32 + j * 16 + li];
+                bi[j] = sBi[kk + lk][wc * 32 + j * 16 + li];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = mfma16(ar[i], br[j], cr[i][j]);
+                    cr[i][j] = mfma16(nai[i], bi[j], cr[i][j]);
+                    ci[i][j] = mfma16(ar[i], bi[j], ci[i][j]);
+                    ci[i][j] = mfma16(ai[i], br[j], ci[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+
+    // ---- epilogue: lane holds column lane%16 and rows acc_row(lane/16, r) of each tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wr * 32 + i * 16 + acc_row(T(0), lk, r);
+                const int gn = n0 + wc * 32 + j * 16 + li;
+                if (gm >= g.M || gn >= g.N) continue;
+                const double xr = (double)cr[i][j][r], xi = (double)ci[i][j][r];
+                const double vr = g.ar * xr - g.ai * xi;
+                const double vi = g.ar * xi + g.ai * xr;
+                const long off = 2 * ((long)gm * g.C.rs + (long)gn * g.C.cs);
+                if (g.atomic) {
+                    atomicAdd(&Cp[off], (T)vr);
+                    atomicAdd(&Cp[off + 1], (T)(g.C.conj ? -vi : vi));
+                } else {
+                    double or_ = 0.0, oi = 0.0;
+                    if (g.br != 0.0 || g.bi != 0.0) {
+                        const double cr0 = (double)Cp[off];
+                        const double ci0 = g.C.conj ? -(double)Cp[off + 1] : (double)Cp[off + 1];
+                        or_ = g.br * cr0 - g.bi * ci0;
+                        oi = g.br * ci0 + g.bi * cr0;
+                    }
+                    const double wr_ = vr + or_;
+                    const double wi_ = vi + oi;
+                    Cp[off] = (T)wr_;
+                    Cp[off + 1] = (T)(g.C.conj ? -wi_ : wi_);
+                }
+            }
+}
+
+template <typename T>
+__global__ void cscale_kernel(CView<T> C, int M, int N, double br, double bi) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)M * N) return;
+    const int m = (int)(idx / N), n = (int)(idx % N);
+    const long off = 2 * ((long)m * C.rs + (long)n * C.cs);
+    if (br == 0.0 && bi == 0.0) {
+        C.p[off] = 0;
+        C.p[off + 1] = 0;
+        return;
+    }
+    const double cr = (double)C.p[off];
+    const double ci = C.conj ? -(double)C.p[off + 1] : (double)C.p[off + 1];
+    const double vr = br * cr - bi * ci, vi = br * ci + bi * cr;
+    C.p[off] = (T)vr;
+    C.p[off + 1] = (T)(C.conj ? -vi : vi);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
+                 CView<T> C, int batch, long sA, long sB, long sC) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    GemmArgs<T> g;
+    g.M = M;
+    g.N = N;
+    g.K = K < 0 ? 0 : K;
+    g.batch = batch;
+    g.A = A;
+    g.B = B;
+    g.C = C;
+    g.sA = sA;
+    g.sB = sB;
+    g.sC = sC;
+    g.ar = alpha.re;
+    g.ai = alpha.im;
+    g.br = beta.re;
+    g.bi = beta.im;
+    g.atomic = 0;
+    g.ksplit = 1;
+    g.kchunk = ((g.K + BK - 1) / BK) * BK;
+    if (g.kchunk == 0) g.kchunk = BK;
+    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+    // split long reductions when the output alone cannot fill the 256 compute units
+    if (tiles < 192 && g.K >= 1024) {
+        int ks = (512 + tiles - 1) / tiles;
+        const int maxks = g.K / 256;
+        if (ks > maxks) ks = maxks;
+        if (ks > 64) ks = 64;
+        if (ks >= 2) {
+            const int chunk = (((g.K + ks - 1) / ks + BK - 1) / BK) * BK;
+            ks = (g.K + chunk - 1) / chunk;
+            if (ks >= 2) {
+                // C <- beta*C first, then accumulate alpha*AB atomically
+                const long tot = (long)M * N;
+                for (int bb = 0; bb < batch; ++bb) {
+                    CView<T> Cb = C;
+                    Cb.p = C.p + 2 * (long)bb * sC;
+                    hipLaunchKernelGGL(cscale_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                                       Cb, M, N, beta.re, beta.im);
+                }
+                g.ksplit = ks;
+                g.kchunk = chunk;
+                g.atomic = 1;
+            }
+        }
+    }
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * g.ksplit);
+    hipLaunchKernelGGL(cgemm_kernel<T>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+template hipError_t cgemm<double>(hipStream_t, int, int, int, cd, CView<double>, CView<double>, cd,
+                                  CView<double>, int, long, long, long);
+template hipError_t cgemm<float>(hipStream_t, int, int, int, cd, CView<float>, CView<float>, cd,
+                                 CView<float>, int, long, long, long);
+
+}  // namespace mpdo

@@ -1,0 +1,210 @@
+"""ctypes binding of libmpdo (include/mpdo.h).
+
+Argument marshalling only: every step of the update runs in the HIP library.  PyTorch
+supplies the device workspace (torch's caching allocator owns it) and the HIP stream.
+The binding refuses to run when libmpdo.so is missing or no GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpdo.so")
+
+MPDO_FP64 = 0
+MPDO_FP32 = 1
+
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_NUMERIC",
+          6: "E_UNSUPPORTED"}
+
+EXPORTS = (
+    "mpdo_create", "mpdo_destroy", "mpdo_workspace_bytes", "mpdo_bind_workspace",
+    "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus",
+    "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_trace", "mpdo_bond_dims",
+    "mpdo_get_site", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
+)
+
+
+class Config(C.Structure):
+    _fields_ = [("n_sites", C.c_int), ("d", C.c_int), ("chi_max", C.c_int),
+                ("precision", C.c_int), ("cutoff_rel", C.c_double), ("ppt", C.c_int),
+                ("renorm_trace", C.c_int), ("hip_stream", C.c_void_p)]
+
+
+class TruncInfo(C.Structure):
+    _fields_ = [("bond", C.c_int), ("chi_l", C.c_int), ("chi_mid", C.c_int), ("chi_r", C.c_int),
+                ("kept", C.c_int), ("path", C.c_int), ("eig_calls", C.c_int),
+                ("ppt_feasible", C.c_int), ("trace_before", C.c_double),
+                ("trace_after", C.c_double), ("xi_before", C.c_double),
+                ("xi_after", C.c_double), ("ppt_theta", C.c_double),
+                ("discarded_weight", C.c_double), ("max_abs_imag_t", C.c_double),
+                ("sigma_max", C.c_double), ("sigma_min_kept", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class MpdoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libmpdo {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library() -> C.CDLL:
+    """Load libmpdo.so (no GPU needed for loading).  Raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: run paper_2309_08572_amd.build first")
+    lib = C.CDLL(_LIB_PATH)
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int)
+    ctx = C.c_void_p
+    lib.mpdo_create.argtypes = [C.POINTER(Config), C.POINTER(ctx)]
+    lib.mpdo_destroy.argtypes = [ctx]
+    lib.mpdo_workspace_bytes.argtypes = [C.POINTER(Config)]
+    lib.mpdo_workspace_bytes.restype = C.c_size_t
+    lib.mpdo_bind_workspace.argtypes = [ctx, C.c_void_p, C.c_size_t]
+    lib.mpdo_init_product_state.argtypes = [ctx, dp]
+    lib.mpdo_apply_gate.argtypes = [ctx, C.c_int, dp, C.POINTER(TruncInfo)]
+    lib.mpdo_apply_gate_kraus.argtypes = [ctx, C.c_int, C.c_int, dp, C.POINTER(TruncInfo)]
+    lib.mpdo_apply_channel.argtypes = [ctx, C.c_int, C.c_int, dp]
+    lib.mpdo_truncate.argtypes = [ctx, C.c_int, C.c_int, C.POINTER(TruncInfo)]
+    lib.mpdo_expect.argtypes = [ctx, C.c_int, ip, ip, dp, C.c_int, dp]
+    lib.mpdo_trace.argtypes = [ctx, dp]
+    lib.mpdo_bond_dims.argtypes = [ctx, ip]
+    lib.mpdo_get_site.argtypes = [ctx, C.c_int, dp, ip]
+    lib.mpdo_synchronize.argtypes = [ctx]
+    lib.mpdo_last_error.argtypes = [ctx]
+    lib.mpdo_last_error.restype = C.c_char_p
+    lib.mpdo_version.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("mpdo_workspace_bytes", "mpdo_last_error", "mpdo_version"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _cplx(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class MPDO:
+    """One density-operator MPO on the GPU (a libmpdo context)."""
+
+    def __init__(self, n_sites: int, d: int, chi_max: int, precision: int = MPDO_FP64,
+                 cutoff_rel: float = 0.0, ppt: bool = True, renorm_trace: bool = False,
+                 device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmpdo needs a visible GPU; no CPU fallback exists")
+        self._torch = torch
+        self.lib = load_library()
+        self.n, self.d, self.chi = n_sites, d, chi_max
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device)
+        self.cfg = Config(n_sites, d, chi_max, precision, cutoff_rel, int(ppt), int(renorm_trace),
+                          C.c_void_p(stream.cuda_stream))
+        self.ctx = C.c_void_p()
+        self._check(self.lib.mpdo_create(C.byref(self.cfg), C.byref(self.ctx)), None)
+        nbytes = self.lib.mpdo_workspace_bytes(C.byref(self.cfg))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.mpdo_bind_workspace(self.ctx, C.c_void_p(self.workspace.data_ptr()),
+                                                 nbytes))
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, status: int, ctx="self"):
+        if status != 0:
+            c = self.ctx if ctx == "self" else None
+            msg = self.lib.mpdo_last_error(c)
+            raise MpdoError(status, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self.lib.mpdo_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ the C ABI
+    def init_product_state(self, rhos: Sequence[np.ndarray]):
+        arr = _cplx(np.stack([np.asarray(r) for r in rhos]))
+        assert arr.shape == (self.n, self.d, self.d)
+        self._check(self.lib.mpdo_init_product_state(self.ctx, _dptr(arr)))
+
+    def apply_gate(self, site: int, superop: np.ndarray, info: bool = False):
+        S = _cplx(superop)
+        ti = TruncInfo()
+        self._check(self.lib.mpdo_apply_gate(self.ctx, site, _dptr(S),
+                                             C.byref(ti) if info else None))
+        return ti.as_dict() if info else None
+
+    def apply_gate_kraus(self, site: int, kraus: Iterable[np.ndarray], info: bool = False):
+        K = _cplx(np.stack([np.asarray(k) for k in kraus]))
+        ti = TruncInfo()
+        self._check(self.lib.mpdo_apply_gate_kraus(self.ctx, site, K.shape[0], _dptr(K),
+                                                   C.byref(ti) if info else None))
+        return ti.as_dict() if info else None
+
+    def apply_channel(self, site: int, kraus: Iterable[np.ndarray]):
+        K = _cplx(np.stack([np.asarray(k) for k in kraus]))
+        self._check(self.lib.mpdo_apply_channel(self.ctx, site, K.shape[0], _dptr(K)))
+
+    def truncate(self, bond: int, chi: int, info: bool = True):
+        ti = TruncInfo()
+        self._check(self.lib.mpdo_truncate(self.ctx, bond, chi, C.byref(ti) if info else None))
+        return ti.as_dict() if info else None
+
+    def expect(self, terms, normalize: bool = True) -> np.ndarray:
+        """terms: list of (first_site, [O_first, O_first+1, ...])."""
+        first = np.array([t[0] for t in terms], dtype=np.int32)
+        lens = np.array([len(t[1]) for t in terms], dtype=np.int32)
+        ops = _cplx(np.concatenate([np.stack([np.asarray(o) for o in t[1]]).reshape(-1)
+                                    for t in terms])) if terms else np.zeros(2)
+        out = np.zeros(2 * len(terms), dtype=np.float64)
+        self._check(self.lib.mpdo_expect(self.ctx, len(terms),
+                                         first.ctypes.data_as(C.POINTER(C.c_int)),
+                                         lens.ctypes.data_as(C.POINTER(C.c_int)), _dptr(ops),
+                                         int(normalize), _dptr(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def trace(self) -> complex:
+        out = np.zeros(2)
+        self._check(self.lib.mpdo_trace(self.ctx, _dptr(out)))
+        return complex(out[0], out[1])
+
+    def bond_dims(self):
+        out = np.zeros(self.n - 1, dtype=np.int32)
+        self._check(self.lib.mpdo_bond_dims(self.ctx, out.ctypes.data_as(C.POINTER(C.c_int))))
+        return [int(x) for x in out]
+
+    def get_site(self, j: int) -> np.ndarray:
+        shape = np.zeros(3, dtype=np.int32)
+        sp = shape.ctypes.data_as(C.POINTER(C.c_int))
+        self._check(self.lib.mpdo_get_site(self.ctx, j, None, sp))
+        out = np.zeros(int(np.prod(shape)), dtype=np.complex128)
+        self._check(self.lib.mpdo_get_site(self.ctx, j, _dptr(out), sp))
+        return out.reshape(tuple(int(x) for x in shape))
+
+    def synchronize(self):
+        self._check(self.lib.mpdo_synchronize(self.ctx))
