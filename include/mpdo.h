@@ -145,6 +145,28 @@ mpdo_status mpdo_bond_dims(mpdo_ctx ctx, int* out);
  * applied); shape[0..2] receives its dimensions.  out may be NULL to query the shape. */
 mpdo_status mpdo_get_site(mpdo_ctx ctx, int site, double* out, int* shape);
 
+/* Kernel families reported by mpdo_profile_read, in this order. */
+enum {
+    MPDO_PROF_GEMM = 0,        /* complex matrix-core GEMM (theta, Gram, projections, rebuild) */
+    MPDO_PROF_EIG_PAIR = 1,    /* Jacobi: 64 x 64 pair eigenproblems in LDS                    */
+    MPDO_PROF_EIG_ROTATE = 2,  /* Jacobi: pair rotations applied to block rows and columns     */
+    MPDO_PROF_EIG_SMALL = 3,   /* Jacobi: whole matrix of order <= 64 in one workgroup         */
+    MPDO_PROF_PHYS = 4,        /* gate factors applied to the physical index of a site         */
+    MPDO_PROF_TRANSFER = 5,    /* transfer-matrix steps of trace / expectation vectors         */
+    MPDO_PROF_OTHER = 6,
+    MPDO_PROF_FAMILIES = 7
+};
+
+/* Measurement switch (instrumentation, not part of the method): with enable = 1 the
+ * context records a HIP event pair around every launch of the families above on its
+ * stream and clears earlier totals; enable = 0 stops recording (totals are kept). */
+mpdo_status mpdo_profile_enable(mpdo_ctx ctx, int enable);
+
+/* Totals since the last mpdo_profile_enable(ctx, 1): out[4 f + 0..3] = launches,
+ * milliseconds, algorithmic flop and algorithmic bytes of family f, for f < n_families.
+ * Synchronises the stream. */
+mpdo_status mpdo_profile_read(mpdo_ctx ctx, double* out, int n_families);
+
 /* Block until all work of the context has finished. */
 mpdo_status mpdo_synchronize(mpdo_ctx ctx);
 

@@ -135,6 +135,64 @@ struct Scratch {
     }
 };
 
+// HIP-event timing of kernel families on the context's stream.
+struct EventProf : public ProfSink {
+    struct Rec {
+        hipEvent_t a, b;
+        int fam;
+        double flop, bytes;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;
+    hipEvent_t cur = nullptr;
+    int cur_fam = -1;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(hipStream_t s, int fam) override {
+        cur = get();
+        cur_fam = fam;
+        if (cur) (void)hipEventRecord(cur, s);
+    }
+    void end(hipStream_t s, int fam, double flop, double bytes) override {
+        hipEvent_t b = get();
+        if (!cur || !b) return;
+        (void)hipEventRecord(b, s);
+        recs.push_back(Rec{cur, b, fam, flop, bytes});
+        cur = nullptr;
+    }
+    // families x (launches, ms, flop, bytes); returns events to the pool
+    void collect(double* acc) {
+        for (auto& r : recs) {
+            float ms = 0.f;
+            (void)hipEventSynchronize(r.b);
+            (void)hipEventElapsedTime(&ms, r.a, r.b);
+            double* o = acc + 4 * r.fam;
+            o[0] += 1.0;
+            o[1] += ms;
+            o[2] += r.flop;
+            o[3] += r.bytes;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    ~EventProf() override {
+        for (auto& r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct GateFactor {
     int r = 0;
     double* X = nullptr;   // r x D2 x D2 (device)
@@ -183,6 +241,8 @@ struct mpdo_ctx_s {
     std::unordered_map<uint64_t, GateFactor> gcache;
     std::vector<uint64_t> gorder;
     std::vector<double*> gslots;  // free device slots for operator-Schmidt factors
+    std::unique_ptr<EventProf> prof;   // non-null while measurement is on
+    double prof_acc[4 * PF_COUNT] = {0};
     double* obuf = nullptr;       // operator vectors of one expectation term (N x D2)
 
     size_t site_cap() const { return (size_t)chi * D2 * chi * 2; }  // in T elements
@@ -224,16 +284,27 @@ struct Engine {
         memcpy(out, c.hbuf, n * sizeof(double));
     }
 
-    void gemm(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_) {
-        HIPCHK(cgemm<T>(st, M, N, K, a, A, B, b, C_));
+    ProfSink* ps() { return c.prof.get(); }
+
+    void gemm(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_, int batch = 1, long sA = 0,
+              long sB = 0, long sC = 0) {
+        ProfSink* p = ps();
+        if (p) p->begin(st, PF_GEMM);
+        HIPCHK(cgemm<T>(st, M, N, K, a, A, B, b, C_, batch, sA, sB, sC));
+        if (p) {
+            const double flop = 8.0 * M * (double)N * K * batch;
+            const double bytes =
+                2.0 * sizeof(T) * batch * ((double)M * K + (double)K * N + (double)M * N * ((b.re != 0 || b.im != 0) ? 2 : 1));
+            p->end(st, PF_GEMM, flop, bytes);
+        }
     }
 
     // Gram G = F^H F (c x c) of the n x c view F, into the FP64 eigen buffer (dense, ld c)
     void gram_cols(CView<T> F, int n, int cc) {
         if (std::is_same<T, double>::value) {
-            HIPCHK(cgemm<T>(st, cc, cc, n, C1(), adj(F), F, C0(), V<T>((T*)s.Gd, cc, 1)));
+            gemm(cc, cc, n, C1(), adj(F), F, C0(), V<T>((T*)s.Gd, cc, 1));
         } else {
-            HIPCHK(cgemm<T>(st, cc, cc, n, C1(), adj(F), F, C0(), V<T>(s.bG, cc, 1)));
+            gemm(cc, cc, n, C1(), adj(F), F, C0(), V<T>(s.bG, cc, 1));
             HIPCHK((geam<T, double>(st, cc, cc, C1(), V<T>(s.bG, cc, 1), C0(), V<double>(s.Gd, cc, 1))));
         }
     }
@@ -242,7 +313,7 @@ struct Engine {
     // the eigenvectors in T
     void eig(int n) {
         int sw = 0;
-        HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, &sw, c.hint));
+        HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, &sw, c.hint, ps()));
         ++eig_calls;
         if (sw >= EIG_MAX_SWEEPS) throw Fail{MPDO_E_NUMERIC, "Jacobi eigensolver did not converge"};
         if (!std::is_same<T, double>::value)
@@ -356,16 +427,23 @@ struct Engine {
     double* Lv(int j) { return c.Lv + (size_t)j * c.chi * 2; }
     double* Rv(int j) { return c.Rv + (size_t)j * c.chi * 2; }
 
+    double tbytes(int j) const { return 2.0 * sizeof(T) * c.dims[j] * (double)c.D2 * c.dims[j + 1]; }
     void ensureL(int i) {
-        for (int j = c.lvalid; j < i; ++j)
+        for (int j = c.lvalid; j < i; ++j) {
+            if (ps()) ps()->begin(st, PF_TRANSFER);
             HIPCHK(transfer_left<T>(st, site(j), c.dims[j], c.D2, c.dims[j + 1], Lv(j), c.ovec + 2 * j * c.D2,
                                     Lv(j + 1)));
+            if (ps()) ps()->end(st, PF_TRANSFER, 8.0 * c.dims[j] * (double)c.D2 * c.dims[j + 1], tbytes(j));
+        }
         if (i > c.lvalid) c.lvalid = i;
     }
     void ensureR(int i) {
-        for (int j = c.rvalid - 1; j >= i; --j)
+        for (int j = c.rvalid - 1; j >= i; --j) {
+            if (ps()) ps()->begin(st, PF_TRANSFER);
             HIPCHK(transfer_right<T>(st, site(j), c.dims[j], c.D2, c.dims[j + 1], Rv(j + 1), c.ovec + 2 * j * c.D2,
                                      Rv(j)));
+            if (ps()) ps()->end(st, PF_TRANSFER, 8.0 * c.dims[j] * (double)c.D2 * c.dims[j + 1], tbytes(j));
+        }
         if (i < c.rvalid) c.rvalid = i;
     }
     void site_changed(int j) {
@@ -448,8 +526,12 @@ struct Engine {
         if (factored) {
             const int k = r * cm;
             // M_L (nL x k) in bA, M_R (k x nR) in bB
+            if (ps()) ps()->begin(st, PF_PHYS);
             HIPCHK(phys_left<T>(st, site(i), cl, D2, cm, gf->X, r, s.bA));
             HIPCHK(phys_right<T>(st, site(i + 1), cm, D2, cr, gf->Y, r, s.bB));
+            if (ps())
+                ps()->end(st, PF_PHYS, 8.0 * D2 * (double)D2 * r * cm * (cl + cr),
+                          2.0 * sizeof(T) * ((double)cl * D2 * cm + (double)cm * D2 * cr) * (1.0 + r));
             CView<T> ML = V<T>(s.bA, k, 1), MR = V<T>(s.bB, nR, 1);
             // tr rho = (lvec^T M_L)(M_R rvec)
             HIPCHK(gemv_left<T>(st, ML, nL, k, s.lvec, s.vtmp));
@@ -480,8 +562,8 @@ struct Engine {
             // explicit theta: merge then gate
             const int m2 = D2 * D2;
             gemm(nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(), V<T>(s.bT1, nR, 1));
-            HIPCHK(cgemm<T>(st, m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(),
-                            V<T>(s.bA, cr, 1), cl, 0, (long)m2 * cr, (long)m2 * cr));
+            gemm(m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(), V<T>(s.bA, cr, 1), cl, 0,
+                 (long)m2 * cr, (long)m2 * cr);
             CView<T> Th = V<T>(s.bA, nR, 1);
             HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
             HIPCHK(dot(st, s.lvec, s.vtmp, nL, s.sc));
@@ -503,6 +585,10 @@ struct Engine {
         }
         Left = outL;
         Right = outR;
+        // Schmidt values as the norms of the rows of B = U^H theta: with them |Lambda'|^2 and
+        // T'.Lambda' equal ||theta||^2 and tr(rho) up to rounding whatever the accuracy of
+        // the Gram eigenvalues, so PPT is the identity when nothing is cut
+        HIPCHK(row_norms<T>(st, V<T>(s.bB2, nb, 1), kept, nb, s.sig));
         // trace factors of the kept Schmidt pairs and PPT
         HIPCHK(gemv_left<T>(st, V<T>(Left, kept, 1), nL, kept, s.lvec, s.tl));
         HIPCHK(gemv_left<T>(st, trans(V<T>(Right, nR, 1)), nR, kept, s.rvec, s.tr));
@@ -1220,6 +1306,27 @@ mpdo_status mpdo_synchronize(mpdo_ctx c) {
         c->poisoned = true;
         return MPDO_E_DEVICE;
     }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_profile_enable(mpdo_ctx c, int enable) {
+    if (!c) return MPDO_E_ARG;
+    if (enable) {
+        c->prof.reset(new EventProf());
+        for (double& x : c->prof_acc) x = 0.0;
+    } else if (c->prof) {
+        c->prof->collect(c->prof_acc);
+        c->prof.reset();
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_profile_read(mpdo_ctx c, double* out, int n_families) {
+    if (!c || !out || n_families < 0) return MPDO_E_ARG;
+    if (c->prof) c->prof->collect(c->prof_acc);
+    const int nf = std::min(n_families, (int)PF_COUNT);
+    for (int f = 0; f < nf; ++f)
+        for (int q = 0; q < 4; ++q) out[4 * f + q] = c->prof_acc[4 * f + q];
     return MPDO_OK;
 }
 

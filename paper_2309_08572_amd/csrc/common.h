@@ -51,4 +51,15 @@ struct cd {
     double re, im;
 };
 
+// Kernel families timed by the profiling sink.
+enum ProfFamily { PF_GEMM = 0, PF_EIG_PAIR = 1, PF_EIG_ROT = 2, PF_EIG_SMALL = 3, PF_PHYS = 4,
+                  PF_TRANSFER = 5, PF_OTHER = 6, PF_COUNT = 7 };
+
+// Receives begin/end marks around kernel launches when measurement is on (else null).
+struct ProfSink {
+    virtual void begin(hipStream_t s, int family) = 0;
+    virtual void end(hipStream_t s, int family, double flop, double bytes) = 0;
+    virtual ~ProfSink() {}
+};
+
 }  // namespace mpdo

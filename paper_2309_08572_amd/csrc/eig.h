@@ -12,7 +12,8 @@ size_t eigh_work_bytes(int n);
 // dimension ldh, overwritten).  evals[0..n) receives the eigenvalues in descending order,
 // V (row-major, leading dimension ldv) the matching unit eigenvectors as columns.  Blocks
 // the host once per sweep (reads a convergence counter through host_pinned, a pinned int).
+// prof (may be null) receives marks around every kernel launch.
 hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, double* evals, void* work,
-                int max_sweeps, int* sweeps_used, int* host_pinned);
+                int max_sweeps, int* sweeps_used, int* host_pinned, ProfSink* prof = nullptr);
 
 }  // namespace mpdo

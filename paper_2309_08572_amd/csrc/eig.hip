@@ -11,6 +11,8 @@
 // (entries below the rounding level of the matrix itself are not rotated away).
 // Matrices of order <= 64 are solved by one workgroup in one launch.
 // Output: eigenvalues in descending order and the matching eigenvectors as columns.
+#include <stdlib.h>
+
 #include "common.h"
 #include "eig.h"
 
@@ -47,7 +49,10 @@ __device__ __forceinline__ void circle_pair(int players, int round, int j, int& 
 }
 
 // Diagonalise the Hermitian n x n matrix in L (n even, <= 64); L.V accumulates the
-// rotations (starts as identity).  Returns the number of sweeps that rotated.
+// rotations (starts as identity).  Each round computes the rotations of the n/2 disjoint
+// pairs, then applies H <- J^+ H J and V <- V J in one pass: a thread owns the 2 x 2 block
+// (rows of pair a) x (columns of pair b) and applies both rotations to it.
+// Returns the number of sweeps that rotated.
 __device__ int lds_jacobi(PairLds& L, int n, double tol_rel, double tol_abs, int max_sweeps) {
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
@@ -86,41 +91,74 @@ __device__ int lds_jacobi(PairLds& L, int n, double tol_rel, double tol_abs, int
                 L.q[tid] = q;
             }
             __syncthreads();
-            // rows: H <- J^+ H ; new_p = c h_p - s e h_q ; new_q = s h_p + c e h_q
-            for (int idx = tid; idx < half * n; idx += nt) {
-                const int j = idx / n, k = idx - (idx / n) * n;
-                const double s = L.s[j];
-                if (s == 0.0) continue;
-                const double c = L.c[j], er = L.er[j], ei = L.ei[j];
-                const int p = L.p[j], q = L.q[j];
-                const double hpr = L.Hr[p][k], hpi = L.Hi[p][k];
-                const double hqr = L.Hr[q][k], hqi = L.Hi[q][k];
-                const double eqr = er * hqr - ei * hqi, eqi = er * hqi + ei * hqr;  // e * h_q
-                L.Hr[p][k] = c * hpr - s * eqr;
-                L.Hi[p][k] = c * hpi - s * eqi;
-                L.Hr[q][k] = s * hpr + c * eqr;
-                L.Hi[q][k] = s * hpi + c * eqi;
-            }
-            __syncthreads();
-            // columns: X <- X J for X in {H, V}; new_p = c x_p - s conj(e) x_q ;
-            // new_q = s x_p + c conj(e) x_q
-            for (int idx = tid; idx < 2 * half * n; idx += nt) {
-                const int which = idx / (half * n);
-                const int rem = idx - which * half * n;
-                const int j = rem / n, k = rem - (rem / n) * n;
-                const double s = L.s[j];
-                if (s == 0.0) continue;
-                const double c = L.c[j], er = L.er[j], ei = -L.ei[j];
-                const int p = L.p[j], q = L.q[j];
-                double (*Xr)[LD] = which ? L.Vr : L.Hr;
-                double (*Xi)[LD] = which ? L.Vi : L.Hi;
-                const double xpr = Xr[k][p], xpi = Xi[k][p];
-                const double xqr = Xr[k][q], xqi = Xi[k][q];
-                const double eqr = er * xqr - ei * xqi, eqi = er * xqi + ei * xqr;
-                Xr[k][p] = c * xpr - s * eqr;
-                Xi[k][p] = c * xpi - s * eqi;
-                Xr[k][q] = s * xpr + c * eqr;
-                Xi[k][q] = s * xpi + c * eqi;
+            const int nh = half * half;
+            for (int idx = tid; idx < nh + half * n; idx += nt) {
+                if (idx < nh) {
+                    // H block: rows {p_a, q_a} x columns {p_b, q_b}
+                    const int a = idx / half, b = idx - (idx / half) * half;
+                    const double sa = L.s[a], sb = L.s[b];
+                    if (sa == 0.0 && sb == 0.0) continue;
+                    const int pa = L.p[a], qa = L.q[a], pb = L.p[b], qb = L.q[b];
+                    double h11r = L.Hr[pa][pb], h11i = L.Hi[pa][pb];
+                    double h12r = L.Hr[pa][qb], h12i = L.Hi[pa][qb];
+                    double h21r = L.Hr[qa][pb], h21i = L.Hi[qa][pb];
+                    double h22r = L.Hr[qa][qb], h22i = L.Hi[qa][qb];
+                    if (sa != 0.0) {
+                        // rows: new_p = c h_p - s e h_q ; new_q = s h_p + c e h_q
+                        const double c = L.c[a], er = L.er[a], ei = L.ei[a];
+                        const double e1r = er * h21r - ei * h21i, e1i = er * h21i + ei * h21r;
+                        const double e2r = er * h22r - ei * h22i, e2i = er * h22i + ei * h22r;
+                        const double n11r = c * h11r - sa * e1r, n11i = c * h11i - sa * e1i;
+                        const double n12r = c * h12r - sa * e2r, n12i = c * h12i - sa * e2i;
+                        h21r = sa * h11r + c * e1r;
+                        h21i = sa * h11i + c * e1i;
+                        h22r = sa * h12r + c * e2r;
+                        h22i = sa * h12i + c * e2i;
+                        h11r = n11r;
+                        h11i = n11i;
+                        h12r = n12r;
+                        h12i = n12i;
+                    }
+                    if (sb != 0.0) {
+                        // columns: new_p = c x_p - s conj(e) x_q ; new_q = s x_p + c conj(e) x_q
+                        const double c = L.c[b], er = L.er[b], ei = -L.ei[b];
+                        const double e1r = er * h12r - ei * h12i, e1i = er * h12i + ei * h12r;
+                        const double e2r = er * h22r - ei * h22i, e2i = er * h22i + ei * h22r;
+                        const double n11r = c * h11r - sb * e1r, n11i = c * h11i - sb * e1i;
+                        const double n21r = c * h21r - sb * e2r, n21i = c * h21i - sb * e2i;
+                        h12r = sb * h11r + c * e1r;
+                        h12i = sb * h11i + c * e1i;
+                        h22r = sb * h21r + c * e2r;
+                        h22i = sb * h21i + c * e2i;
+                        h11r = n11r;
+                        h11i = n11i;
+                        h21r = n21r;
+                        h21i = n21i;
+                    }
+                    L.Hr[pa][pb] = h11r;
+                    L.Hi[pa][pb] = h11i;
+                    L.Hr[pa][qb] = h12r;
+                    L.Hi[pa][qb] = h12i;
+                    L.Hr[qa][pb] = h21r;
+                    L.Hi[qa][pb] = h21i;
+                    L.Hr[qa][qb] = h22r;
+                    L.Hi[qa][qb] = h22i;
+                } else {
+                    // V <- V J on the columns of pair b, row k
+                    const int rem = idx - nh;
+                    const int b = rem / n, k = rem - (rem / n) * n;
+                    const double sb = L.s[b];
+                    if (sb == 0.0) continue;
+                    const double c = L.c[b], er = L.er[b], ei = -L.ei[b];
+                    const int pb = L.p[b], qb = L.q[b];
+                    const double xpr = L.Vr[k][pb], xpi = L.Vi[k][pb];
+                    const double xqr = L.Vr[k][qb], xqi = L.Vi[k][qb];
+                    const double eqr = er * xqr - ei * xqi, eqi = er * xqi + ei * xqr;
+                    L.Vr[k][pb] = c * xpr - sb * eqr;
+                    L.Vi[k][pb] = c * xpi - sb * eqi;
+                    L.Vr[k][qb] = sb * xpr + c * eqr;
+                    L.Vi[k][qb] = sb * xpi + c * eqi;
+                }
             }
             __syncthreads();
         }
@@ -141,7 +179,7 @@ __device__ __forceinline__ int pair_index(int P, int Q, int x) {
 }
 
 // ---------------------------------------------------------------- small matrices
-__global__ __launch_bounds__(256) void jac_small_kernel(const double* __restrict__ H, int ld, int n,
+__global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restrict__ H, int ld, int n,
                                                         const double* __restrict__ fro, double tol_rel,
                                                         int max_sweeps, double* __restrict__ evals,
                                                         double* __restrict__ V, int ldv,
@@ -200,7 +238,7 @@ __global__ __launch_bounds__(256) void jac_small_kernel(const double* __restrict
 }
 
 // ---------------------------------------------------------------- blocked matrices
-__global__ __launch_bounds__(256) void jac_pair_kernel(const double* __restrict__ H, int ld, int n, int nblk,
+__global__ __launch_bounds__(1024) void jac_pair_kernel(const double* __restrict__ H, int ld, int n, int nblk,
                                                        int round, double* __restrict__ Vp,
                                                        int* __restrict__ skip, int* __restrict__ nrot,
                                                        const double* __restrict__ fro, double tol_rel,
@@ -322,35 +360,8 @@ __device__ void rot_product(const RotLds& L, int mode, v4d cr[2][2], v4d ci[2][2
     }
 }
 
-// rows of pair p, columns [64 ct, 64 ct + 64):  X <- Vp^+ X
-__global__ __launch_bounds__(256) void jac_rot_rows_kernel(double* __restrict__ H, int ld, int n, int nblk,
-                                                           int round, const double* __restrict__ Vp,
-                                                           const int* __restrict__ skip) {
-    __shared__ RotLds L;
-    const int pair = blockIdx.y;
-    if (skip[pair]) return;
-    int P, Q;
-    pair_rows(nblk, round, pair, P, Q);
-    const int c0 = blockIdx.x * NP;
-    const int tid = threadIdx.x;
-    const double* U = Vp + (long)pair * NP * NP * 2;
-    for (int idx = tid; idx < NP * NP; idx += blockDim.x) {
-        const int x = idx / NP, y = idx % NP;
-        const int gx = pair_index(P, Q, x), gy = c0 + y;
-        double xr = 0.0, xi = 0.0;
-        if (gx < n && gy < n) {
-            xr = H[2 * ((long)gx * ld + gy)];
-            xi = H[2 * ((long)gx * ld + gy) + 1];
-        }
-        L.Xr[x][y] = xr;
-        L.Xi[x][y] = xi;
-        L.Ur[x][y] = U[2 * idx];
-        L.Ui[x][y] = U[2 * idx + 1];
-    }
-    __syncthreads();
-    v4d cr[2][2], ci[2][2];
-    rot_product(L, 0, cr, ci);
-    const int lane = tid & 63, wave = tid >> 6;
+__device__ void store_acc(RotLds& L, const v4d cr[2][2], const v4d ci[2][2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -358,61 +369,109 @@ __global__ __launch_bounds__(256) void jac_rot_rows_kernel(double* __restrict__ 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int x = wr * 32 + i * 16 + lk + 4 * r;   // FP64 MFMA row interleave
+                const int x = wr * 32 + i * 16 + lk + 4 * r;
                 const int y = wc * 32 + j * 16 + li;
-                const int gx = pair_index(P, Q, x), gy = c0 + y;
-                if (gx < n && gy < n) {
-                    H[2 * ((long)gx * ld + gy)] = cr[i][j][r];
-                    H[2 * ((long)gx * ld + gy) + 1] = ci[i][j][r];
-                }
+                L.Xr[x][y] = cr[i][j][r];
+                L.Xi[x][y] = ci[i][j][r];
             }
 }
 
-// columns of pair p, rows [64 rt, 64 rt + 64) of H (z = 0) or of Z (z = 1):  X <- X Vp
-__global__ __launch_bounds__(256) void jac_rot_cols_kernel(double* __restrict__ H, int ld, double* __restrict__ Z,
-                                                           int ldz, int n, int nblk, int round,
-                                                           const double* __restrict__ Vp,
-                                                           const int* __restrict__ skip) {
-    __shared__ RotLds L;
-    const int pair = blockIdx.y;
-    if (skip[pair]) return;
-    int P, Q;
-    pair_rows(nblk, round, pair, P, Q);
-    double* M = blockIdx.z ? Z : H;
-    const int ldm = blockIdx.z ? ldz : ld;
-    const int r0 = blockIdx.x * NP;
-    const int tid = threadIdx.x;
+__device__ void load_rot(RotLds& L, const double* Vp, int pair, int skipped) {
     const double* U = Vp + (long)pair * NP * NP * 2;
-    for (int idx = tid; idx < NP * NP; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
         const int x = idx / NP, y = idx % NP;
-        const int gx = r0 + x, gy = pair_index(P, Q, y);
+        L.Ur[x][y] = skipped ? (x == y ? 1.0 : 0.0) : U[2 * idx];
+        L.Ui[x][y] = skipped ? 0.0 : U[2 * idx + 1];
+    }
+}
+
+// One launch per round: blocks [0, m^2) apply H_ab <- V_a^+ H_ab V_b to the 64 x 64 block
+// (rows of pair a) x (columns of pair b); blocks [m^2, m^2 + m * tiles) apply Z <- Z V_b to a
+// 64-row tile of the eigenvector accumulator.  Every block owns the entries it rewrites.
+__global__ __launch_bounds__(256) void jac_rot2_kernel(double* __restrict__ H, int ld, double* __restrict__ Z,
+                                                       int ldz, int n, int nblk, int round,
+                                                       const double* __restrict__ Vp,
+                                                       const int* __restrict__ skip) {
+    __shared__ RotLds L;
+    const int m = nblk / 2;
+    const int bid = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+    v4d cr[2][2], ci[2][2];
+    if (bid < m * m) {
+        const int a = bid / m, b = bid % m;
+        const int sa = skip[a], sb = skip[b];
+        if (sa && sb) return;
+        int Pa, Qa, Pb, Qb;
+        pair_rows(nblk, round, a, Pa, Qa);
+        pair_rows(nblk, round, b, Pb, Qb);
+        for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+            const int x = idx / NP, y = idx % NP;
+            const int gx = pair_index(Pa, Qa, x), gy = pair_index(Pb, Qb, y);
+            double xr = 0.0, xi = 0.0;
+            if (gx < n && gy < n) {
+                xr = H[2 * ((long)gx * ld + gy)];
+                xi = H[2 * ((long)gx * ld + gy) + 1];
+            }
+            L.Xr[x][y] = xr;
+            L.Xi[x][y] = xi;
+        }
+        load_rot(L, Vp, b, sb);
+        __syncthreads();
+        rot_product(L, 1, cr, ci);   // X V_b
+        __syncthreads();
+        store_acc(L, cr, ci);
+        load_rot(L, Vp, a, sa);
+        __syncthreads();
+        rot_product(L, 0, cr, ci);   // V_a^+ (X V_b)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int x = wr * 32 + i * 16 + lk + 4 * r;   // FP64 MFMA row interleave
+                    const int y = wc * 32 + j * 16 + li;
+                    const int gx = pair_index(Pa, Qa, x), gy = pair_index(Pb, Qb, y);
+                    if (gx < n && gy < n) {
+                        H[2 * ((long)gx * ld + gy)] = cr[i][j][r];
+                        H[2 * ((long)gx * ld + gy) + 1] = ci[i][j][r];
+                    }
+                }
+        return;
+    }
+    const int idx0 = bid - m * m;
+    const int b = idx0 % m, rt = idx0 / m;
+    if (skip[b]) return;
+    int Pb, Qb;
+    pair_rows(nblk, round, b, Pb, Qb);
+    const int r0 = rt * NP;
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+        const int x = idx / NP, y = idx % NP;
+        const int gx = r0 + x, gy = pair_index(Pb, Qb, y);
         double xr = 0.0, xi = 0.0;
         if (gx < n && gy < n) {
-            xr = M[2 * ((long)gx * ldm + gy)];
-            xi = M[2 * ((long)gx * ldm + gy) + 1];
+            xr = Z[2 * ((long)gx * ldz + gy)];
+            xi = Z[2 * ((long)gx * ldz + gy) + 1];
         }
         L.Xr[x][y] = xr;
         L.Xi[x][y] = xi;
-        L.Ur[x][y] = U[2 * idx];
-        L.Ui[x][y] = U[2 * idx + 1];
     }
+    load_rot(L, Vp, b, 0);
     __syncthreads();
-    v4d cr[2][2], ci[2][2];
     rot_product(L, 1, cr, ci);
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int x = wr * 32 + i * 16 + lk + 4 * r;   // FP64 MFMA row interleave
+                const int x = wr * 32 + i * 16 + lk + 4 * r;
                 const int y = wc * 32 + j * 16 + li;
-                const int gx = r0 + x, gy = pair_index(P, Q, y);
+                const int gx = r0 + x, gy = pair_index(Pb, Qb, y);
                 if (gx < n && gy < n) {
-                    M[2 * ((long)gx * ldm + gy)] = cr[i][j][r];
-                    M[2 * ((long)gx * ldm + gy) + 1] = ci[i][j][r];
+                    Z[2 * ((long)gx * ldz + gy)] = cr[i][j][r];
+                    Z[2 * ((long)gx * ldz + gy) + 1] = ci[i][j][r];
                 }
             }
 }
@@ -485,7 +544,7 @@ size_t eigh_work_bytes(int n) {
 }
 
 hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, double* evals, void* work,
-                int max_sweeps, int* sweeps_used, int* host_pinned) {
+                int max_sweeps, int* sweeps_used, int* host_pinned, ProfSink* prof) {
     if (n <= 0) return hipSuccess;
     const double tol_rel = 1e-15;
     char* w = (char*)work;
@@ -502,8 +561,10 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
 
     hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, H, ldh, n, fro);
     if (n <= NP) {
-        hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(256), 0, s, H, ldh, n, fro, tol_rel, max_sweeps,
+        if (prof) prof->begin(s, PF_EIG_SMALL);
+        hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(1024), 0, s, H, ldh, n, fro, tol_rel, max_sweeps,
                            evals, V, ldv, nrot);
+        if (prof) prof->end(s, PF_EIG_SMALL, 0.0, 32.0 * n * n);
         if (sweeps_used) {
             hipMemcpyAsync(host_pinned, nrot, sizeof(int), hipMemcpyDeviceToHost, s);
             hipError_t e = hipStreamSynchronize(s);
@@ -512,19 +573,36 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
         }
         return hipGetLastError();
     }
+    static int inner_sweeps = -1;
+    if (inner_sweeps < 0) {
+        const char* e = getenv("MPDO_JACOBI_INNER_SWEEPS");
+        inner_sweeps = e ? atoi(e) : 1;
+        if (inner_sweeps < 1) inner_sweeps = 1;
+    }
     const long nn = (long)n * n;
     hipLaunchKernelGGL(eye_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, Z, n, n);
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, nrot, 1);
         for (int r = 0; r < nblk - 1; ++r) {
-            hipLaunchKernelGGL(jac_pair_kernel, dim3(nblk / 2), dim3(256), 0, s, H, ldh, n, nblk, r, Vp, skip,
-                               nrot, fro, tol_rel, 30);
+            const double pairs = nblk / 2;
+            if (prof) prof->begin(s, PF_EIG_PAIR);
+            hipLaunchKernelGGL(jac_pair_kernel, dim3(nblk / 2), dim3(1024), 0, s, H, ldh, n, nblk, r, Vp, skip,
+                               nrot, fro, tol_rel, inner_sweeps);
+            // one inner sweep: NP-1 rounds; per round NP/2 rotations (~40 flop each), the 2 x 2
+            // block updates of H ((NP/2)^2 blocks, 56 flop) and of V (NP * NP/2 pairs, 14 flop)
+            const double pair_flop = (double)inner_sweeps * (NP - 1) *
+                                     (40.0 * (NP / 2) + 56.0 * (NP / 2) * (NP / 2) + 14.0 * NP * (NP / 2));
+            if (prof) prof->end(s, PF_EIG_PAIR, pairs * pair_flop, pairs * NP * NP * 16.0 * 2.0);
             const int tiles = (n + NP - 1) / NP;
-            hipLaunchKernelGGL(jac_rot_rows_kernel, dim3(tiles, nblk / 2), dim3(256), 0, s, H, ldh, n, nblk, r,
-                               Vp, skip);
-            hipLaunchKernelGGL(jac_rot_cols_kernel, dim3(tiles, nblk / 2, 2), dim3(256), 0, s, H, ldh, Z, n, n,
-                               nblk, r, Vp, skip);
+            const int m = nblk / 2;
+            // per block pair two 64^3 complex products; per Z tile one
+            const double rotflop = 8.0 * NP * NP * (double)NP * (2.0 * m * m + (double)m * tiles);
+            const double rotbytes = 16.0 * NP * (double)NP * (2.0 * m * m + 2.0 * m * tiles);
+            if (prof) prof->begin(s, PF_EIG_ROT);
+            hipLaunchKernelGGL(jac_rot2_kernel, dim3(m * m + m * tiles), dim3(256), 0, s, H, ldh, Z, n, n, nblk,
+                               r, Vp, skip);
+            if (prof) prof->end(s, PF_EIG_ROT, rotflop, rotbytes);
         }
         hipMemcpyAsync(host_pinned, nrot, sizeof(int), hipMemcpyDeviceToHost, s);
         hipError_t e = hipStreamSynchronize(s);

@@ -64,6 +64,10 @@ hipError_t zero_doubles(hipStream_t s, double* p, int n);
 template <typename T>
 hipError_t gemv_left(hipStream_t s, CView<T> M, int a, int n, const double* x, double* y);
 
+// out[j] = ||X[j, :]|| (FP64) for the k x ncol view X.
+template <typename T>
+hipError_t row_norms(hipStream_t s, CView<T> X, int k, int ncol, double* out);
+
 // out[0] + i out[1] = sum_a x[a] y[a] (FP64 complex).
 hipError_t dot(hipStream_t s, const double* x, const double* y, int n, double* out);
 

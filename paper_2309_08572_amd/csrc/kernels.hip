@@ -447,6 +447,26 @@ __global__ __launch_bounds__(256) void gemv_left_kernel(CView<T> M, int a, int n
     }
 }
 
+// out[j] = ||X[j, :]||_2 for the k x ncol view X, FP64 accumulation; one block per row.
+template <typename T>
+__global__ __launch_bounds__(256) void row_norms_kernel(CView<T> X, int ncol, double* __restrict__ out) {
+    __shared__ double part[256];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+        const long off = 2 * ((long)j * X.rs + (long)c * X.cs);
+        const double r = (double)X.p[off], i = (double)X.p[off + 1];
+        acc += r * r + i * i;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = sqrt(part[0]);
+}
+
 // out[0..1] = sum_a x[a] y[a] (unconjugated complex dot), FP64
 __global__ void dot_kernel(const double* __restrict__ x, const double* __restrict__ y, int n,
                            double* __restrict__ out) {
@@ -585,6 +605,13 @@ hipError_t gemv_left(hipStream_t s, CView<T> M, int a, int n, const double* x, d
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t row_norms(hipStream_t s, CView<T> X, int k, int ncol, double* out) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(row_norms_kernel<T>, dim3(k), dim3(256), 0, s, X, ncol, out);
+    return hipGetLastError();
+}
+
 hipError_t dot(hipStream_t s, const double* x, const double* y, int n, double* out) {
     hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(256), 0, s, x, y, n, out);
     return hipGetLastError();
@@ -601,7 +628,8 @@ hipError_t dot(hipStream_t s, const double* x, const double* y, int n, double* o
     template hipError_t scale_cols<T>(hipStream_t, CView<T>, int, int, const double*);                          \
     template hipError_t ns_prep<T>(hipStream_t, const T*, int, T*);                                              \
     template hipError_t scale_rows<T>(hipStream_t, T*, int, int, long, const double*);                          \
-    template hipError_t gemv_left<T>(hipStream_t, CView<T>, int, int, const double*, double*);
+    template hipError_t gemv_left<T>(hipStream_t, CView<T>, int, int, const double*, double*);                  \
+    template hipError_t row_norms<T>(hipStream_t, CView<T>, int, int, double*);
 
 MPDO_INST_T(double)
 MPDO_INST_T(float)

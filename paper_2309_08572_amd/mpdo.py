@@ -25,7 +25,10 @@ EXPORTS = (
     "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus",
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
+    "mpdo_profile_enable", "mpdo_profile_read",
 )
+
+PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other")
 
 
 class Config(C.Structure):
@@ -89,6 +92,8 @@ def load_library() -> C.CDLL:
     lib.mpdo_last_error.argtypes = [ctx]
     lib.mpdo_last_error.restype = C.c_char_p
     lib.mpdo_version.restype = C.c_char_p
+    lib.mpdo_profile_enable.argtypes = [ctx, C.c_int]
+    lib.mpdo_profile_read.argtypes = [ctx, dp, C.c_int]
     for name in EXPORTS:
         if name not in ("mpdo_workspace_bytes", "mpdo_last_error", "mpdo_version"):
             getattr(lib, name).restype = C.c_int
@@ -205,6 +210,19 @@ class MPDO:
         out = np.zeros(int(np.prod(shape)), dtype=np.complex128)
         self._check(self.lib.mpdo_get_site(self.ctx, j, _dptr(out), sp))
         return out.reshape(tuple(int(x) for x in shape))
+
+    def profile(self, enable: bool):
+        self._check(self.lib.mpdo_profile_enable(self.ctx, int(enable)))
+
+    def profile_read(self) -> dict:
+        nf = len(PROF_FAMILIES)
+        out = np.zeros(4 * nf)
+        self._check(self.lib.mpdo_profile_read(self.ctx, _dptr(out), nf))
+        res = {}
+        for f, name in enumerate(PROF_FAMILIES):
+            res[name] = {"launches": int(out[4 * f]), "ms": float(out[4 * f + 1]),
+                         "flops": float(out[4 * f + 2]), "bytes": float(out[4 * f + 3])}
+        return res
 
     def synchronize(self):
         self._check(self.lib.mpdo_synchronize(self.ctx))
