@@ -20,19 +20,21 @@ namespace mpdo {
 
 namespace {
 
-constexpr int NB = 32;       // block rows
-constexpr int NP = 64;       // pair matrix order
-constexpr int LD = NP + 1;   // LDS row stride (doubles)
+constexpr int NB = 16;       // block rows of the blocked solver
+constexpr int NP = 2 * NB;   // pair matrix order
+constexpr int NS = 64;       // largest order solved by one workgroup in one launch
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+template <int N>
 struct PairLds {
-    double Hr[NP][LD];
-    double Hi[NP][LD];
-    double Vr[NP][LD];
-    double Vi[NP][LD];
-    double c[NP / 2], s[NP / 2], er[NP / 2], ei[NP / 2];
-    int p[NP / 2], q[NP / 2];
+    static constexpr int LD = N + 1;   // LDS row stride (doubles)
+    double Hr[N][LD];
+    double Hi[N][LD];
+    double Vr[N][LD];
+    double Vi[N][LD];
+    double c[N / 2], s[N / 2], er[N / 2], ei[N / 2];
+    int p[N / 2], q[N / 2];
     int flag;
 };
 
@@ -53,7 +55,8 @@ __device__ __forceinline__ void circle_pair(int players, int round, int j, int& 
 // pairs, then applies H <- J^+ H J and V <- V J in one pass: a thread owns the 2 x 2 block
 // (rows of pair a) x (columns of pair b) and applies both rotations to it.
 // Returns the number of sweeps that rotated.
-__device__ int lds_jacobi(PairLds& L, int n, double tol_rel, double tol_abs, int max_sweeps) {
+template <int N>
+__device__ int lds_jacobi(PairLds<N>& L, int n, double tol_rel, double tol_abs, int max_sweeps) {
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     const int half = n / 2;
@@ -184,12 +187,12 @@ __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restric
                                                         int max_sweeps, double* __restrict__ evals,
                                                         double* __restrict__ V, int ldv,
                                                         int* __restrict__ sweeps_out) {
-    __shared__ PairLds L;
-    __shared__ int rank[NP];
+    __shared__ PairLds<NS> L;
+    __shared__ int rank[NS];
     const int tid = threadIdx.x;
     const int np = (n + 1) & ~1;
-    for (int idx = tid; idx < NP * NP; idx += blockDim.x) {
-        const int x = idx / NP, y = idx % NP;
+    for (int idx = tid; idx < NS * NS; idx += blockDim.x) {
+        const int x = idx / NS, y = idx % NS;
         double hr = 0.0, hi = 0.0;
         if (x < n && y < n) {
             hr = H[2 * ((long)x * ld + y)];
@@ -202,8 +205,8 @@ __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restric
     }
     __syncthreads();
     // Hermitian part: average the two triangles, real diagonal
-    for (int idx = tid; idx < NP * NP; idx += blockDim.x) {
-        const int x = idx / NP, y = idx % NP;
+    for (int idx = tid; idx < NS * NS; idx += blockDim.x) {
+        const int x = idx / NS, y = idx % NS;
         if (x < y) {
             const double r = 0.5 * (L.Hr[x][y] + L.Hr[y][x]);
             const double i = 0.5 * (L.Hi[x][y] - L.Hi[y][x]);
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restric
         }
     }
     __syncthreads();
-    const int sw = lds_jacobi(L, np, tol_rel, 2.220446049250313e-16 * fro[0], max_sweeps);
+    const int sw = lds_jacobi<NS>(L, np, tol_rel, 2.220446049250313e-16 * fro[0], max_sweeps);
     if (tid < n) {
         const double lam = L.Hr[tid][tid];
         int rk = 0;
@@ -238,12 +241,12 @@ __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restric
 }
 
 // ---------------------------------------------------------------- blocked matrices
-__global__ __launch_bounds__(1024) void jac_pair_kernel(const double* __restrict__ H, int ld, int n, int nblk,
+__global__ __launch_bounds__(256) void jac_pair_kernel(const double* __restrict__ H, int ld, int n, int nblk,
                                                        int round, double* __restrict__ Vp,
                                                        int* __restrict__ skip, int* __restrict__ nrot,
                                                        const double* __restrict__ fro, double tol_rel,
                                                        int max_inner) {
-    __shared__ PairLds L;
+    __shared__ PairLds<NP> L;
     __shared__ int any;
     const int tid = threadIdx.x;
     const int pair = blockIdx.x;
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(1024) void jac_pair_kernel(const double* __restrict
         if (tid == 0) skip[pair] = 1;
         return;
     }
-    lds_jacobi(L, NP, tol_rel, tol_abs, max_inner);
+    lds_jacobi<NP>(L, NP, tol_rel, tol_abs, max_inner);
     double* out = Vp + (long)pair * NP * NP * 2;
     for (int idx = tid; idx < NP * NP; idx += blockDim.x) {
         const int x = idx / NP, y = idx % NP;
@@ -302,6 +305,7 @@ __global__ __launch_bounds__(1024) void jac_pair_kernel(const double* __restrict
 //   Y = op(U) X   (mode 0, op(U) = U^+)   or   Y = X U   (mode 1)
 // with U, X staged in (Ur, Ui), (Xr, Xi).  Each wave owns a 32 x 32 quadrant.
 struct RotLds {
+    static constexpr int LD = NP + 1;
     double Xr[NP][LD];
     double Xi[NP][LD];
     double Ur[NP][LD];
@@ -388,7 +392,7 @@ __device__ void load_rot(RotLds& L, const double* Vp, int pair, int skipped) {
 // One launch per round: blocks [0, m^2) apply H_ab <- V_a^+ H_ab V_b to the 64 x 64 block
 // (rows of pair a) x (columns of pair b); blocks [m^2, m^2 + m * tiles) apply Z <- Z V_b to a
 // 64-row tile of the eigenvector accumulator.  Every block owns the entries it rewrites.
-__global__ __launch_bounds__(256) void jac_rot2_kernel(double* __restrict__ H, int ld, double* __restrict__ Z,
+__global__ __launch_bounds__(64) void jac_rot2_kernel(double* __restrict__ H, int ld, double* __restrict__ Z,
                                                        int ldz, int n, int nblk, int round,
                                                        const double* __restrict__ Vp,
                                                        const int* __restrict__ skip) {
@@ -560,7 +564,7 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
     int* nrot = perm + n;
 
     hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, H, ldh, n, fro);
-    if (n <= NP) {
+    if (n <= NS) {
         if (prof) prof->begin(s, PF_EIG_SMALL);
         hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(1024), 0, s, H, ldh, n, fro, tol_rel, max_sweeps,
                            evals, V, ldv, nrot);
@@ -587,7 +591,7 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
         for (int r = 0; r < nblk - 1; ++r) {
             const double pairs = nblk / 2;
             if (prof) prof->begin(s, PF_EIG_PAIR);
-            hipLaunchKernelGGL(jac_pair_kernel, dim3(nblk / 2), dim3(1024), 0, s, H, ldh, n, nblk, r, Vp, skip,
+            hipLaunchKernelGGL(jac_pair_kernel, dim3(nblk / 2), dim3(256), 0, s, H, ldh, n, nblk, r, Vp, skip,
                                nrot, fro, tol_rel, inner_sweeps);
             // one inner sweep: NP-1 rounds; per round NP/2 rotations (~40 flop each), the 2 x 2
             // block updates of H ((NP/2)^2 blocks, 56 flop) and of V (NP * NP/2 pairs, 14 flop)
@@ -600,7 +604,7 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
             const double rotflop = 8.0 * NP * NP * (double)NP * (2.0 * m * m + (double)m * tiles);
             const double rotbytes = 16.0 * NP * (double)NP * (2.0 * m * m + 2.0 * m * tiles);
             if (prof) prof->begin(s, PF_EIG_ROT);
-            hipLaunchKernelGGL(jac_rot2_kernel, dim3(m * m + m * tiles), dim3(256), 0, s, H, ldh, Z, n, n, nblk,
+            hipLaunchKernelGGL(jac_rot2_kernel, dim3(m * m + m * tiles), dim3(64), 0, s, H, ldh, Z, n, n, nblk,
                                r, Vp, skip);
             if (prof) prof->end(s, PF_EIG_ROT, rotflop, rotbytes);
         }
