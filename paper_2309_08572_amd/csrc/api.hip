@@ -84,7 +84,7 @@ struct Arena {
 template <typename T>
 struct Scratch {
     int nmax = 0;        // largest matrix side handled
-    T *bA, *bB, *bT1, *bQ, *bK, *bC, *bR, *bU, *bB2, *bG, *bZ, *bW, *bVT;
+    T *bA, *bB, *bT1, *bQ, *bK, *bC, *bR, *bU, *bB2, *bG, *bZ, *bW, *bVT, *bQ2, *bK2, *bU2;
     double *Gd, *Vd, *evals, *sig, *inv, *st, *sums, *lvec, *rvec, *tl, *tr, *fac, *pout, *sc, *vtmp, *vtmp2;
     int* cnt;
     void* eigwork;
@@ -92,7 +92,7 @@ struct Scratch {
     static size_t bytes(int nmax) {
         const size_t n2 = (size_t)nmax * nmax * 2;
         size_t b = 0;
-        b += 13 * (n2 * sizeof(T) + 256);
+        b += 16 * (n2 * sizeof(T) + 256);
         b += 2 * (n2 * sizeof(double) + 256);
         b += 14 * ((size_t)nmax * 2 * sizeof(double) + 256) + 4096;
         b += eigh_work_bytes(nmax) + 256;
@@ -113,6 +113,9 @@ struct Scratch {
         bG = a.take<T>(n2);
         bZ = a.take<T>(n2);
         bW = a.take<T>(n2);
+        bQ2 = a.take<T>(n2);
+        bK2 = a.take<T>(n2);
+        bU2 = a.take<T>(n2);
         Gd = a.take<double>(n2);
         Vd = a.take<double>(n2);
         bVT = std::is_same<T, double>::value ? (T*)Vd : a.take<T>(n2);
@@ -320,6 +323,9 @@ struct Engine {
             HIPCHK((geam<double, T>(st, n, n, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));
     }
 
+    // relative eigenvalue noise of a Gram matrix of order n formed in this precision
+    double noise_of(int n) const { return std::max(64.0, 4.0 * n) * eps(); }
+
     // Newton-Schulz: make the n x q columns of Q (view, dense storage in buffer with ld) orthonormal
     void ns_orth(T* Q, long ldq, int n, int q, int iters) {
         for (int it = 0; it < iters; ++it) {
@@ -330,51 +336,59 @@ struct Engine {
         }
     }
 
-    // Orthonormal basis of range(F) for the n x cc view F (two Gram levels).
+    // Orthonormal basis of range(F) for the n x cc view F, up to three Gram levels: level 0
+    // takes the well-conditioned directions (lambda > 1e-10 lambda_max in FP64, 1e-5 in FP32),
+    // each further level the residual F - Q Q^H F down to the cutoff or the residual's rounding
+    // floor, so that F = Q K holds to rounding.
     // Q: n x q written to Qb (ld cc); K = Q^H F: q x cc written to Kb (ld cc).  Uses bT1.
     int orth2(CView<T> F, int n, int cc, T* Qb, T* Kb) {
         const double e = eps();
-        gram_cols(F, n, cc);
-        eig(cc);
-        // level 0: lambda > 1e-10 lambda_max (FP64) / 1e-5 (FP32)
+        const int qmax = std::min(n, cc);
         const double tau0 = std::is_same<T, double>::value ? 1e-10 : 1e-5;
-        HIPCHK(spectrum_cut(st, s.evals, cc, 0, 0.0, 64.0 * e, tau0, cc, s.st, s.cnt, nullptr, s.inv));
-        const int q1 = read_int(s.cnt);
-        if (q1 == 0) return 0;
-        // Q1 = F W diag(lambda^-1/2)
-        gemm(n, q1, cc, C1(), F, V<T>(s.bVT, cc, 1), C0(), V<T>(Qb, cc, 1));
-        HIPCHK(scale_cols<T>(st, V<T>(Qb, cc, 1), n, q1, s.inv));
-        ns_orth(Qb, cc, n, q1, 3);
-        // K1 = Q1^H F
-        gemm(q1, cc, n, C1(), adj(V<T>(Qb, cc, 1)), F, C0(), V<T>(Kb, cc, 1));
-        // residual Fr = F - Q1 K1
-        HIPCHK((geam<T, T>(st, n, cc, C1(), F, C0(), V<T>(s.bT1, cc, 1))));
-        gemm(n, cc, q1, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(Kb, cc, 1), C1(), V<T>(s.bT1, cc, 1));
-        HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums));
-        double sums[2], st0[1];
-        read_doubles(s.sums, 2, sums);
-        read_doubles(s.st, 1, st0);
-        const double lam0 = st0[0];
-        // nothing left above the cutoff: done
-        if (!(sums[0] > c.cutoff * c.cutoff * lam0) || q1 >= n) return q1;
-        CView<T> Fr = V<T>(s.bT1, cc, 1);
-        gram_cols(Fr, n, cc);
-        eig(cc);
-        // level 1: lambda > max(cutoff^2 lambda_max, 4096 eps lambda_max(level))
-        const int cap = std::min(cc, n) - q1;
-        HIPCHK(spectrum_cut(st, s.evals, cc, 1, c.cutoff * c.cutoff, 4096.0 * e, 0.0, cap, s.st, s.cnt, nullptr,
-                            s.inv));
-        const int q2 = read_int(s.cnt);
-        if (q2 <= 0) return q1;
-        T* Q2 = Qb + 2 * q1;   // columns q1.. of Qb
-        gemm(n, q2, cc, C1(), Fr, V<T>(s.bVT, cc, 1), C0(), V<T>(Q2, cc, 1));
-        HIPCHK(scale_cols<T>(st, V<T>(Q2, cc, 1), n, q2, s.inv));
-        // Q2 -= Q1 (Q1^H Q2)
-        gemm(q1, q2, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(Q2, cc, 1), C0(), V<T>(s.bG, q2, 1));
-        gemm(n, q2, q1, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bG, q2, 1), C1(), V<T>(Q2, cc, 1));
-        ns_orth(Q2, cc, n, q2, 3);
-        gemm(q2, cc, n, C1(), adj(V<T>(Q2, cc, 1)), F, C0(), V<T>(Kb + 2 * (long)q1 * cc, cc, 1));
-        return q1 + q2;
+        // deeper levels stop at the residual's rounding floor (8 eps ||F||_F, set after
+        // level 0 as a fraction of lambda_max): content above it is kept so that F = Q K
+        // holds to rounding whatever the later cut of the product
+        double floor2 = 0.0, fro2 = 0.0;
+        CView<T> R = F;
+        int q = 0;
+        for (int lev = 0; lev < 3; ++lev) {
+            gram_cols(R, n, cc);
+            eig(cc);
+            if (lev == 0)
+                HIPCHK(spectrum_cut(st, s.evals, cc, 0, 0.0, noise_of(cc), tau0, qmax, s.st, s.cnt, nullptr, s.inv));
+            else
+                HIPCHK(spectrum_cut(st, s.evals, cc, lev, floor2, 4096.0 * e, 0.0, qmax - q, s.st, s.cnt, nullptr,
+                                    s.inv));
+            const int acc = read_int(s.cnt);
+            if (acc <= 0) break;
+            // new columns R W diag(lambda^-1/2), made orthogonal to the earlier ones
+            T* Qn = Qb + 2 * q;
+            gemm(n, acc, cc, C1(), R, V<T>(s.bVT, cc, 1), C0(), V<T>(Qn, cc, 1));
+            HIPCHK(scale_cols<T>(st, V<T>(Qn, cc, 1), n, acc, s.inv));
+            if (q > 0) {
+                gemm(q, acc, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(Qn, cc, 1), C0(), V<T>(s.bG, acc, 1));
+                gemm(n, acc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Qn, cc, 1));
+            }
+            ns_orth(Qn, cc, n, acc, 3);
+            gemm(acc, cc, n, C1(), adj(V<T>(Qn, cc, 1)), F, C0(), V<T>(Kb + 2 * (long)q * cc, cc, 1));
+            q += acc;
+            if (q >= qmax || lev == 2) break;
+            // residual F - Q K; stop once nothing above the cutoff is left
+            HIPCHK((geam<T, T>(st, n, cc, C1(), F, C0(), V<T>(s.bT1, cc, 1))));
+            gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(Kb, cc, 1), C1(), V<T>(s.bT1, cc, 1));
+            HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums));
+            double sums[2];
+            read_doubles(s.sums, 2, sums);
+            if (lev == 0) {
+                double st5[5];
+                read_doubles(s.st, 5, st5);
+                fro2 = st5[4];
+                floor2 = st5[0] > 0.0 ? 64.0 * e * e * fro2 / st5[0] : 0.0;
+            }
+            if (!(sums[0] > 64.0 * e * e * fro2)) break;
+            R = V<T>(s.bT1, cc, 1);
+        }
+        return q;
     }
 
     // Left split of the a x b view F: U (a x kept) into Ub (ld chi_cap), Schmidt values in
@@ -382,6 +396,7 @@ struct Engine {
     int split_left(CView<T> F, int a, int b, int chi, T* Ub, long ldu, T* Bb) {
         const double e = eps();
         int kacc = 0;
+        double rfloor = 0.0;   // residual rounding floor 8 eps ||F||_F, as a fraction of lambda_max
         CView<T> R = F;
         for (int lev = 0; lev < 3; ++lev) {
             // H = R R^H (a x a)
@@ -393,18 +408,26 @@ struct Engine {
             }
             eig(a);
             const double tau = (lev == 0) ? 1e-4 : 0.0;
-            const double noise = 64.0 * e;
-            HIPCHK(spectrum_cut(st, s.evals, a, lev, c.cutoff * c.cutoff, noise, tau, chi - kacc, s.st, s.cnt,
-                                s.sig + kacc, nullptr));
+            const double noise = noise_of(a);
+            HIPCHK(spectrum_cut(st, s.evals, a, lev, std::max(c.cutoff * c.cutoff, rfloor), noise, tau, chi - kacc,
+                                s.st, s.cnt,
+                                s.sig + kacc, s.inv));
             const int acc = read_int(s.cnt);
             if (acc <= 0) break;
             T* Vn = Ub + 2 * kacc;   // columns kacc.. of U
-            HIPCHK((geam<T, T>(st, a, acc, C1(), V<T>(s.bVT, a, 1), C0(), V<T>(Vn, ldu, 1))));
+            // Eigenvectors of R R^H lean out of range(R) by about eps lambda_max / lambda_j; the
+            // next residual would carry that lean as directions of size eps sigma_max^2 / sigma_j
+            // and the cut would keep them as spurious Schmidt values.  One pass
+            // V <- R (R^H V) diag(1/lambda) puts the columns back into range(R) to rounding.
+            gemm(b, acc, a, C1(), adj(R), V<T>(s.bVT, a, 1), C0(), V<T>(s.bT1, acc, 1));
+            HIPCHK(scale_cols<T>(st, V<T>(s.bT1, acc, 1), b, acc, s.inv));
+            gemm(a, acc, b, C1(), R, V<T>(s.bT1, acc, 1), C0(), V<T>(Vn, ldu, 1));
+            HIPCHK(scale_cols<T>(st, V<T>(Vn, ldu, 1), a, acc, s.inv));
             if (kacc > 0) {
                 gemm(kacc, acc, a, C1(), adj(V<T>(Ub, ldu, 1)), V<T>(Vn, ldu, 1), C0(), V<T>(s.bG, acc, 1));
                 gemm(a, acc, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Vn, ldu, 1));
-                ns_orth(Vn, ldu, a, acc, 3);
             }
+            ns_orth(Vn, ldu, a, acc, 3);
             kacc += acc;
             if (kacc >= chi || kacc >= a || lev == 2) break;
             // residual R = F - U (U^H F)
@@ -412,15 +435,37 @@ struct Engine {
             HIPCHK((geam<T, T>(st, a, b, C1(), F, C0(), V<T>(s.bR, b, 1))));
             gemm(a, b, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(Bb, b, 1), C1(), V<T>(s.bR, b, 1));
             HIPCHK(sumsq<T>(st, V<T>(s.bR, b, 1), a, b, s.sums));
-            double sums[2], st0[1];
+            double sums[2], st5[5];
             read_doubles(s.sums, 2, sums);
-            read_doubles(s.st, 1, st0);
-            if (!(sums[0] > c.cutoff * c.cutoff * st0[0])) break;
+            read_doubles(s.st, 5, st5);
+            // the residual R = F - U U^H F carries rounding of about eps ||F||_F: values below
+            // 8 eps ||F||_F are not spectrum
+            if (lev == 0 && st5[0] > 0.0) rfloor = 64.0 * e * e * st5[4] / st5[0];
+            if (!(sums[0] > std::max(c.cutoff * c.cutoff, rfloor) * st5[0])) break;
             R = V<T>(s.bR, b, 1);
         }
         if (kacc == 0) return 0;
         gemm(kacc, b, a, C1(), adj(V<T>(Ub, ldu, 1)), F, C0(), V<T>(Bb, b, 1));
         return kacc;
+    }
+
+    // Left singular vectors of the a x b view F without an eigenproblem larger than
+    // min(a, b): a tall F is first compressed to an orthonormal basis Q of its range
+    // (Gram of the short side), F = Q K, and the split runs on the q x b core K.
+    // U (a x kept) -> Uout (ld kept), B = U^H F (kept x b) -> s.bB2, values in s.sig.
+    int svd_left(CView<T> F, int a, int b, int chi, T* Uout) {
+        if (a > b) {
+            const int q = orth2(F, a, b, s.bQ2, s.bK2);
+            if (q <= 0) return 0;
+            const int kept = split_left(V<T>(s.bK2, b, 1), q, b, chi, s.bU, c.chi, s.bB2);
+            if (kept <= 0) return 0;
+            gemm(a, kept, q, C1(), V<T>(s.bQ2, b, 1), V<T>(s.bU, c.chi, 1), C0(), V<T>(Uout, kept, 1));
+            return kept;
+        }
+        const int kept = split_left(F, a, b, chi, s.bU, c.chi, s.bB2);
+        if (kept > 0)
+            HIPCHK((geam<T, T>(st, a, kept, C1(), V<T>(s.bU, c.chi, 1), C0(), V<T>(Uout, kept, 1))));
+        return kept;
     }
 
     // ------------------------------------------------------------ trace vectors
@@ -515,8 +560,6 @@ struct Engine {
         const int nb = dir > 0 ? nR : nL;
         const int r = gf ? gf->r : 0;
         const bool factored = gf && r <= MAX_FACTOR_RANK && (long)r * cm < (long)na;
-        T* Ut = s.bU;        // a-side isometry before placement (ld = chi cap)
-        const long ldu = c.chi;
         int kept = 0;
         double tr_re = 0.0, tr_im = 0.0, n2 = 0.0;
         T* Left = nullptr;   // new site i  (nL x kept), unscaled
@@ -548,14 +591,14 @@ struct Engine {
             read_doubles(s.sums, 2, sums);
             if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
             n2 = sums[0];
-            kept = split_left(V<T>(s.bC, nb, 1), q, nb, chi, Ut, ldu, s.bB2);
+            kept = svd_left(V<T>(s.bC, nb, 1), q, nb, chi, s.bU2);
             if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
             if (dir > 0) {
-                gemm(nL, kept, q, C1(), V<T>(s.bQ, k, 1), V<T>(Ut, ldu, 1), C0(), V<T>(outL, kept, 1));
+                gemm(nL, kept, q, C1(), V<T>(s.bQ, k, 1), V<T>(s.bU2, kept, 1), C0(), V<T>(outL, kept, 1));
                 HIPCHK((geam<T, T>(st, kept, nR, C1(), V<T>(s.bB2, nR, 1), C0(), V<T>(outR, nR, 1))));
             } else {
                 // new site i+1 = U^H = Uc^H Q^H ; new site i = B^H
-                gemm(kept, nR, q, C1(), adj(V<T>(Ut, ldu, 1)), adj(V<T>(s.bQ, k, 1)), C0(), V<T>(outR, nR, 1));
+                gemm(kept, nR, q, C1(), adj(V<T>(s.bU2, kept, 1)), adj(V<T>(s.bQ, k, 1)), C0(), V<T>(outR, nR, 1));
                 HIPCHK((geam<T, T>(st, nL, kept, C1(), adj(V<T>(s.bB2, nL, 1)), C0(), V<T>(outL, kept, 1))));
             }
         } else {
@@ -573,13 +616,13 @@ struct Engine {
             if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
             n2 = sums[0];
             CView<T> Fa = dir > 0 ? Th : adj(Th);
-            kept = split_left(Fa, na, nb, chi, Ut, ldu, s.bB2);
+            kept = svd_left(Fa, na, nb, chi, s.bU2);
             if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
             if (dir > 0) {
-                HIPCHK((geam<T, T>(st, nL, kept, C1(), V<T>(Ut, ldu, 1), C0(), V<T>(outL, kept, 1))));
+                HIPCHK((geam<T, T>(st, nL, kept, C1(), V<T>(s.bU2, kept, 1), C0(), V<T>(outL, kept, 1))));
                 HIPCHK((geam<T, T>(st, kept, nR, C1(), V<T>(s.bB2, nR, 1), C0(), V<T>(outR, nR, 1))));
             } else {
-                HIPCHK((geam<T, T>(st, kept, nR, C1(), adj(V<T>(Ut, ldu, 1)), C0(), V<T>(outR, nR, 1))));
+                HIPCHK((geam<T, T>(st, kept, nR, C1(), adj(V<T>(s.bU2, kept, 1)), C0(), V<T>(outR, nR, 1))));
                 HIPCHK((geam<T, T>(st, nL, kept, C1(), adj(V<T>(s.bB2, nL, 1)), C0(), V<T>(outL, kept, 1))));
             }
         }

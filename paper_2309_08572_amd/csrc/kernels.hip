@@ -230,6 +230,8 @@ __global__ void sumsq_kernel(CView<T> X, int M, int N, double* __restrict__ out)
 // Accept the eigenvalues of one level of the split.  lam: descending eigenvalues of the
 // level's Gram matrix.  st (device, FP64):
 //   st[0] = largest eigenvalue of the first level (set when level == 0)
+//   st[1 + level] = the level's acceptance threshold
+//   st[4] = sum of the first level's non-negative eigenvalues (set when level == 0)
 // Accepted: lam_j > max(floor2 * st[0], noise * lam_0, tau * lam_0) and j < cap.
 // Writes cnt[0] = accepted count, sig[j] = sqrt(lam_j) for accepted j, and
 // inv[j] = 1/sqrt(lam_j) (used to normalise orthonormal-basis columns).
@@ -240,7 +242,13 @@ __global__ void spectrum_cut_kernel(const double* __restrict__ lam, int n, int l
     __shared__ int c;
     if (threadIdx.x == 0) {
         const double l0 = n > 0 ? lam[0] : 0.0;
-        if (level == 0) st[0] = l0;
+        if (level == 0) {
+            // st[4]: sum of the non-negative eigenvalues = squared Frobenius norm of the factor
+            double tot = 0.0;
+            for (int j = 0; j < n; ++j) tot += lam[j] > 0.0 ? lam[j] : 0.0;
+            st[0] = l0;
+            st[4] = tot;
+        }
         double t = floor2 * st[0];
         if (noise * l0 > t) t = noise * l0;
         if (tau * l0 > t) t = tau * l0;

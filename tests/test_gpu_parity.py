@@ -85,14 +85,7 @@ def test_truncating_fp64(seed):
             assert abs(x["xi_after"] - x["xi_before"]) <= 1e-9 * abs(x["xi_before"])
 
 
-@pytest.mark.parametrize("seed", [
-    0,
-    pytest.param(1, marks=pytest.mark.xfail(
-        strict=False,
-        reason="FP32 theta/Gram products cannot resolve Schmidt values below ~1e-7 sigma_1; "
-               "in this circuit five of them carry ~5e-4 of the trace (bond 21 -> 16), so the "
-               "per-site energy misses 1e-5 by ~1.9e-4 (reproduced by a numpy emulation)")),
-])
+@pytest.mark.parametrize("seed", [0, 1])
 def test_m1_shape_fp32(seed):
     circuits, mpdo = _gpu()
     spec = config_m1(seed, n=16)
@@ -100,8 +93,11 @@ def test_m1_shape_fp32(seed):
     o, _ = _oracle_obs(spec)
     m = circuits.run_circuit(spec, precision=mpdo.MPDO_FP32)
     g = circuits.observables(m)
-    assert abs(g["energy_per_site"] - o["energy_per_site"]) <= FP32_ABS
-    np.testing.assert_allclose(g["populations"], o["populations"], rtol=0, atol=FP32_ABS)
+    de = abs(g["energy_per_site"] - o["energy_per_site"])
+    dp = float(np.max(np.abs(g["populations"] - o["populations"])))
+    print(f"[gpu] fp32 energy err {de:.2e} population err {dp:.2e}", flush=True)
+    assert de <= FP32_ABS
+    assert dp <= FP32_ABS
 
 
 def test_single_atom_closed_forms():
