@@ -71,6 +71,26 @@ def _cpu_baseline(spec, budget_s: float) -> dict:
     }
 
 
+def _batch(count: int, workers: int) -> dict:
+    """Circuits of the batch workload (N in [20,100], chi in {64,128,256}, p in {1,2,3},
+    d=4, log-uniform noise): all at once on worker streams vs one at a time."""
+    from paper_2309_08572_amd import circuits, mpdo
+    from workloads import config_m2_batch
+    specs = config_m2_batch(0)[:count]
+    descs = [circuits.describe(s) for s in specs]
+    updates = sum(s.n_two_site_updates() for s in specs)
+    t0 = time.perf_counter()
+    mpdo.run_batch(descs, n_workers=1)
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = mpdo.run_batch(descs, n_workers=workers)
+    t_par = time.perf_counter() - t0
+    return {"circuits": count, "workers": workers, "two_site_updates": updates,
+            "updates_per_s_batched": updates / t_par, "updates_per_s_one_at_a_time": updates / t_seq,
+            "speedup": t_seq / t_par,
+            "max_bond": max(max(r["bonds"]) for r in res)}
+
+
 PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp64_vector": 78.6, "hbm_gbs": 8000.0}
 
 
@@ -110,6 +130,10 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "fp32", "both"], default="both")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-circuits", type=int, default=0,
+                    help="also time this many circuits of the 256-circuit batch workload "
+                         "(one per worker stream vs one at a time)")
+    ap.add_argument("--workers", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
@@ -182,6 +206,8 @@ def main() -> int:
     out["observables"] = {"energy_per_site": r["obs"]["energy_per_site"],
                           "p_success": r["obs"]["p_success"],
                           "trace": [r["obs"]["trace"].real, r["obs"]["trace"].imag]}
+    if args.batch_circuits > 0:
+        out["batch"] = _batch(args.batch_circuits, args.workers)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(spec, args.cpu_baseline_seconds)
     print(json.dumps(out))

@@ -145,6 +145,44 @@ mpdo_status mpdo_bond_dims(mpdo_ctx ctx, int* out);
  * applied); shape[0..2] receives its dimensions.  out may be NULL to query the shape. */
 mpdo_status mpdo_get_site(mpdo_ctx ctx, int site, double* out, int* shape);
 
+/* ---------------------------------------------------------------- batches of circuits
+ * Many independent circuits (QAOA angle sets x noise rates, of uneven N and chi): each is
+ * an ordered list of Kraus maps applied to a product state, then linear observables.
+ * Circuits share nothing, so they run concurrently (Sec. IV studies sweep parameters as
+ * independent simulations). */
+typedef struct {
+    int n_sites, d, chi_max, precision, ppt;
+    int n_ops;
+    const int* op_kind;        /* per operation: 0 = two-atom map on (site, site+1), 1 = one atom */
+    const int* op_site;
+    const int* op_set;         /* index of its Kraus set                                         */
+    const int* set_count;      /* operators in each set                                          */
+    const long* set_offset;    /* offset of each set in kraus, in complex numbers               */
+    const double* kraus;       /* complex operators, d^2 x d^2 (two-atom) or d x d (one atom)   */
+    const double* rho0;        /* n_sites * d * d complex: the initial product state            */
+    int n_terms;               /* observables as in mpdo_expect, normalised by tr(rho)          */
+    const int* term_first;
+    const int* term_len;
+    const double* term_ops;
+    double* out;               /* 2 * n_terms: re, im                                            */
+    double* out_trace;         /* 2: tr(rho)                                                     */
+    int* out_bonds;            /* n_sites - 1 final bond dimensions (may be NULL)               */
+    int status;                /* set by mpdo_run_batch: mpdo_status of this circuit            */
+    double seconds;            /* set by mpdo_run_batch: wall time of this circuit on its worker */
+} mpdo_circuit;
+
+/* Device bytes one worker needs to run any circuit of the batch (the largest circuit). */
+size_t mpdo_batch_workspace_bytes(const mpdo_circuit* circuits, int n_circuits);
+
+/* Run n_circuits circuits on n_workers host threads, each with its own HIP stream and
+ * context (default stream priority), taking circuits from a shared queue; the kernels of
+ * different circuits overlap on the GPU.  device_workspace: NULL (the library allocates
+ * n_workers * mpdo_batch_workspace_bytes with hipMalloc) or a caller buffer of at least
+ * that size.  Per-circuit failures are reported in circuits[i].status; the call returns
+ * MPDO_E_ARG for bad arguments and otherwise the first failing circuit's status. */
+mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers, void* device_workspace,
+                           size_t workspace_bytes);
+
 /* Kernel families reported by mpdo_profile_read, in this order. */
 enum {
     MPDO_PROF_GEMM = 0,        /* complex matrix-core GEMM (theta, Gram, projections, rebuild) */

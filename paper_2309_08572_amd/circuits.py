@@ -124,3 +124,57 @@ def observables(m: MPDO, g: float = 1.0) -> dict:
     popv = vals[nzz + n:nzz + n + n * d].real.reshape(n, d)
     return {"trace": m.trace(), "energy_per_site": energy / n, "populations": popv,
             "p_success": float(vals[-1].real)}
+
+
+def observable_terms(n: int, d: int):
+    """Energy terms (ZZ bonds, X sites), per-atom populations and the all-qubit projector."""
+    Z = np.zeros((d, d), dtype=np.complex128)
+    Z[0, 0], Z[1, 1] = 1.0, -1.0
+    X = np.zeros((d, d), dtype=np.complex128)
+    X[0, 1] = X[1, 0] = 1.0
+    terms = [(i, [Z, Z]) for i in range(n - 1)] + [(i, [X]) for i in range(n)]
+    terms += [(j, [_e(d, a, a)]) for j in range(n) for a in range(d)]
+    terms += [(0, [_e(d, 0, 0) + _e(d, 1, 1)] * n)]
+    return terms
+
+
+def summarize(values: np.ndarray, n: int, d: int, g: float = 1.0) -> dict:
+    """Energy per site, populations and success probability from observable_terms values."""
+    nzz = n - 1
+    energy = -np.sum(values[:nzz]).real - g * np.sum(values[nzz:nzz + n]).real
+    pops = values[nzz + n:nzz + n + n * d].real.reshape(n, d)
+    return {"energy_per_site": energy / n, "populations": pops, "p_success": float(values[-1].real)}
+
+
+def describe(spec, precision: int = MPDO_FP64, chi: Optional[int] = None, ppt: bool = True) -> dict:
+    """The circuit of run_circuit as flat arrays for mpdo_run_batch."""
+    n, d = spec.n, spec.d
+    sets = []
+    kind, site, which = [], [], []
+    for k in range(spec.p):
+        base = len(sets)
+        sets += [block_kraus(spec.gamma[k], spec.p_leak, d), [x_rotation(spec.beta[k], d)],
+                 dephasing_kraus(spec.p_deph, d), decay_kraus(spec.p_decay, d)]
+        for i in bond_order(n):
+            kind.append(0)
+            site.append(i)
+            which.append(base)
+        for j in range(n):
+            for q in (1, 2, 3):
+                kind.append(1)
+                site.append(j)
+                which.append(base + q)
+    counts = [len(s_) for s_ in sets]
+    offs, flat, pos = [], [], 0
+    for s_ in sets:
+        offs.append(pos)
+        for K in s_:
+            flat.append(np.asarray(K, dtype=np.complex128).reshape(-1))
+            pos += K.size
+    terms = observable_terms(n, d)
+    return {"n": n, "d": d, "chi": spec.chi if chi is None else chi, "precision": precision,
+            "ppt": ppt, "op_kind": kind, "op_site": site, "op_set": which, "set_count": counts,
+            "set_offset": offs, "kraus": np.concatenate(flat),
+            "rho0": np.stack([plus_rho(d)] * n), "term_first": [t[0] for t in terms],
+            "term_len": [len(t[1]) for t in terms],
+            "term_ops": np.concatenate([np.stack(t[1]).reshape(-1) for t in terms])}

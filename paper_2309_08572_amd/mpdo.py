@@ -25,7 +25,7 @@ EXPORTS = (
     "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus",
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
-    "mpdo_profile_enable", "mpdo_profile_read",
+    "mpdo_profile_enable", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
 )
 
 PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other")
@@ -48,6 +48,18 @@ class TruncInfo(C.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Circuit(C.Structure):
+    _fields_ = [("n_sites", C.c_int), ("d", C.c_int), ("chi_max", C.c_int), ("precision", C.c_int),
+                ("ppt", C.c_int), ("n_ops", C.c_int), ("op_kind", C.POINTER(C.c_int)),
+                ("op_site", C.POINTER(C.c_int)), ("op_set", C.POINTER(C.c_int)),
+                ("set_count", C.POINTER(C.c_int)), ("set_offset", C.POINTER(C.c_long)),
+                ("kraus", C.POINTER(C.c_double)), ("rho0", C.POINTER(C.c_double)),
+                ("n_terms", C.c_int), ("term_first", C.POINTER(C.c_int)),
+                ("term_len", C.POINTER(C.c_int)), ("term_ops", C.POINTER(C.c_double)),
+                ("out", C.POINTER(C.c_double)), ("out_trace", C.POINTER(C.c_double)),
+                ("out_bonds", C.POINTER(C.c_int)), ("status", C.c_int), ("seconds", C.c_double)]
 
 
 class MpdoError(RuntimeError):
@@ -93,9 +105,13 @@ def load_library() -> C.CDLL:
     lib.mpdo_last_error.restype = C.c_char_p
     lib.mpdo_version.restype = C.c_char_p
     lib.mpdo_profile_enable.argtypes = [ctx, C.c_int]
+    lib.mpdo_batch_workspace_bytes.argtypes = [C.POINTER(Circuit), C.c_int]
+    lib.mpdo_batch_workspace_bytes.restype = C.c_size_t
+    lib.mpdo_run_batch.argtypes = [C.POINTER(Circuit), C.c_int, C.c_int, C.c_void_p, C.c_size_t]
     lib.mpdo_profile_read.argtypes = [ctx, dp, C.c_int]
     for name in EXPORTS:
-        if name not in ("mpdo_workspace_bytes", "mpdo_last_error", "mpdo_version"):
+        if name not in ("mpdo_workspace_bytes", "mpdo_last_error", "mpdo_version",
+                        "mpdo_batch_workspace_bytes"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -226,3 +242,65 @@ class MPDO:
 
     def synchronize(self):
         self._check(self.lib.mpdo_synchronize(self.ctx))
+
+
+def run_batch(descs, n_workers: int = 8, device: int = 0):
+    """Run circuit descriptions (dicts from circuits.describe) through mpdo_run_batch.
+
+    Returns one dict per circuit: observables (complex array), trace, bonds, status,
+    seconds.  The device workspace comes from torch."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libmpdo needs a visible GPU; no CPU fallback exists")
+    lib = load_library()
+    n = len(descs)
+    arr = (Circuit * n)()
+    keep = []
+    outs = []
+    ip = C.POINTER(C.c_int)
+
+    def iptr(a):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        keep.append(a)
+        return a.ctypes.data_as(ip)
+
+    for i, dsc in enumerate(descs):
+        c = arr[i]
+        c.n_sites, c.d, c.chi_max = dsc["n"], dsc["d"], dsc["chi"]
+        c.precision, c.ppt = dsc.get("precision", MPDO_FP64), int(dsc.get("ppt", True))
+        c.n_ops = len(dsc["op_kind"])
+        c.op_kind, c.op_site, c.op_set = iptr(dsc["op_kind"]), iptr(dsc["op_site"]), iptr(dsc["op_set"])
+        c.set_count = iptr(dsc["set_count"])
+        off = np.ascontiguousarray(dsc["set_offset"], dtype=np.int64)
+        keep.append(off)
+        c.set_offset = off.ctypes.data_as(C.POINTER(C.c_long))
+        kr = _cplx(dsc["kraus"])
+        rho = _cplx(dsc["rho0"])
+        tops = _cplx(dsc["term_ops"])
+        keep.extend([kr, rho, tops])
+        c.kraus, c.rho0, c.term_ops = _dptr(kr), _dptr(rho), _dptr(tops)
+        c.n_terms = len(dsc["term_first"])
+        c.term_first, c.term_len = iptr(dsc["term_first"]), iptr(dsc["term_len"])
+        out = np.zeros(2 * c.n_terms)
+        tr = np.zeros(2)
+        bonds = np.zeros(dsc["n"] - 1, dtype=np.int32)
+        keep.extend([out, tr, bonds])
+        c.out, c.out_trace = _dptr(out), _dptr(tr)
+        c.out_bonds = bonds.ctypes.data_as(ip)
+        outs.append((out, tr, bonds))
+    per = lib.mpdo_batch_workspace_bytes(arr, n)
+    workers = max(1, min(n_workers, n))
+    ws = torch.empty(per * workers, dtype=torch.uint8, device=torch.device("cuda", device))
+    torch.cuda.synchronize()
+    status = lib.mpdo_run_batch(arr, n, workers, C.c_void_p(ws.data_ptr()), per * workers)
+    res = []
+    for i in range(n):
+        out, tr, bonds = outs[i]
+        res.append({"values": out[0::2] + 1j * out[1::2], "trace": complex(tr[0], tr[1]),
+                    "bonds": [int(b) for b in bonds], "status": int(arr[i].status),
+                    "seconds": float(arr[i].seconds)})
+    del ws
+    if status != 0:
+        bad = [i for i in range(n) if arr[i].status != 0]
+        raise MpdoError(status, f"batch circuits failed: {bad[:8]}")
+    return res
