@@ -186,13 +186,16 @@ mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers
 /* Kernel families reported by mpdo_profile_read, in this order. */
 enum {
     MPDO_PROF_GEMM = 0,        /* complex matrix-core GEMM (theta, Gram, projections, rebuild) */
-    MPDO_PROF_EIG_PAIR = 1,    /* Jacobi: 64 x 64 pair eigenproblems in LDS                    */
+    MPDO_PROF_EIG_PAIR = 1,    /* Jacobi: 32 x 32 pair eigenproblems in LDS                    */
     MPDO_PROF_EIG_ROTATE = 2,  /* Jacobi: pair rotations applied to block rows and columns     */
     MPDO_PROF_EIG_SMALL = 3,   /* Jacobi: whole matrix of order <= 64 in one workgroup         */
     MPDO_PROF_PHYS = 4,        /* gate factors applied to the physical index of a site         */
     MPDO_PROF_TRANSFER = 5,    /* transfer-matrix steps of trace / expectation vectors         */
     MPDO_PROF_OTHER = 6,
-    MPDO_PROF_FAMILIES = 7
+    MPDO_PROF_TRI_REDUCE = 7,  /* Householder reduction to tridiagonal form (one workgroup)    */
+    MPDO_PROF_TRI_SOLVE = 8,   /* bisection + inverse iteration for the accepted eigenpairs    */
+    MPDO_PROF_TRI_BACK = 9,    /* back-transformation of the accepted eigenvectors             */
+    MPDO_PROF_FAMILIES = 10
 };
 
 /* Measurement switch (instrumentation, not part of the method): with enable = 1 the

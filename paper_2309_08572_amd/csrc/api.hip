@@ -28,6 +28,7 @@
 #include "../../include/mpdo.h"
 #include "common.h"
 #include "eig.h"
+#include "tri.h"
 #include "gemm.h"
 #include "kernels.h"
 
@@ -323,6 +324,27 @@ struct Engine {
             HIPCHK((geam<double, T>(st, n, n, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));
     }
 
+    // Eigenpairs of the Gram in s.Gd (order n) that a deflation level accepts (the rule of
+    // spectrum_cut): returns the accepted count; s.sig/s.inv style outputs go to sig/inv, the
+    // eigenvectors to columns [0, count) of s.Vd (ld n) and s.bVT.  Orders 65..TRI_MAX use the
+    // tridiagonal solver, which computes only the accepted pairs; the others the Jacobi solver.
+    int eig_cut(int n, int level, double floor2, double noise, double tau, int cap, double* sig, double* inv) {
+        int acc;
+        if (n > 64 && n <= TRI_MAX) {
+            HIPCHK(eigh_top(st, n, s.Gd, n, level, floor2, noise, tau, cap, s.st, s.cnt, s.evals, sig, inv, s.Vd, n,
+                            s.eigwork, ps()));
+            ++eig_calls;
+            acc = read_int(s.cnt);
+            if (!std::is_same<T, double>::value && acc > 0)
+                HIPCHK((geam<double, T>(st, n, acc, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));
+        } else {
+            eig(n);
+            HIPCHK(spectrum_cut(st, s.evals, n, level, floor2, noise, tau, cap, s.st, s.cnt, sig, inv));
+            acc = read_int(s.cnt);
+        }
+        return acc;
+    }
+
     // relative eigenvalue noise of a Gram matrix of order n formed in this precision
     double noise_of(int n) const { return std::max(64.0, 4.0 * n) * eps(); }
 
@@ -353,13 +375,8 @@ struct Engine {
         int q = 0;
         for (int lev = 0; lev < 3; ++lev) {
             gram_cols(R, n, cc);
-            eig(cc);
-            if (lev == 0)
-                HIPCHK(spectrum_cut(st, s.evals, cc, 0, 0.0, noise_of(cc), tau0, qmax, s.st, s.cnt, nullptr, s.inv));
-            else
-                HIPCHK(spectrum_cut(st, s.evals, cc, lev, floor2, 4096.0 * e, 0.0, qmax - q, s.st, s.cnt, nullptr,
-                                    s.inv));
-            const int acc = read_int(s.cnt);
+            const int acc = lev == 0 ? eig_cut(cc, 0, 0.0, noise_of(cc), tau0, qmax, nullptr, s.inv)
+                                     : eig_cut(cc, lev, floor2, 4096.0 * e, 0.0, qmax - q, nullptr, s.inv);
             if (acc <= 0) break;
             // new columns R W diag(lambda^-1/2), made orthogonal to the earlier ones
             T* Qn = Qb + 2 * q;
@@ -406,13 +423,9 @@ struct Engine {
                 gemm(a, a, b, C1(), R, adj(R), C0(), V<T>(s.bG, a, 1));
                 HIPCHK((geam<T, double>(st, a, a, C1(), V<T>(s.bG, a, 1), C0(), V<double>(s.Gd, a, 1))));
             }
-            eig(a);
             const double tau = (lev == 0) ? 1e-4 : 0.0;
-            const double noise = noise_of(a);
-            HIPCHK(spectrum_cut(st, s.evals, a, lev, std::max(c.cutoff * c.cutoff, rfloor), noise, tau, chi - kacc,
-                                s.st, s.cnt,
-                                s.sig + kacc, s.inv));
-            const int acc = read_int(s.cnt);
+            const int acc = eig_cut(a, lev, std::max(c.cutoff * c.cutoff, rfloor), noise_of(a), tau, chi - kacc,
+                                    s.sig + kacc, s.inv);
             if (acc <= 0) break;
             T* Vn = Ub + 2 * kacc;   // columns kacc.. of U
             // Eigenvectors of R R^H lean out of range(R) by about eps lambda_max / lambda_j; the

@@ -53,7 +53,8 @@ struct cd {
 
 // Kernel families timed by the profiling sink.
 enum ProfFamily { PF_GEMM = 0, PF_EIG_PAIR = 1, PF_EIG_ROT = 2, PF_EIG_SMALL = 3, PF_PHYS = 4,
-                  PF_TRANSFER = 5, PF_OTHER = 6, PF_COUNT = 7 };
+                  PF_TRANSFER = 5, PF_OTHER = 6, PF_TRI_REDUCE = 7, PF_TRI_SOLVE = 8, PF_TRI_BACK = 9,
+                  PF_COUNT = 10 };
 
 // Receives begin/end marks around kernel launches when measurement is on (else null).
 struct ProfSink {

@@ -15,6 +15,7 @@
 
 #include "common.h"
 #include "eig.h"
+#include "tri.h"
 
 namespace mpdo {
 
@@ -544,7 +545,9 @@ size_t eigh_work_bytes(int n) {
     b += (size_t)n * n * 2 * sizeof(double);                  // accumulated eigenvectors
     b += 64 * sizeof(double);                                  // norms
     b += (size_t)(nblk / 2 + n + 64) * sizeof(int);            // skip flags, perm, counters
-    return b + 1024;
+    // the tridiagonal solver (orders 65..TRI_MAX) uses the same scratch at other times
+    const size_t bt = tri_work_bytes(n < TRI_MAX ? n : TRI_MAX);
+    return (b > bt ? b : bt) + 1024;
 }
 
 hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, double* evals, void* work,

@@ -1,0 +1,953 @@
+// Hermitian eigensolver for Gram matrices of order 65..TRI_MAX in FP64 (gfx950), restricted to
+// the eigenpairs one deflation level of the split accepts.
+//
+//   tri_reduce_kernel  one workgroup: Householder reduction H = Q T Q^H to a real symmetric
+//                      tridiagonal T (complex reflectors chosen so the off-diagonal is real);
+//                      the reflectors are copied to contiguous rows for the back-transform
+//   tri_top_kernel     one wave: the largest eigenvalue by multisection of Sturm counts, the
+//                      level's threshold and the number m of accepted eigenvalues
+//   tri_eval_kernel    one wave per accepted eigenvalue: multisection (64 shifts per pass)
+//   tri_vec_kernel     one wave per accepted eigenvalue: inverse iteration on T, factors in LDS
+//   tri_mgs_kernel     modified Gram-Schmidt inside clusters of eigenvalues closer than
+//                      1e-12 ||T|| (one wave per cluster)
+//   tri_back_kernel    independent workgroups of 8 columns: V = Q Z for the m vectors
+//
+// Grids are sized for the cap on the host and exit early past the accepted count, which lives
+// on the device, so the launches need no host synchronisation.
+#include <float.h>
+#include <math.h>
+
+#include "common.h"
+#include "tri.h"
+
+namespace mpdo {
+
+namespace {
+
+constexpr int TB = 1024;      // threads of the one-workgroup kernels
+constexpr int NW = TB / 64;   // waves
+constexpr int BK_COLS = 8;    // columns per back-transform workgroup
+constexpr int BK_THREADS = 256;
+constexpr double EPS = 2.220446049250313e-16;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// sums of a and b over a workgroup of NWV waves, returned to every thread (red: 2 * NWV doubles)
+template <int NWV = NW>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    for (int k = 0; k < NWV; ++k) {
+        sa += red[2 * k];
+        sb += red[2 * k + 1];
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
+// max of a and min of b over the workgroup
+__device__ __forceinline__ void block_maxmin(double& a, double& b, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a = fmax(a, __shfl_xor(a, o, 64));
+        b = fmin(b, __shfl_xor(b, o, 64));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    double sa = red[0], sb = red[1];
+    for (int k = 1; k < NW; ++k) {
+        sa = fmax(sa, red[2 * k]);
+        sb = fmin(sb, red[2 * k + 1]);
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
+// ------------------------------------------------------------------ reduction
+// H (n x n complex, row-major, leading dimension ld) is overwritten.  Outputs: dg[0..n) and
+// off[0..n-1) (T), tau[j] (complex) and refl row j = v_j (length n-1-j, v_j[0] = 1) of
+// H_j = I - tau_j v_j v_j^H acting on rows j+1..n-1, so that H = H_0 ... H_{n-2} T (...)^H;
+// trace[0] = sum of the diagonal of H.
+__global__ __launch_bounds__(TB) void tri_reduce_kernel(double* __restrict__ H, int ld, int n,
+                                                        double* __restrict__ dg, double* __restrict__ off,
+                                                        double* __restrict__ tau, double* __restrict__ refl,
+                                                        double* __restrict__ trace) {
+    __shared__ double v[2 * TRI_MAX];
+    __shared__ double p[2 * TRI_MAX];
+    __shared__ double red[2 * NW];
+    __shared__ double sc[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+    // Hermitian part (average of the two triangles, real diagonal) and the trace
+    {
+        double tr = 0.0, unused = 0.0;
+        for (int x = w; x < n; x += NW)
+            for (int y = lane; y < n; y += 64) {
+                double* a = H + 2 * ((long)x * ld + y);
+                if (x < y) {
+                    double* b = H + 2 * ((long)y * ld + x);
+                    const double r = 0.5 * (a[0] + b[0]), im = 0.5 * (a[1] - b[1]);
+                    a[0] = r;
+                    a[1] = im;
+                    b[0] = r;
+                    b[1] = -im;
+                } else if (x == y) {
+                    a[1] = 0.0;
+                    tr += a[0];
+                }
+            }
+        block_sum2(tr, unused, red);
+        if (tid == 0) trace[0] = tr;
+    }
+
+    for (int j = 0; j < n - 1; ++j) {
+        const int m = n - j - 1;
+        // x = column j below the diagonal
+        double x2 = 0.0, unused = 0.0;
+        for (int i = tid; i < m; i += TB) {
+            const double* h = H + 2 * ((long)(j + 1 + i) * ld + j);
+            v[2 * i] = h[0];
+            v[2 * i + 1] = h[1];
+            if (i > 0) x2 += h[0] * h[0] + h[1] * h[1];
+        }
+        block_sum2(x2, unused, red);
+        if (tid == 0) {
+            const double ar = v[0], ai = v[1];
+            double beta, tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
+            if (x2 == 0.0 && ai == 0.0) {
+                beta = ar;   // already reduced: H_j = I
+            } else {
+                beta = -copysign(sqrt(ar * ar + ai * ai + x2), ar);
+                tr_ = (beta - ar) / beta;
+                ti_ = -ai / beta;
+                const double dr = ar - beta, di = ai, den = dr * dr + di * di;   // 1/(alpha - beta)
+                sr = dr / den;
+                si = -di / den;
+            }
+            sc[0] = tr_;
+            sc[1] = ti_;
+            sc[2] = sr;
+            sc[3] = si;
+            off[j] = beta;
+            tau[2 * j] = tr_;
+            tau[2 * j + 1] = ti_;
+            dg[j] = H[2 * ((long)j * ld + j)];
+        }
+        __syncthreads();
+        const double tr_ = sc[0], ti_ = sc[1], sr = sc[2], si = sc[3];
+        for (int i = tid; i < m; i += TB) {
+            double vr = 1.0, vi = 0.0;
+            if (i > 0) {
+                const double xr = v[2 * i], xi = v[2 * i + 1];
+                vr = xr * sr - xi * si;
+                vi = xr * si + xi * sr;
+            }
+            v[2 * i] = vr;
+            v[2 * i + 1] = vi;
+            refl[2 * ((long)j * n + i)] = vr;
+            refl[2 * ((long)j * n + i) + 1] = vi;
+        }
+        __syncthreads();
+        if (tr_ == 0.0 && ti_ == 0.0) continue;
+        const long base = (long)(j + 1) * ld + (j + 1);
+        // p = tau A22 v: each wave takes four rows at a time (four loads in flight per lane)
+        for (int r0 = 4 * w; r0 < m; r0 += 4 * NW) {
+            double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int c = lane; c < m; c += 64) {
+                const double vr = v[2 * c], vi = v[2 * c + 1];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (r0 + q < m) {
+                        const double* h = H + 2 * (base + (long)(r0 + q) * ld + c);
+                        const double hr = h[0], hi = h[1];
+                        ar[q] += hr * vr - hi * vi;
+                        ai[q] += hr * vi + hi * vr;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double qr = wave_sum(ar[q]), qi = wave_sum(ai[q]);
+                if (lane == 0 && r0 + q < m) {
+                    p[2 * (r0 + q)] = tr_ * qr - ti_ * qi;
+                    p[2 * (r0 + q) + 1] = tr_ * qi + ti_ * qr;
+                }
+            }
+        }
+        __syncthreads();
+        // w = p - (tau/2) (p^H v) v
+        double hr = 0.0, hi = 0.0;
+        for (int i = tid; i < m; i += TB) {
+            const double pr = p[2 * i], pi = p[2 * i + 1], vr = v[2 * i], vi = v[2 * i + 1];
+            hr += pr * vr + pi * vi;
+            hi += pr * vi - pi * vr;
+        }
+        block_sum2(hr, hi, red);
+        const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
+        for (int i = tid; i < m; i += TB) {
+            const double vr = v[2 * i], vi = v[2 * i + 1];
+            p[2 * i] += a2r * vr - a2i * vi;
+            p[2 * i + 1] += a2r * vi + a2i * vr;
+        }
+        __syncthreads();
+        // A22 -= v w^H + w v^H, four rows per wave at a time
+        for (int r0 = 4 * w; r0 < m; r0 += 4 * NW) {
+            for (int c = lane; c < m; c += 64) {
+                const double vcr = v[2 * c], vci = v[2 * c + 1], wcr = p[2 * c], wci = p[2 * c + 1];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = r0 + q;
+                    if (r < m) {
+                        const double vr = v[2 * r], vi = v[2 * r + 1], wr = p[2 * r], wi = p[2 * r + 1];
+                        double* h = H + 2 * (base + (long)r * ld + c);
+                        h[0] -= vr * wcr + vi * wci + wr * vcr + wi * vci;
+                        h[1] -= vi * wcr - vr * wci + wi * vcr - wr * vci;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) dg[n - 1] = H[2 * ((long)(n - 1) * ld + (n - 1))];
+}
+
+// On-chip reduction for orders <= RMAX.  The lower triangle is cut into 8 x 8 tiles (diagonal
+// tiles stored in full); a group of 8 lanes owns RS tiles, lane k row k of each (8 complex
+// values): RS_REG tiles in registers, the rest in LDS, so no matrix element leaves the chip
+// until the reflectors are written.  v and w live in LDS at absolute indices with zeros over
+// the reduced part, so the arithmetic needs no masks.  Per column: Hermitian matvec (row sums
+// in registers, column sums and row totals by LDS f64 atomics), rank-2 update in place.
+constexpr int RB = 512;        // threads: 2 waves per SIMD leave 256 registers per lane
+constexpr int RNW = RB / 64;
+constexpr int RT = 8;
+constexpr int RG = RB / RT;    // 64 tile groups
+constexpr int RS_REG = 3;      // tiles per group in registers
+constexpr int RS_LDS = 2;      // tiles per group in LDS
+constexpr int RS = RS_REG + RS_LDS;
+constexpr int RMAX = 192;      // 24 tile rows: 300 lower tiles <= RG * RS = 320
+static_assert((RMAX / RT) * (RMAX / RT + 1) / 2 <= RG * RS, "tiles of the largest order must fit");
+
+struct RedLds {
+    double tr[RS_LDS][RT][RB];   // LDS tiles, [slot][column][lane]
+    double ti[RS_LDS][RT][RB];
+    double vabs[2 * RMAX];
+    double pabs[2 * RMAX];
+    double red[2 * RNW];
+    double sc[4];
+};
+
+// sum over the 8 lanes of an aligned group, returned to all 8 (DPP: quad xor 1, quad xor 2,
+// then the mirror inside each half-row brings in the other quad; no LDS traffic)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double group8_sum(double x) {
+    x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
+    x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
+    x += dpp_mov<0x141>(x);   // row_half_mirror
+    return x;
+}
+
+__device__ __forceinline__ bool tile_live(int I, int J, int j) {
+    return I >= 0 && RT * I + RT - 1 > j && RT * J + RT - 1 > j;
+}
+
+// column j of the tile row held by this lane -> vabs, and the diagonal entry -> dg[j]
+template <class TileRow>
+__device__ __forceinline__ void tile_extract(const TileRow& x, int I, int J, int j, int k, int n, double* vabs,
+                                             double* dg, double& x2) {
+    if (I < 0 || J != j / RT) return;
+    const int r = RT * I + k, jq = j - RT * (j / RT);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int q = 0; q < RT; ++q)
+        if (q == jq) {
+            a = x.re(q);
+            b = x.im(q);
+        }
+    if (r == j) dg[j] = a;
+    if (r > j && r < n) {
+        vabs[2 * r] = a;
+        vabs[2 * r + 1] = b;
+        if (r > j + 1) x2 += a * a + b * b;
+    }
+}
+
+// Row sums of the tile row stay in the lane; the column contributions of an off-diagonal tile
+// (its mirror image above the diagonal) are summed over the 8 lanes of the group by DPP moves,
+// so that lane k adds column 8J + k: two atomics per lane per tile, none of them to the same
+// address within a group.
+template <class TileRow>
+__device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, const double* vabs, double* pabs) {
+    __builtin_amdgcn_sched_barrier(0);   // keep one tile's operands live at a time
+    const int r = RT * I + k;
+    const double vrr = vabs[2 * r], vri = vabs[2 * r + 1];
+    double rr = 0.0, ri = 0.0, cr = 0.0, ci = 0.0;
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int c = RT * J + q;
+        const double vcr = vabs[2 * c], vci = vabs[2 * c + 1];
+        const double hr = x.re(q), hi = x.im(q);
+        rr += hr * vcr - hi * vci;
+        ri += hr * vci + hi * vcr;
+        if (I != J) {
+            // conj(A_rc) v_r, summed over the group's rows
+            const double a = group8_sum(hr * vrr + hi * vri), b = group8_sum(hr * vri - hi * vrr);
+            if (k == q) {
+                cr = a;
+                ci = b;
+            }
+        }
+    }
+    if (I != J) {
+        atomicAdd(&pabs[2 * (RT * J + k)], cr);
+        atomicAdd(&pabs[2 * (RT * J + k) + 1], ci);
+    }
+    atomicAdd(&pabs[2 * r], rr);
+    atomicAdd(&pabs[2 * r + 1], ri);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// A -= v w^H + w v^H on this lane's tile row (w in pabs)
+template <class TileRow>
+__device__ __forceinline__ void tile_update(TileRow& x, int I, int J, int k, const double* vabs, const double* wabs) {
+    __builtin_amdgcn_sched_barrier(0);
+    const int r = RT * I + k;
+    const double vr = vabs[2 * r], vi = vabs[2 * r + 1], wr = wabs[2 * r], wi = wabs[2 * r + 1];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int c = RT * J + q;
+        const double vcr = vabs[2 * c], vci = vabs[2 * c + 1], wcr = wabs[2 * c], wci = wabs[2 * c + 1];
+        x.set(q, x.re(q) - (vr * wcr + vi * wci + wr * vcr + wi * vci),
+              x.im(q) - (vi * wcr - vr * wci + wi * vcr - wr * vci));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// a lane's row of one tile: in registers, or in LDS ([column][lane] planes)
+struct RegRow {
+    double (&r)[RT];
+    double (&i)[RT];
+    __device__ double re(int q) const { return r[q]; }
+    __device__ double im(int q) const { return i[q]; }
+    __device__ void set(int q, double a, double b) {
+        r[q] = a;
+        i[q] = b;
+    }
+};
+struct LdsRow {
+    double (*r)[RB];
+    double (*i)[RB];
+    int lane;
+    __device__ double re(int q) const { return r[q][lane]; }
+    __device__ double im(int q) const { return i[q][lane]; }
+    __device__ void set(int q, double a, double b) {
+        r[q][lane] = a;
+        i[q][lane] = b;
+    }
+};
+
+__global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __restrict__ H, int ld, int n,
+                                                            double* __restrict__ dg, double* __restrict__ off,
+                                                            double* __restrict__ tau, double* __restrict__ refl,
+                                                            double* __restrict__ trace) {
+    __shared__ RedLds L;
+    const int tid = threadIdx.x;
+    const int g = tid >> 3, k = tid & 7;
+    const int NT = (n + RT - 1) / RT, NTT = NT * (NT + 1) / 2;
+    int tI[RS], tJ[RS];
+    double ar[RS_REG][RT], ai[RS_REG][RT];
+    double tr = 0.0;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+        // Tiles in column-major order (J, then I): a tile stops being live after column
+        // 8J + 7, so the 8 groups of a wave get 8 consecutive tiles of this order in each
+        // slot and go idle together; consecutive batches go to different waves.
+        const int b = s * RNW + (g >> 3);
+        const int t = b * RT + (g & 7);
+        int I = -1, J = 0;
+        if (t < NTT) {
+            int c0 = 0;
+            while (c0 + (NT - J) <= t) {
+                c0 += NT - J;
+                ++J;
+            }
+            I = J + (t - c0);
+        }
+        tI[s] = I;
+        tJ[s] = J;
+        __builtin_amdgcn_sched_barrier(0);
+        const int r = RT * I + k;
+        double xr[RT], xi[RT];
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const int c = RT * J + q;
+            xr[q] = 0.0;
+            xi[q] = 0.0;
+            if (I >= 0 && r < n && c < n) {
+                // Hermitian part: (H_rc + conj(H_cr)) / 2
+                const double* a = H + 2 * ((long)r * ld + c);
+                const double* b = H + 2 * ((long)c * ld + r);
+                xr[q] = 0.5 * (a[0] + b[0]);
+                xi[q] = 0.5 * (a[1] - b[1]);
+                if (r == c) {
+                    xi[q] = 0.0;
+                    tr += xr[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            if (s < RS_REG) {
+                ar[s < RS_REG ? s : 0][q] = xr[q];
+                ai[s < RS_REG ? s : 0][q] = xi[q];
+            } else {
+                L.tr[s - RS_REG][q][tid] = xr[q];
+                L.ti[s - RS_REG][q][tid] = xi[q];
+            }
+        }
+    }
+    for (int i = tid; i < 2 * RMAX; i += RB) {
+        L.vabs[i] = 0.0;
+        L.pabs[i] = 0.0;
+    }
+    {
+        double unused = 0.0;
+        block_sum2<RNW>(tr, unused, L.red);
+        if (tid == 0) trace[0] = tr;
+    }
+
+    for (int j = 0; j < n - 1; ++j) {
+        // Tile coordinates are laundered each column so that the compiler recomputes the
+        // LDS column addresses instead of keeping 40 of them live across the loop.
+#pragma unroll
+        for (int s = 0; s < RS; ++s) {
+            asm volatile("" : "+v"(tI[s]));
+            asm volatile("" : "+v"(tJ[s]));
+        }
+        // column j below the diagonal -> vabs (absolute rows); diagonal entry -> dg[j]
+        double x2 = 0.0, unused = 0.0;
+#pragma unroll
+        for (int s = 0; s < RS_REG; ++s) tile_extract(RegRow{ar[s], ai[s]}, tI[s], tJ[s], j, k, n, L.vabs, dg, x2);
+#pragma unroll
+        for (int s = 0; s < RS_LDS; ++s)
+            tile_extract(LdsRow{L.tr[s], L.ti[s], tid}, tI[RS_REG + s], tJ[RS_REG + s], j, k, n, L.vabs, dg, x2);
+        block_sum2<RNW>(x2, unused, L.red);
+        if (tid == 0) {
+            const double arr = L.vabs[2 * (j + 1)], aii = L.vabs[2 * (j + 1) + 1];
+            double beta, tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
+            if (x2 == 0.0 && aii == 0.0) {
+                beta = arr;
+            } else {
+                beta = -copysign(sqrt(arr * arr + aii * aii + x2), arr);
+                tr_ = (beta - arr) / beta;
+                ti_ = -aii / beta;
+                const double dr = arr - beta, di = aii, den = dr * dr + di * di;
+                sr = dr / den;
+                si = -di / den;
+            }
+            L.sc[0] = tr_;
+            L.sc[1] = ti_;
+            L.sc[2] = sr;
+            L.sc[3] = si;
+            off[j] = beta;
+            tau[2 * j] = tr_;
+            tau[2 * j + 1] = ti_;
+        }
+        __syncthreads();
+        const double tr_ = L.sc[0], ti_ = L.sc[1], sr = L.sc[2], si = L.sc[3];
+        // v (absolute index, zero at rows <= j), reflector row j; clear the accumulator
+        for (int i = tid; i < n; i += RB) {
+            double vr = 0.0, vi = 0.0;
+            if (i == j + 1) {
+                vr = 1.0;
+            } else if (i > j + 1) {
+                const double xr = L.vabs[2 * i], xi = L.vabs[2 * i + 1];
+                vr = xr * sr - xi * si;
+                vi = xr * si + xi * sr;
+            }
+            L.vabs[2 * i] = vr;
+            L.vabs[2 * i + 1] = vi;
+            if (i > j) {
+                refl[2 * ((long)j * n + (i - j - 1))] = vr;
+                refl[2 * ((long)j * n + (i - j - 1)) + 1] = vi;
+            }
+            L.pabs[2 * i] = 0.0;
+            L.pabs[2 * i + 1] = 0.0;
+        }
+        __syncthreads();
+        if (tr_ == 0.0 && ti_ == 0.0) continue;
+        // p = A22 v (tau applied below)
+#pragma unroll
+        for (int s = 0; s < RS_REG; ++s)
+            if (tile_live(tI[s], tJ[s], j)) {
+                RegRow x{ar[s], ai[s]};
+                tile_matvec(x, tI[s], tJ[s], k, L.vabs, L.pabs);
+            }
+#pragma unroll
+        for (int s = 0; s < RS_LDS; ++s)
+            if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
+                LdsRow x{L.tr[s], L.ti[s], tid};
+                tile_matvec(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.vabs, L.pabs);
+            }
+        __syncthreads();
+        // p <- tau p; w = p - (tau/2)(p^H v) v
+        double hr = 0.0, hi = 0.0;
+        for (int i = j + 1 + tid; i < n; i += RB) {
+            const double pr0 = L.pabs[2 * i], pi0 = L.pabs[2 * i + 1];
+            const double pr = tr_ * pr0 - ti_ * pi0, pi = tr_ * pi0 + ti_ * pr0;
+            L.pabs[2 * i] = pr;
+            L.pabs[2 * i + 1] = pi;
+            const double vr = L.vabs[2 * i], vi = L.vabs[2 * i + 1];
+            hr += pr * vr + pi * vi;
+            hi += pr * vi - pi * vr;
+        }
+        block_sum2<RNW>(hr, hi, L.red);
+        const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
+        for (int i = tid; i < RMAX; i += RB) {
+            double wr = 0.0, wi = 0.0;
+            if (i > j && i < n) {
+                const double vr = L.vabs[2 * i], vi = L.vabs[2 * i + 1];
+                wr = L.pabs[2 * i] + a2r * vr - a2i * vi;
+                wi = L.pabs[2 * i + 1] + a2r * vi + a2i * vr;
+            }
+            L.pabs[2 * i] = wr;
+            L.pabs[2 * i + 1] = wi;
+        }
+        __syncthreads();
+        // A22 -= v w^H + w v^H (entries outside the trailing block see v = w = 0)
+#pragma unroll
+        for (int s = 0; s < RS_REG; ++s)
+            if (tile_live(tI[s], tJ[s], j)) {
+                RegRow x{ar[s], ai[s]};
+                tile_update(x, tI[s], tJ[s], k, L.vabs, L.pabs);
+            }
+#pragma unroll
+        for (int s = 0; s < RS_LDS; ++s)
+            if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
+                LdsRow x{L.tr[s], L.ti[s], tid};
+                tile_update(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.vabs, L.pabs);
+            }
+        __syncthreads();
+    }
+    // last diagonal entry
+    double unused = 0.0;
+#pragma unroll
+    for (int s = 0; s < RS_REG; ++s)
+        tile_extract(RegRow{ar[s], ai[s]}, tI[s], tJ[s], n - 1, k, n, L.vabs, dg, unused);
+#pragma unroll
+    for (int s = 0; s < RS_LDS; ++s)
+        tile_extract(LdsRow{L.tr[s], L.ti[s], tid}, tI[RS_REG + s], tJ[RS_REG + s], n - 1, k, n, L.vabs, dg, unused);
+}
+
+// ------------------------------------------------------------------ eigenvalues / vectors
+// 1/q from the hardware reciprocal and one Newton step (the Sturm count tolerates a last-bit
+// difference from IEEE division; |q| >= pivmin keeps q normal)
+__device__ __forceinline__ double rcp_nr(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    const double e = fma(-q, r, 1.0);
+    return fma(r, e, r);
+}
+
+// number of eigenvalues of T below x (Sturm sequence in ratio form with the LAPACK pivot guard)
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int c = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+        q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double bis_tol(double lo, double hi, double tnorm) {
+    return 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + EPS * tnorm;
+}
+
+// One wave narrows [lo, hi] around the eigenvalue of ascending index idx (count(lo) <= idx <
+// count(hi)) with 64 shifts per pass (6 bits); every lane returns the same bracket.  One
+// shift per lane: the pass is issue-bound, so more shifts per lane would buy fewer bits per
+// cycle.
+__device__ void wave_multisect(const double* d, const double* e2, int n, int idx, double pivmin, double tnorm,
+                               double& lo, double& hi) {
+    const int lane = threadIdx.x & 63;
+    for (int it = 0; it < 24; ++it) {
+        if (hi - lo <= bis_tol(lo, hi, tnorm)) break;
+        const double h = (hi - lo) / 65.0;
+        const double x = lo + (double)(lane + 1) * h;
+        const int c = sturm_count(d, e2, n, x, pivmin);
+        double nlo = c <= idx ? x : lo, nhi = c <= idx ? hi : x;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
+            nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
+        }
+        lo = nlo;
+        hi = nhi;
+    }
+}
+
+__device__ __forceinline__ unsigned hash32(unsigned x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// par[] written by tri_top_kernel and read by the later kernels
+enum { P_TNORM = 0, P_PIVMIN = 1, P_TOP = 2, P_THR = 3, P_COUNT = 8 };
+
+// One wave: Gershgorin bounds, the largest eigenvalue, the level's threshold t and the
+// accepted count m (cnt[0]); st as spectrum_cut writes it.
+__global__ __launch_bounds__(64) void tri_top_kernel(const double* __restrict__ dg, const double* __restrict__ off,
+                                                     int n, int level, double floor2, double noise, double tau_rel,
+                                                     int cap, const double* __restrict__ trace,
+                                                     double* __restrict__ st, int* __restrict__ cnt,
+                                                     double* __restrict__ par) {
+    __shared__ double d[TRI_MAX], e2[TRI_MAX];
+    const int lane = threadIdx.x;
+    double gmax = -INFINITY, gmin = INFINITY, e2max = 0.0, dmax = -INFINITY;
+    for (int i = lane; i < n; i += 64) {
+        const double di = dg[i];
+        const double el = i > 0 ? fabs(off[i - 1]) : 0.0, er = i < n - 1 ? fabs(off[i]) : 0.0;
+        d[i] = di;
+        e2[i] = i < n - 1 ? off[i] * off[i] : 0.0;
+        gmax = fmax(gmax, di + el + er);
+        gmin = fmin(gmin, di - el - er);
+        e2max = fmax(e2max, e2[i]);
+        dmax = fmax(dmax, di);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+        gmin = fmin(gmin, __shfl_xor(gmin, o, 64));
+        e2max = fmax(e2max, __shfl_xor(e2max, o, 64));
+        dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    }
+    __syncthreads();
+    const double tnorm = fmax(fabs(gmin), fabs(gmax));
+    const double pivmin = DBL_MIN * fmax(1.0, e2max);
+    double lo = dmax, hi = gmax + EPS * tnorm + pivmin;   // count(lo) <= n-1 < count(hi)
+    wave_multisect(d, e2, n, n - 1, pivmin, tnorm, lo, hi);
+    if (lane == 0) {
+        const double lmax = 0.5 * (lo + hi);
+        const double st0 = level == 0 ? lmax : st[0];
+        double t = floor2 * st0;
+        if (noise * lmax > t) t = noise * lmax;
+        if (tau_rel * lmax > t) t = tau_rel * lmax;
+        int m = 0;
+        if (lmax > 0.0) {
+            m = n - sturm_count(d, e2, n, t, pivmin);
+            if (m > cap) m = cap;
+            if (m < 0) m = 0;
+        }
+        if (level == 0) {
+            st[0] = lmax;
+            st[4] = trace[0];
+        }
+        st[1 + level] = t;
+        cnt[0] = m;
+        par[P_TNORM] = tnorm;
+        par[P_PIVMIN] = pivmin;
+        par[P_TOP] = hi;
+        par[P_THR] = t;
+    }
+}
+
+// Wave k < m: eigenvalue k (descending) by multisection on [t, top].
+__global__ __launch_bounds__(64) void tri_eval_kernel(const double* __restrict__ dg, const double* __restrict__ off,
+                                                      int n, const int* __restrict__ cnt,
+                                                      const double* __restrict__ par, double* __restrict__ evals,
+                                                      double* __restrict__ sig, double* __restrict__ inv) {
+    __shared__ double d[TRI_MAX], e2[TRI_MAX];
+    const int k = blockIdx.x, lane = threadIdx.x;
+    if (k >= cnt[0]) return;
+    for (int i = lane; i < n; i += 64) {
+        d[i] = dg[i];
+        e2[i] = i < n - 1 ? off[i] * off[i] : 0.0;
+    }
+    __syncthreads();
+    double lo = par[P_THR], hi = par[P_TOP];
+    wave_multisect(d, e2, n, n - 1 - k, par[P_PIVMIN], par[P_TNORM], lo, hi);
+    if (lane == 0) {
+        const double lk = 0.5 * (lo + hi);
+        evals[k] = lk;
+        const double sk = sqrt(fmax(lk, 0.0));
+        if (sig) sig[k] = sk;
+        if (inv) inv[k] = sk > 0.0 ? 1.0 / sk : 0.0;
+    }
+}
+
+// Wave k < m: eigenvector k of T by three steps of inverse iteration (LU with partial pivoting
+// of T - lambda_k I fused with the forward solve, factors in the wave's LDS).  Z row k (length
+// n) receives the unit vector.
+__global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ dg, const double* __restrict__ off,
+                                                     int n, const int* __restrict__ cnt,
+                                                     const double* __restrict__ par,
+                                                     const double* __restrict__ evals, double* __restrict__ Z) {
+    __shared__ double d[TRI_MAX], e[TRI_MAX], u0[TRI_MAX], u1[TRI_MAX], u2[TRI_MAX], yv[TRI_MAX], z[TRI_MAX];
+    __shared__ double ssum;
+    const int k = blockIdx.x, lane = threadIdx.x;
+    if (k >= cnt[0]) return;
+    for (int i = lane; i < n; i += 64) {
+        d[i] = dg[i];
+        e[i] = i < n - 1 ? off[i] : 0.0;
+        z[i] = (double)(hash32((unsigned)(i * 7919 + k * 104729 + 17)) >> 8) * (2.0 / 16777216.0) - 1.0;
+    }
+    __syncthreads();
+    const double lk = evals[k];
+    const double tnorm = par[P_TNORM];
+    const double tiny = EPS * tnorm > 0.0 ? EPS * tnorm : DBL_MIN;
+    for (int iter = 0; iter < 3; ++iter) {
+        if (lane == 0) {
+            double p0 = d[0] - lk, p1 = n > 1 ? e[0] : 0.0, y = z[0];
+            for (int i = 0; i < n - 1; ++i) {
+                const double sub = e[i], nd = d[i + 1] - lk, ns = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+                const double xn = z[i + 1];
+                if (fabs(p0) >= fabs(sub)) {
+                    if (p0 == 0.0) p0 = tiny;
+                    const double mlt = sub / p0;
+                    u0[i] = p0;
+                    u1[i] = p1;
+                    u2[i] = 0.0;
+                    yv[i] = y;
+                    p0 = nd - mlt * p1;
+                    p1 = ns;
+                    y = xn - mlt * y;
+                } else {
+                    const double mlt = p0 / sub;
+                    u0[i] = sub;
+                    u1[i] = nd;
+                    u2[i] = ns;
+                    yv[i] = xn;
+                    const double np0 = p1 - mlt * nd;
+                    p1 = -mlt * ns;
+                    p0 = np0;
+                    y = y - mlt * xn;
+                }
+            }
+            if (p0 == 0.0) p0 = tiny;
+            double z1 = y / p0, z2 = 0.0;
+            z[n - 1] = z1;
+            for (int i = n - 2; i >= 0; --i) {
+                const double z0 = (yv[i] - u1[i] * z1 - u2[i] * z2) / u0[i];
+                z[i] = z0;
+                z2 = z1;
+                z1 = z0;
+            }
+        }
+        __syncthreads();
+        double s = 0.0;
+        for (int i = lane; i < n; i += 64) s += z[i] * z[i];
+        s = wave_sum(s);
+        const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+        for (int i = lane; i < n; i += 64) z[i] *= sc;
+        __syncthreads();
+    }
+    for (int i = lane; i < n; i += 64) Z[(long)k * n + i] = z[i];
+}
+
+// Clusters of eigenvalues closer than 1e-12 ||T|| (inverse iteration leaves their vectors at
+// arbitrary angles inside the cluster): modified Gram-Schmidt, one wave per cluster.  Vectors of
+// different clusters are orthogonal to about eps ||T|| / gap <= 2e-4.
+__global__ __launch_bounds__(TB) void tri_mgs_kernel(int n, const int* __restrict__ cnt,
+                                                     const double* __restrict__ par,
+                                                     const double* __restrict__ evals, double* __restrict__ Z) {
+    __shared__ int cstart[TRI_MAX + 1];
+    __shared__ int ncl;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m = cnt[0];
+    if (m < 2) return;
+    if (tid == 0) {
+        const double gap = 1e-12 * par[P_TNORM];
+        int nc = 0;
+        cstart[nc++] = 0;
+        for (int k = 1; k < m; ++k)
+            if (evals[k - 1] - evals[k] >= gap) cstart[nc++] = k;
+        cstart[nc] = m;
+        ncl = nc;
+    }
+    __syncthreads();
+    const int nc = ncl;
+    for (int ci = w; ci < nc; ci += NW) {
+        const int c0 = cstart[ci], c1 = cstart[ci + 1];
+        if (c1 - c0 < 2) continue;
+        for (int j = c0; j < c1; ++j) {
+            double* zj = Z + (long)j * n;
+            for (int pq = c0; pq < j; ++pq) {
+                const double* zp = Z + (long)pq * n;
+                double s = 0.0;
+                for (int i = lane; i < n; i += 64) s += zp[i] * zj[i];
+                s = wave_sum(s);
+                for (int i = lane; i < n; i += 64) zj[i] -= s * zp[i];
+            }
+            double s = 0.0;
+            for (int i = lane; i < n; i += 64) s += zj[i] * zj[i];
+            s = wave_sum(s);
+            const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+            for (int i = lane; i < n; i += 64) zj[i] *= sc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ back-transform
+// V[:, k] = H_0 ... H_{n-2} z_k for k < cnt[0]; workgroup b owns columns [8b, 8b+8).  The
+// reflector of the next step is loaded into registers while the current one is applied.
+__global__ __launch_bounds__(BK_THREADS) void tri_back_kernel(const double* __restrict__ refl,
+                                                              const double* __restrict__ tau, int n,
+                                                              const double* __restrict__ Z,
+                                                              const int* __restrict__ cnt, double* __restrict__ V,
+                                                              int ldv) {
+    constexpr int PF = (2 * TRI_MAX + BK_THREADS - 1) / BK_THREADS;   // doubles per thread per reflector
+    __shared__ double zb[BK_COLS][2 * TRI_MAX];
+    __shared__ double vb[2][2 * TRI_MAX];
+    __shared__ double tl[2 * TRI_MAX];
+    const int m = cnt[0];
+    const int k0 = blockIdx.x * BK_COLS;
+    if (k0 >= m) return;
+    const int kc = min(BK_COLS, m - k0);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 2 * (n - 1); i += BK_THREADS) tl[i] = tau[i];
+    for (int idx = tid; idx < BK_COLS * n; idx += BK_THREADS) {
+        const int c = idx / n, i = idx - c * n;
+        zb[c][2 * i] = c < kc ? Z[(long)(k0 + c) * n + i] : 0.0;
+        zb[c][2 * i + 1] = 0.0;
+    }
+    const int c = tid >> 5, part = tid & 31;   // 32 lanes per column
+    // reflector j occupies refl[2 j n .. 2 j n + 2 (n-1-j))
+    double pf[PF];
+    auto fetch = [&](int j) {
+        const int L2 = 2 * (n - 1 - j);
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int i = tid + q * BK_THREADS;
+            pf[q] = (j >= 0 && i < L2) ? refl[2L * j * n + i] : 0.0;
+        }
+    };
+    int buf = 0;
+    fetch(n - 2);
+    for (int j = n - 2; j >= 0; --j) {
+        const int L = n - 1 - j;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int i = tid + q * BK_THREADS;
+            if (i < 2 * L) vb[buf][i] = pf[q];
+        }
+        fetch(j - 1);
+        __syncthreads();
+        const double tr = tl[2 * j], ti = tl[2 * j + 1];
+        if (tr != 0.0 || ti != 0.0) {
+            // s = v^H z[j+1..]
+            double sr = 0.0, si = 0.0;
+            const double* zc = &zb[c][2 * (j + 1)];
+            const double* vv = vb[buf];
+            for (int i = part; i < L; i += 32) {
+                const double vr = vv[2 * i], vi = vv[2 * i + 1], zr = zc[2 * i], zi = zc[2 * i + 1];
+                sr += vr * zr + vi * zi;
+                si += vr * zi - vi * zr;
+            }
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) {
+                sr += __shfl_xor(sr, o, 64);
+                si += __shfl_xor(si, o, 64);
+            }
+            // z -= tau s v
+            const double fr = tr * sr - ti * si, fi = tr * si + ti * sr;
+            double* zw = &zb[c][2 * (j + 1)];
+            for (int i = part; i < L; i += 32) {
+                const double vr = vv[2 * i], vi = vv[2 * i + 1];
+                zw[2 * i] -= fr * vr - fi * vi;
+                zw[2 * i + 1] -= fr * vi + fi * vr;
+            }
+        }
+        buf ^= 1;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * kc; idx += BK_THREADS) {
+        const int i = idx / kc, cc = idx - i * kc;
+        V[2 * ((long)i * ldv + k0 + cc)] = zb[cc][2 * i];
+        V[2 * ((long)i * ldv + k0 + cc) + 1] = zb[cc][2 * i + 1];
+    }
+}
+
+}  // namespace
+
+size_t tri_work_bytes(int n) {
+    if (n > TRI_MAX) n = TRI_MAX;
+    size_t b = 0;
+    b += (size_t)n * sizeof(double) * 4;          // dg, off, tau (complex)
+    b += 64 * sizeof(double);                     // trace
+    b += P_COUNT * sizeof(double);                // par
+    b += (size_t)n * n * 2 * sizeof(double);      // reflector rows
+    b += (size_t)n * n * sizeof(double);          // Z
+    return b + 1024;
+}
+
+hipError_t eigh_top(hipStream_t s, int n, double* H, int ldh, int level, double floor2, double noise, double tau,
+                    int cap, double* st, int* cnt, double* evals, double* sig, double* inv, double* V, int ldv,
+                    void* work, ProfSink* prof) {
+    if (n < 1 || n > TRI_MAX || cap < 0) return hipErrorInvalidValue;
+    if (cap > n) cap = n;
+    char* w = (char*)work;
+    double* dg = (double*)w;
+    double* off = dg + n;
+    double* tv = off + n;
+    double* trace = tv + 2 * n;
+    double* par = trace + 64;
+    double* refl = par + P_COUNT;
+    double* Z = refl + (size_t)n * n * 2;
+    const double nn = (double)n;
+    if (prof) prof->begin(s, PF_TRI_REDUCE);
+    if (n <= RMAX)
+        hipLaunchKernelGGL(tri_reduce_reg_kernel, dim3(1), dim3(RB), 0, s, H, ldh, n, dg, off, tv, refl, trace);
+    else
+        hipLaunchKernelGGL(tri_reduce_kernel, dim3(1), dim3(TB), 0, s, H, ldh, n, dg, off, tv, refl, trace);
+    // Hermitian tridiagonal reduction: 16/3 n^3 real flop; the matrix is read and rewritten
+    // once per column
+    if (prof) prof->end(s, PF_TRI_REDUCE, 16.0 / 3.0 * nn * nn * nn, 16.0 * nn * nn * 2.0);
+    if (prof) prof->begin(s, PF_TRI_SOLVE);
+    hipLaunchKernelGGL(tri_top_kernel, dim3(1), dim3(64), 0, s, dg, off, n, level, floor2, noise, tau, cap, trace,
+                       st, cnt, par);
+    if (cap > 0) {
+        hipLaunchKernelGGL(tri_eval_kernel, dim3(cap), dim3(64), 0, s, dg, off, n, cnt, par, evals, sig, inv);
+        hipLaunchKernelGGL(tri_vec_kernel, dim3(cap), dim3(64), 0, s, dg, off, n, cnt, par, evals, Z);
+        hipLaunchKernelGGL(tri_mgs_kernel, dim3(1), dim3(TB), 0, s, n, cnt, par, evals, Z);
+    }
+    if (prof) prof->end(s, PF_TRI_SOLVE, 0.0, 0.0);
+    if (cap > 0) {
+        if (prof) prof->begin(s, PF_TRI_BACK);
+        hipLaunchKernelGGL(tri_back_kernel, dim3((cap + BK_COLS - 1) / BK_COLS), dim3(BK_THREADS), 0, s, refl, tv, n,
+                           Z, cnt, V, ldv);
+        // n reflectors applied to at most cap vectors: 8 n^2 cap flop (bound, the count is on
+        // the device)
+        if (prof) prof->end(s, PF_TRI_BACK, 8.0 * nn * nn * cap, 16.0 * nn * nn);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mpdo

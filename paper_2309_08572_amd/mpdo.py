@@ -28,7 +28,8 @@ EXPORTS = (
     "mpdo_profile_enable", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
 )
 
-PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other")
+PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other",
+                 "tri_reduce", "tri_solve", "tri_back")
 
 
 class Config(C.Structure):
