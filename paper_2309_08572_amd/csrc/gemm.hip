@@ -8,7 +8,7 @@
 //
 // Complex products use four real MFMA products per k-step (re*re - im*im, re*im + im*re);
 // counted as 8 real flop per complex multiply-add, the same as the algorithm.
-// Block tile 64 x 64, k-step 16, 256 threads = 4 waves of 64 lanes, each wave owns a
+// Block tile 64 x 64, k-step 32, 256 threads = 4 waves of 64 lanes, each wave owns a
 // 32 x 32 quadrant = 2 x 2 MFMA 16x16 tiles.  Tiles of A and B are staged through LDS as
 // separate real and imaginary planes; the global loader walks the contiguous dimension of
 // each view so loads coalesce whichever way the view is laid out.  Large-k products with a
@@ -23,7 +23,7 @@ namespace {
 
 constexpr int BM = 64;
 constexpr int BN = 64;
-constexpr int BK = 16;
+constexpr int BK = 32;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -108,43 +108,48 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
     const int li = lane & 15;
     const int lk = lane >> 4;
 
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        // ---- stage A tile (BM x BK) and B tile (BK x BN)
+    // The next k-tile is loaded into registers while the current one is multiplied from LDS.
+    constexpr int PA = (BM * BK) / 256, PB = (BN * BK) / 256;
+    T par[PA], pai[PA], pbr[PB], pbi[PB];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int j = 0; j < (BM * BK) / 256; ++j) {
+        for (int j = 0; j < PA; ++j) {
             const int e = tid + 256 * j;
-            int m, k;
-            if (a_kfast) {
-                m = e >> 4;
-                k = e & 15;
-            } else {
-                m = e & 63;
-                k = e >> 6;
-            }
+            const int m = a_kfast ? e / BK : e % BM, k = a_kfast ? e % BK : e / BM;
             const int gm = m0 + m, gk = k0 + k;
-            T re = 0, im = 0;
-            if (gm < g.M && gk < kend) load_cplx(Ap, (long)gm * g.A.rs + (long)gk * g.A.cs, g.A.conj, re, im);
-            sAr[m][k] = re;
-            sAi[m][k] = im;
+            par[j] = 0;
+            pai[j] = 0;
+            if (gm < g.M && gk < kend) load_cplx(Ap, (long)gm * g.A.rs + (long)gk * g.A.cs, g.A.conj, par[j], pai[j]);
         }
 #pragma unroll
-        for (int j = 0; j < (BN * BK) / 256; ++j) {
+        for (int j = 0; j < PB; ++j) {
             const int e = tid + 256 * j;
-            int n, k;
-            if (b_nfast) {
-                n = e & 63;
-                k = e >> 6;
-            } else {
-                n = e >> 4;
-                k = e & 15;
-            }
+            const int n = b_nfast ? e % BN : e / BK, k = b_nfast ? e / BN : e % BK;
             const int gn = n0 + n, gk = k0 + k;
-            T re = 0, im = 0;
-            if (gn < g.N && gk < kend) load_cplx(Bp, (long)gk * g.B.rs + (long)gn * g.B.cs, g.B.conj, re, im);
-            sBr[k][n] = re;
-            sBi[k][n] = im;
+            pbr[j] = 0;
+            pbi[j] = 0;
+            if (gn < g.N && gk < kend) load_cplx(Bp, (long)gk * g.B.rs + (long)gn * g.B.cs, g.B.conj, pbr[j], pbi[j]);
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        // ---- stage the fetched A tile (BM x BK) and B tile (BK x BN) in LDS
+#pragma unroll
+        for (int j = 0; j < PA; ++j) {
+            const int e = tid + 256 * j;
+            const int m = a_kfast ? e / BK : e % BM, k = a_kfast ? e % BK : e / BM;
+            sAr[m][k] = par[j];
+            sAi[m][k] = pai[j];
+        }
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            const int e = tid + 256 * j;
+            const int n = b_nfast ? e % BN : e / BK, k = b_nfast ? e / BN : e % BK;
+            sBr[k][n] = pbr[j];
+            sBi[k][n] = pbi[j];
         }
         __syncthreads();
+        if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             T ar[2], ai[2], nai[2], br[2], bi[2];
@@ -250,9 +255,11 @@ hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView
     if (g.kchunk == 0) g.kchunk = BK;
     const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
     // split long reductions when the output alone cannot fill the 256 compute units
-    if (tiles < 192 && g.K >= 1024) {
-        int ks = (512 + tiles - 1) / tiles;
-        const int maxks = g.K / 256;
+    // (one 64 x 64 x 32 complex k-step keeps a CU's FP64 matrix cores busy for ~3.4 us, so
+    // small outputs are spread over the chip in k-chunks of at least 64)
+    if (tiles < 192 && g.K >= 128) {
+        int ks = (768 + tiles - 1) / tiles;
+        const int maxks = g.K / 64;
         if (ks > maxks) ks = maxks;
         if (ks > 64) ks = 64;
         if (ks >= 2) {
