@@ -292,15 +292,7 @@ struct Engine {
 
     void gemm(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_, int batch = 1, long sA = 0,
               long sB = 0, long sC = 0) {
-        ProfSink* p = ps();
-        if (p) p->begin(st, PF_GEMM);
-        HIPCHK(cgemm<T>(st, M, N, K, a, A, B, b, C_, batch, sA, sB, sC));
-        if (p) {
-            const double flop = 8.0 * M * (double)N * K * batch;
-            const double bytes =
-                2.0 * sizeof(T) * batch * ((double)M * K + (double)K * N + (double)M * N * ((b.re != 0 || b.im != 0) ? 2 : 1));
-            p->end(st, PF_GEMM, flop, bytes);
-        }
+        HIPCHK(cgemm<T>(st, M, N, K, a, A, B, b, C_, batch, sA, sB, sC, ps()));
     }
 
     // Gram G = F^H F (c x c) of the n x c view F, into the FP64 eigen buffer (dense, ld c)

@@ -7,9 +7,11 @@ namespace mpdo {
 
 // C = alpha * A * B + beta * C over `batch` problems; A is M x K, B is K x N, C is M x N as
 // strided views (see CView); batch strides sA, sB, sC are in complex elements.  C must not
-// alias A or B.  Returns the launch status.
+// alias A or B.  prof (may be null) brackets the matrix-core kernel as PF_GEMM with its
+// algorithmic flop and bytes, and the output pre-scaling of split-k products as PF_OTHER.
+// Returns the launch status.
 template <typename T>
 hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
-                 CView<T> C, int batch = 1, long sA = 0, long sB = 0, long sC = 0);
+                 CView<T> C, int batch = 1, long sA = 0, long sB = 0, long sC = 0, ProfSink* prof = nullptr);
 
 }  // namespace mpdo

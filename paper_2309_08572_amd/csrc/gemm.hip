@@ -232,7 +232,7 @@ __global__ void cscale_kernel(CView<T> C, int M, int N, double br, double bi) {
 
 template <typename T>
 hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
-                 CView<T> C, int batch, long sA, long sB, long sC) {
+                 CView<T> C, int batch, long sA, long sB, long sC, ProfSink* prof) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     GemmArgs<T> g;
     g.M = M;
@@ -268,12 +268,14 @@ hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView
             if (ks >= 2) {
                 // C <- beta*C first, then accumulate alpha*AB atomically
                 const long tot = (long)M * N;
+                if (prof) prof->begin(s, PF_OTHER);
                 for (int bb = 0; bb < batch; ++bb) {
                     CView<T> Cb = C;
                     Cb.p = C.p + 2 * (long)bb * sC;
                     hipLaunchKernelGGL(cscale_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                                        Cb, M, N, beta.re, beta.im);
                 }
+                if (prof) prof->end(s, PF_OTHER, 0.0, 2.0 * sizeof(T) * (double)tot * batch);
                 g.ksplit = ks;
                 g.kchunk = chunk;
                 g.atomic = 1;
@@ -281,13 +283,22 @@ hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView
         }
     }
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * g.ksplit);
+    if (prof) prof->begin(s, PF_GEMM);
     hipLaunchKernelGGL(cgemm_kernel<T>, grid, dim3(256), 0, s, g);
+    if (prof) {
+        // algorithmic: 8 flop per complex multiply-add; A, B read and C written once (and read
+        // when beta != 0)
+        const double flop = 8.0 * M * (double)N * K * batch;
+        const double bytes = 2.0 * sizeof(T) * batch *
+                             ((double)M * K + (double)K * N + (double)M * N * ((beta.re != 0 || beta.im != 0) ? 2 : 1));
+        prof->end(s, PF_GEMM, flop, bytes);
+    }
     return hipGetLastError();
 }
 
 template hipError_t cgemm<double>(hipStream_t, int, int, int, cd, CView<double>, CView<double>, cd,
-                                  CView<double>, int, long, long, long);
+                                  CView<double>, int, long, long, long, ProfSink*);
 template hipError_t cgemm<float>(hipStream_t, int, int, int, cd, CView<float>, CView<float>, cd,
-                                 CView<float>, int, long, long, long);
+                                 CView<float>, int, long, long, long, ProfSink*);
 
 }  // namespace mpdo
