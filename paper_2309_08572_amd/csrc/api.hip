@@ -287,6 +287,14 @@ struct Engine {
         sync();
         memcpy(out, c.hbuf, n * sizeof(double));
     }
+    // two device arrays (na + nb <= 64 doubles) with one synchronisation
+    void read_doubles2(const double* da, int na, double* oa, const double* db, int nb, double* ob) {
+        HIPCHK(hipMemcpyAsync(c.hbuf, da, na * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(c.hbuf + na, db, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        memcpy(oa, c.hbuf, na * sizeof(double));
+        memcpy(ob, c.hbuf + na, nb * sizeof(double));
+    }
 
     ProfSink* ps() { return c.prof.get(); }
 
@@ -329,6 +337,20 @@ struct Engine {
             acc = read_int(s.cnt);
             if (!std::is_same<T, double>::value && acc > 0)
                 HIPCHK((geam<double, T>(st, n, acc, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));
+        } else if (n <= 64) {
+            // one workgroup solves to convergence; its sweep count is read together with the
+            // accepted count, in one synchronisation
+            HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, nullptr, c.hint, ps()));
+            ++eig_calls;
+            if (!std::is_same<T, double>::value)
+                HIPCHK((geam<double, T>(st, n, n, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));
+            HIPCHK(spectrum_cut(st, s.evals, n, level, floor2, noise, tau, cap, s.st, s.cnt, sig, inv));
+            HIPCHK(hipMemcpyAsync(c.hint, s.cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(c.hint + 1, eigh_sweep_counter(s.eigwork, n), sizeof(int), hipMemcpyDeviceToHost,
+                                  st));
+            sync();
+            if (c.hint[1] >= EIG_MAX_SWEEPS) throw Fail{MPDO_E_NUMERIC, "Jacobi eigensolver did not converge"};
+            acc = c.hint[0];
         } else {
             eig(n);
             HIPCHK(spectrum_cut(st, s.evals, n, level, floor2, noise, tau, cap, s.st, s.cnt, sig, inv));
@@ -386,11 +408,9 @@ struct Engine {
             HIPCHK((geam<T, T>(st, n, cc, C1(), F, C0(), V<T>(s.bT1, cc, 1))));
             gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(Kb, cc, 1), C1(), V<T>(s.bT1, cc, 1));
             HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums));
-            double sums[2];
-            read_doubles(s.sums, 2, sums);
+            double sums[2], st5[5];
+            read_doubles2(s.sums, 2, sums, s.st, 5, st5);
             if (lev == 0) {
-                double st5[5];
-                read_doubles(s.st, 5, st5);
                 fro2 = st5[4];
                 floor2 = st5[0] > 0.0 ? 64.0 * e * e * fro2 / st5[0] : 0.0;
             }
@@ -441,8 +461,7 @@ struct Engine {
             gemm(a, b, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(Bb, b, 1), C1(), V<T>(s.bR, b, 1));
             HIPCHK(sumsq<T>(st, V<T>(s.bR, b, 1), a, b, s.sums));
             double sums[2], st5[5];
-            read_doubles(s.sums, 2, sums);
-            read_doubles(s.st, 5, st5);
+            read_doubles2(s.sums, 2, sums, s.st, 5, st5);
             // the residual R = F - U U^H F carries rounding of about eps ||F||_F: values below
             // 8 eps ||F||_F are not spectrum
             if (lev == 0 && st5[0] > 0.0) rfloor = 64.0 * e * e * st5[4] / st5[0];
@@ -566,7 +585,7 @@ struct Engine {
         const int r = gf ? gf->r : 0;
         const bool factored = gf && r <= MAX_FACTOR_RANK && (long)r * cm < (long)na;
         int kept = 0;
-        double tr_re = 0.0, tr_im = 0.0, n2 = 0.0;
+        double n2 = 0.0;
         T* Left = nullptr;   // new site i  (nL x kept), unscaled
         T* Right = nullptr;  // new site i+1 (kept x nR), unscaled
         T* outL = (T*)c.spare[0];
@@ -591,9 +610,10 @@ struct Engine {
             if (q <= 0) throw Fail{MPDO_E_NUMERIC, "merged tensor vanished"};
             // core C = K Fb (q x nb)
             gemm(q, nb, k, C1(), V<T>(s.bK, k, 1), Fb, C0(), V<T>(s.bC, nb, 1));
-            HIPCHK(sumsq<T>(st, V<T>(s.bC, nb, 1), q, nb, s.sums));
+            // ||theta||^2 (= ||C||^2) and its non-finite count stay in sc[4..5] for PPT
+            HIPCHK(sumsq<T>(st, V<T>(s.bC, nb, 1), q, nb, s.sc + 4));
             double sums[2];
-            read_doubles(s.sums, 2, sums);
+            read_doubles(s.sc + 4, 2, sums);
             if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
             n2 = sums[0];
             kept = svd_left(V<T>(s.bC, nb, 1), q, nb, chi, s.bU2);
@@ -615,9 +635,9 @@ struct Engine {
             CView<T> Th = V<T>(s.bA, nR, 1);
             HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
             HIPCHK(dot(st, s.lvec, s.vtmp, nL, s.sc));
-            HIPCHK(sumsq<T>(st, Th, nL, nR, s.sums));
+            HIPCHK(sumsq<T>(st, Th, nL, nR, s.sc + 4));
             double sums[2];
-            read_doubles(s.sums, 2, sums);
+            read_doubles(s.sc + 4, 2, sums);
             if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
             n2 = sums[0];
             CView<T> Fa = dir > 0 ? Th : adj(Th);
@@ -640,16 +660,7 @@ struct Engine {
         // trace factors of the kept Schmidt pairs and PPT
         HIPCHK(gemv_left<T>(st, V<T>(Left, kept, 1), nL, kept, s.lvec, s.tl));
         HIPCHK(gemv_left<T>(st, trans(V<T>(Right, nR, 1)), nR, kept, s.rvec, s.tr));
-        // sc[0..1] holds tr(rho) from the dot; sc[2] = ||theta||^2
-        {
-            double h[2];
-            read_doubles(s.sc, 2, h);
-            tr_re = h[0];
-            tr_im = h[1];
-            double scv[4] = {tr_re, tr_im, n2, 0.0};
-            memcpy(c.hbuf, scv, sizeof(scv));
-            HIPCHK(hipMemcpyAsync(s.sc, c.hbuf, sizeof(scv), hipMemcpyHostToDevice, st));
-        }
+        // sc[0..1] holds tr(rho) from the dot, sc[4] = ||theta||^2: PPT reads both on the device
         HIPCHK(ppt(st, s.sig, s.tl, s.tr, s.sc, kept, c.cfg.ppt, c.cfg.renorm_trace, s.fac, s.pout));
         if (dir > 0)
             HIPCHK(scale_rows<T>(st, Right, kept, nR, nR, s.fac));

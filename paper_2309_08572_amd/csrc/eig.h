@@ -8,6 +8,10 @@ namespace mpdo {
 // Device scratch bytes eigh() needs for order n.
 size_t eigh_work_bytes(int n);
 
+// Device int where eigh() leaves the number of sweeps of an order <= 64 solve (read it after
+// the stream reaches that point; eigh() itself only waits for it when sweeps_used is given).
+int* eigh_sweep_counter(void* work, int n);
+
 // Eigen-decomposition of the Hermitian n x n complex matrix H (row-major, leading
 // dimension ldh, overwritten).  evals[0..n) receives the eigenvalues in descending order,
 // V (row-major, leading dimension ldv) the matching unit eigenvectors as columns.  Blocks

@@ -550,6 +550,16 @@ size_t eigh_work_bytes(int n) {
     return (b > bt ? b : bt) + 1024;
 }
 
+int* eigh_sweep_counter(void* work, int n) {
+    const int nblk = ((n + NB - 1) / NB + 1) & ~1;
+    char* w = (char*)work;
+    w += (size_t)(nblk / 2) * NP * NP * 2 * sizeof(double);
+    w += (size_t)n * n * 2 * sizeof(double);
+    w += 64 * sizeof(double);
+    int* skip = (int*)w;
+    return skip + nblk / 2 + n;
+}
+
 hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, double* evals, void* work,
                 int max_sweeps, int* sweeps_used, int* host_pinned, ProfSink* prof) {
     if (n <= 0) return hipSuccess;

@@ -291,7 +291,7 @@ __global__ void ns_prep_kernel(const T* __restrict__ G, int q, T* __restrict__ Z
 //   sig[k]   kept Schmidt values Lambda'
 //   tl[k]    left trace factors  (l . U_j), complex
 //   tr[k]    right trace factors (B_j . r), complex; T'_j Lambda'_j = tl_j tr_j
-//   sc[0..3] = re tr(rho), im tr(rho), ||theta||_F^2, (unused)
+//   sc[0..1] = re, im tr(rho); sc[4] = ||theta||_F^2 (sc[5]: its non-finite count)
 // Output: fac[j] = Lambda~_j / Lambda'_j and out[0..15] (see PptOut in kernels.h).
 __global__ void ppt_kernel(const double* __restrict__ sig, const double* __restrict__ tl,
                            const double* __restrict__ tr, const double* __restrict__ sc, int k, int use_ppt,
@@ -329,7 +329,7 @@ __global__ void ppt_kernel(const double* __restrict__ sig, const double* __restr
     __shared__ int feasible, degen;
     if (tid == 0) {
         const double tt = red[0][0], tl_ = red[1][0], ll = red[2][0];
-        const double trr = sc[0], n2 = sc[2];
+        const double trr = sc[0], n2 = sc[4];
         const double nT = sqrt(tt), nL = sqrt(ll);
         double x = 0.0, cth = 1.0, theta = 0.0, sigma = 0.0;
         int feas = 1, dg = 0;

@@ -184,3 +184,22 @@ def test_truncating_ppt_keeps_xi_and_converges():
                 assert abs(x["xi_after"] - x["xi_before"]) <= 1e-10 * abs(x["xi_before"])
         errs.append(abs(mpo.observables(m)["energy_per_site"] - ref["energy_per_site"]))
     assert errs[2] < errs[0]
+
+
+def test_stored_full_size_oracle_values_are_consistent():
+    """The cached oracle output for the N=100 chi=512 p=3 workload obeys what the maps fix:
+    trace 1 (no value above the cut is dropped at these bonds, so tr rho is kept), populations of
+    every atom sum to 1 and lie in [0, 1], and the all-qubit probability is at most the
+    smallest single-atom qubit probability."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "m3_seed0_oracle.json")
+    with open(path) as f:
+        o = json.load(f)
+    pops = np.array(o["populations"])
+    assert pops.shape == (100, 4)
+    assert abs(complex(*o["trace"]) - 1.0) < 1e-12
+    np.testing.assert_allclose(pops.sum(axis=1), 1.0, atol=1e-12)
+    assert pops.min() > -1e-12 and pops.max() < 1 + 1e-12
+    assert o["p_success"] <= float(np.min(pops[:, 0] + pops[:, 1])) + 1e-12
+    assert max(o["bond_dims"]) <= 512
