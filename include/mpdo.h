@@ -135,6 +135,27 @@ mpdo_status mpdo_expect(mpdo_ctx ctx, int n_terms, const int* first_site,
                         const int* n_sites_in_term, const double* ops, int normalize,
                         double* out);
 
+/* Second-order observables, i.e. linear functions of rho (x) rho, by doubled transfer
+ * matrices (Fig. 6c; Sec. III.E).  Examples are the purity, the collision probability
+ * (Sec. III.F) and the second Renyi entropy of a block of atoms.
+ *
+ * Term t covers the consecutive atoms first_site[t] .. first_site[t] + n_sites_in_term[t] - 1.
+ * For each atom j of the term, ops holds one D2 x D2 complex matrix M_j (D2 = d^2), row-major
+ * [eta][eta'] with eta = sigma d + sigma'.  The terms' matrices are concatenated in order, on
+ * the host, and are copied before the call returns.  Atoms outside the term are traced out in
+ * both copies.
+ *
+ * out[2t], out[2t+1] receive the real and imaginary parts of
+ *     sum_{eta, eta'} vec(rho)[eta] vec(rho)[eta'] prod_j M_j[eta_j, eta'_j],
+ * divided by tr(rho)^2 when normalize != 0.  Queued channels P on an atom enter as P^T M P.
+ *
+ * Per atom this costs three complex GEMMs of order D2 chi^3.  The call synchronises the stream.
+ * Errors: MPDO_E_ARG for a term out of range, a null pointer or a non-finite entry;
+ * MPDO_E_STATE before the state is initialised. */
+mpdo_status mpdo_expect2(mpdo_ctx ctx, int n_terms, const int* first_site,
+                         const int* n_sites_in_term, const double* ops, int normalize,
+                         double* out);
+
 /* tr(rho): out[0], out[1] = re, im. */
 mpdo_status mpdo_trace(mpdo_ctx ctx, double* out);
 

@@ -14,7 +14,8 @@ for per-atom second-order operators M_j (D2 x D2):
   swap (purity of the atom's part)    M[(s,s'),(t,t')] = delta(s,t') delta(s',t)
   diagonal collision                  M[(s,s'),(t,t')] = delta(s,s') delta(t,t') delta(s,t)
   atom traced out in both copies      M[(s,s'),(t,t')] = delta(s,s') delta(t,t')
-and E2 is contracted left to right with a doubled transfer matrix (einsum, no blocking).
+and E2 is contracted left to right with a doubled transfer matrix (one einsum per atom,
+evaluated in the pairwise order numpy chooses).
 """
 from __future__ import annotations
 
@@ -92,7 +93,7 @@ def mpo_expect2(m, ops_by_site) -> complex:
     E = np.ones((1, 1), dtype=np.complex128)
     for j, a in enumerate(m.A):
         M = np.asarray(ops_by_site.get(j, tr_op), dtype=np.complex128)
-        E = np.einsum("ab,asc,st,btd->cd", E, a, M, a)
+        E = np.einsum("ab,asc,st,btd->cd", E, a, M, a, optimize=True)
     return complex(E[0, 0])
 
 

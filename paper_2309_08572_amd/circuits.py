@@ -178,3 +178,55 @@ def describe(spec, precision: int = MPDO_FP64, chi: Optional[int] = None, ppt: b
             "rho0": np.stack([plus_rho(d)] * n), "term_first": [t[0] for t in terms],
             "term_len": [len(t[1]) for t in terms],
             "term_ops": np.concatenate([np.stack(t[1]).reshape(-1) for t in terms])}
+
+
+# ----------------------------------------------------------------- second-order observables
+# Per-atom operators on the (eta, eta') pair of the two copies of vec(rho), eta = s d + s'
+# (Fig. 6c): the swap pairs rho_{s s'} with rho_{s' s} (purity of the atom's part), the
+# diagonal pairs rho_{ss} with rho_{ss} (collision probability), the trace pairs traces.
+def swap_op(d: int) -> np.ndarray:
+    M = np.zeros((d * d, d * d), dtype=np.complex128)
+    for a in range(d):
+        for b in range(d):
+            M[a * d + b, b * d + a] = 1.0
+    return M
+
+
+def diagonal_op(d: int) -> np.ndarray:
+    M = np.zeros((d * d, d * d), dtype=np.complex128)
+    for a in range(d):
+        M[a * d + a, a * d + a] = 1.0
+    return M
+
+
+def trace_op(d: int) -> np.ndarray:
+    v = np.eye(d, dtype=np.complex128).reshape(-1)
+    return np.outer(v, v)
+
+
+def purity(m: MPDO) -> float:
+    """tr(rho^2) / tr(rho)^2."""
+    return float(m.expect2([(0, [swap_op(m.d)] * m.n)])[0].real)
+
+
+def collision_probability(m: MPDO) -> float:
+    """sum_x p(x)^2 over all d^N basis states, p(x) = rho_xx / tr rho (Sec. III.F)."""
+    return float(m.expect2([(0, [diagonal_op(m.d)] * m.n)])[0].real)
+
+
+def _block_term(m: MPDO, sites):
+    lo, hi = min(sites), max(sites)
+    ops = [swap_op(m.d) if j in sites else trace_op(m.d) for j in range(lo, hi + 1)]
+    return (lo, ops)
+
+
+def renyi2(m: MPDO, sites) -> float:
+    """S2 = -log tr(rho_X^2) of the atoms in `sites`, rho normalised to unit trace."""
+    return float(-math.log(m.expect2([_block_term(m, set(sites))])[0].real))
+
+
+def renyi2_mutual_information(m: MPDO, a, b) -> float:
+    """S2(A) + S2(B) - S2(AB) (Sec. III.F)."""
+    a, b = set(a), set(b)
+    v = m.expect2([_block_term(m, a), _block_term(m, b), _block_term(m, a | b)]).real
+    return float(-math.log(v[0]) - math.log(v[1]) + math.log(v[2]))

@@ -248,6 +248,7 @@ struct mpdo_ctx_s {
     std::unique_ptr<EventProf> prof;   // non-null while measurement is on
     double prof_acc[4 * PF_COUNT] = {0};
     double* obuf = nullptr;       // operator vectors of one expectation term (N x D2)
+    double* o2buf = nullptr;      // second-order operators of one term (N x D2 x D2 complex, in T)
 
     size_t site_cap() const { return (size_t)chi * D2 * chi * 2; }  // in T elements
     size_t tsize() const { return fp32 ? sizeof(float) : sizeof(double); }
@@ -778,6 +779,7 @@ size_t workspace_for(const mpdo_config& cfg) {
     b += Scratch<double>::bytes(D2 * D2);
     b += (size_t)128 * (MAX_FACTOR_RANK * D2 * D2 * 2 * sizeof(double) + 256);   // gate factor slots
     b += (size_t)cfg.n_sites * D2 * 2 * sizeof(double) + 256;                       // expectation operators
+    b += (size_t)cfg.n_sites * D2 * D2 * 2 * sizeof(double) + 256;                  // second-order operators
     return b + (1 << 20);
 }
 
@@ -819,6 +821,7 @@ void alloc_state(mpdo_ctx c) {
     c->gorder.clear();
     for (int q = 0; q < 128; ++q) c->gslots.push_back(c->arena.take<double>((size_t)MAX_FACTOR_RANK * m2 * 2));
     c->obuf = c->arena.take<double>((size_t)c->N * c->D2 * 2);
+    c->o2buf = c->arena.take<double>((size_t)c->N * c->D2 * c->D2 * 2);
     if (!c->hbuf) {
         if (hipHostMalloc((void**)&c->hbuf, 1 << 16) != hipSuccess) throw Fail{MPDO_E_NOMEM, "pinned buffer"};
         if (hipHostMalloc((void**)&c->hint, 256) != hipSuccess) throw Fail{MPDO_E_NOMEM, "pinned buffer"};
@@ -1017,6 +1020,92 @@ static void expect_impl(mpdo_ctx c, int n_terms, const int* first, const int* le
     for (int t = 0; t < n_terms; ++t) {
         zc v(all[2 * t], all[2 * t + 1]);
         if (normalize) v /= zc(trv[0], trv[1]);
+        out[2 * t] = v.real();
+        out[2 * t + 1] = v.imag();
+    }
+}
+
+// Second-order expectation (Fig. 6c): E2 = sum vec(rho)[eta] vec(rho)[eta'] prod_j M_j[eta_j, eta'_j]
+// with the given M_j on atoms f..f+m-1 and vec(I) vec(I)^T (both copies traced) elsewhere, so the
+// environments outside the term are outer products of the cached trace vectors.  An atom's
+// queued single-atom maps P enter as M' = P^T M P.  Per atom three complex GEMMs:
+//   T1[eta][l'][r]  = sum_l  L[l][l'] A[l][eta][r]                 (batch over eta)
+//   T2[l'][eta'][r] = sum_eta M'[eta][eta'] T1[eta][l'][r]           (batch over l')
+//   L'[r][r']       = sum_{l',eta'} T2[l'][eta'][r] A[l'][eta'][r']
+template <typename T>
+static void expect2_impl(mpdo_ctx c, int n_terms, const int* first, const int* len, const double* ops, int normalize,
+                         double* out) {
+    Scratch<T>& s = scratch_of<T>(c);
+    Engine<T> E(*c, s);
+    const int D2 = c->D2;
+    E.ensureL(c->N);
+    std::vector<double> all((size_t)n_terms * 2);
+    size_t opos = 0;
+    T* Mdev = (T*)c->o2buf;
+    for (int t = 0; t < n_terms; ++t) {
+        const int f = first[t], m = len[t];
+        // M' = P^T M P per atom, in T
+        std::vector<T> Mh((size_t)m * D2 * D2 * 2);
+        for (int u = 0; u < m; ++u) {
+            const int j = f + u;
+            const zc* M = (const zc*)(ops + (opos + (size_t)u * D2 * D2) * 2);
+            std::vector<zc> MP((size_t)D2 * D2, zc(0, 0));   // M P
+            for (int a = 0; a < D2; ++a)
+                for (int b = 0; b < D2; ++b) {
+                    zc acc(0, 0);
+                    for (int q = 0; q < D2; ++q) {
+                        const zc pq = c->pend_id[j] ? zc(q == b ? 1 : 0, 0) : c->pending[j][(size_t)q * D2 + b];
+                        acc += M[(size_t)a * D2 + q] * pq;
+                    }
+                    MP[(size_t)a * D2 + b] = acc;
+                }
+            for (int a = 0; a < D2; ++a)
+                for (int b = 0; b < D2; ++b) {
+                    zc acc(0, 0);
+                    for (int q = 0; q < D2; ++q) {
+                        const zc pq = c->pend_id[j] ? zc(q == a ? 1 : 0, 0) : c->pending[j][(size_t)q * D2 + a];
+                        acc += pq * MP[(size_t)q * D2 + b];
+                    }
+                    Mh[2 * ((size_t)u * D2 * D2 + (size_t)a * D2 + b)] = (T)acc.real();
+                    Mh[2 * ((size_t)u * D2 * D2 + (size_t)a * D2 + b) + 1] = (T)acc.imag();
+                }
+        }
+        opos += (size_t)m * D2 * D2;
+        HIPCHK(hipMemcpyAsync(Mdev, Mh.data(), Mh.size() * sizeof(T), hipMemcpyHostToDevice, c->st));
+        E.ensureR(f + m);
+        T* L = s.bA;
+        T* L2 = s.bT1;
+        T* T1 = s.bB;
+        T* T2 = s.bC;
+        HIPCHK(outer<T>(c->st, E.Lv(f), c->dims[f], L));
+        for (int u = 0; u < m; ++u) {
+            const int j = f + u, cl = c->dims[j], cr = c->dims[j + 1];
+            const T* A = E.site(j);
+            const T* Mj = Mdev + 2 * (size_t)u * D2 * D2;
+            E.gemm(cl, cr, cl, C1(), V<T>(L, 1, cl), V<T>((T*)A, (long)D2 * cr, 1), C0(), V<T>(T1, cr, 1), D2, 0, cr,
+                   (long)cl * cr);
+            E.gemm(D2, cr, D2, C1(), V<T>((T*)Mj, 1, D2), V<T>(T1, (long)cl * cr, 1), C0(), V<T>(T2, cr, 1), cl, 0, cr,
+                   (long)D2 * cr);
+            E.gemm(cr, cr, cl * D2, C1(), V<T>(T2, 1, cr), V<T>((T*)A, cr, 1), C0(), V<T>(L2, cr, 1));
+            std::swap(L, L2);
+        }
+        HIPCHK(bilinear<T>(c->st, L, c->dims[f + m], E.Rv(f + m), s.pout + 2 * (t % 16)));
+        if (t % 16 == 15 || t == n_terms - 1) {
+            const int t0 = t - (t % 16);
+            E.read_doubles(s.pout, 2 * (t - t0 + 1), all.data() + 2 * t0);
+        } else {
+            HIPCHK(hipStreamSynchronize(c->st));   // Mdev is rewritten by the next term
+        }
+    }
+    zc tr2(1, 0);
+    if (normalize) {
+        double trv[2];
+        E.read_doubles(E.Lv(c->N), 2, trv);
+        tr2 = zc(trv[0], trv[1]) * zc(trv[0], trv[1]);
+    }
+    for (int t = 0; t < n_terms; ++t) {
+        zc v(all[2 * t], all[2 * t + 1]);
+        if (normalize) v /= tr2;
         out[2 * t] = v.real();
         out[2 * t + 1] = v.imag();
     }
@@ -1292,6 +1381,42 @@ mpdo_status mpdo_expect(mpdo_ctx c, int n_terms, const int* first_site, const in
             expect_impl<float>(c, n_terms, first_site, n_sites_in_term, ops, normalize, out);
         else
             expect_impl<double>(c, n_terms, first_site, n_sites_in_term, ops, normalize, out);
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_expect2(mpdo_ctx c, int n_terms, const int* first_site, const int* n_sites_in_term,
+                         const double* ops, int normalize, double* out) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready) {
+        c->err = "state not initialised";
+        return MPDO_E_STATE;
+    }
+    if (n_terms < 0 || (n_terms > 0 && (!first_site || !n_sites_in_term || !ops || !out))) {
+        c->err = "null argument";
+        return MPDO_E_ARG;
+    }
+    size_t nops = 0;
+    for (int t = 0; t < n_terms; ++t) {
+        if (n_sites_in_term[t] < 1 || first_site[t] < 0 || first_site[t] + n_sites_in_term[t] > c->N) {
+            c->err = "term out of range";
+            return MPDO_E_ARG;
+        }
+        nops += n_sites_in_term[t];
+    }
+    if (!all_finite(ops, nops * c->D2 * c->D2 * 2)) {
+        c->err = "non-finite operator entry";
+        return MPDO_E_ARG;
+    }
+    try {
+        if (c->fp32)
+            expect2_impl<float>(c, n_terms, first_site, n_sites_in_term, ops, normalize, out);
+        else
+            expect2_impl<double>(c, n_terms, first_site, n_sites_in_term, ops, normalize, out);
     } catch (const Fail& f) {
         set_err(c, f);
         return f.st;

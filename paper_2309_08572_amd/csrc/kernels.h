@@ -35,6 +35,14 @@ hipError_t kron_vec(hipStream_t s, const double* x, int na, const double* z, int
 template <typename T>
 hipError_t sumsq(hipStream_t s, CView<T> X, int M, int N, double* out2);
 
+// L[a][b] = x[a] x[b] for the complex FP64 vector x of length n (n x n, row-major, in T).
+template <typename T>
+hipError_t outer(hipStream_t s, const double* x, int n, T* L);
+
+// out[0..1] = sum_{a,b} y[a] L[a][b] y[b] (complex, FP64 accumulation).
+template <typename T>
+hipError_t bilinear(hipStream_t s, const T* L, int n, const double* y, double* out);
+
 // Accept the eigenvalues of one level of the split (see spectrum_cut_kernel).
 hipError_t spectrum_cut(hipStream_t s, const double* lam, int n, int level, double floor2, double noise,
                         double tau, int cap, double* st, int* cnt, double* sig, double* inv);

@@ -501,6 +501,47 @@ __global__ void dot_kernel(const double* __restrict__ x, const double* __restric
     }
 }
 
+// L[a][b] = x[a] x[b] (complex, no conjugation: both factors are the same vec(rho)), n x n
+template <typename T>
+__global__ void outer_kernel(const double* __restrict__ x, int n, T* __restrict__ L) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    const int a = (int)(idx / n), b = (int)(idx - (idx / n) * n);
+    const double ar = x[2 * a], ai = x[2 * a + 1], br = x[2 * b], bi = x[2 * b + 1];
+    L[2 * idx] = (T)(ar * br - ai * bi);
+    L[2 * idx + 1] = (T)(ar * bi + ai * br);
+}
+
+// out = sum_{a,b} y[a] L[a][b] y[b] (complex, FP64 accumulation), one block
+template <typename T>
+__global__ void bilinear_kernel(const T* __restrict__ L, int n, const double* __restrict__ y,
+                                double* __restrict__ out) {
+    __shared__ double pr[256], pi[256];
+    double sr = 0.0, si = 0.0;
+    for (long idx = threadIdx.x; idx < (long)n * n; idx += blockDim.x) {
+        const int a = (int)(idx / n), b = (int)(idx - (idx / n) * n);
+        const double lr = (double)L[2 * idx], li = (double)L[2 * idx + 1];
+        const double yr = y[2 * a] * y[2 * b] - y[2 * a + 1] * y[2 * b + 1];
+        const double yi = y[2 * a] * y[2 * b + 1] + y[2 * a + 1] * y[2 * b];
+        sr += lr * yr - li * yi;
+        si += lr * yi + li * yr;
+    }
+    pr[threadIdx.x] = sr;
+    pi[threadIdx.x] = si;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            pr[threadIdx.x] += pr[threadIdx.x + s];
+            pi[threadIdx.x] += pi[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = pr[0];
+        out[1] = pi[0];
+    }
+}
+
 inline unsigned blocks_for(long n, int bs = 256) {
     long b = (n + bs - 1) / bs;
     if (b < 1) b = 1;
@@ -625,6 +666,19 @@ hipError_t dot(hipStream_t s, const double* x, const double* y, int n, double* o
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t outer(hipStream_t s, const double* x, int n, T* L) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(outer_kernel<T>, dim3(blocks_for((long)n * n)), dim3(256), 0, s, x, n, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bilinear(hipStream_t s, const T* L, int n, const double* y, double* out) {
+    hipLaunchKernelGGL(bilinear_kernel<T>, dim3(1), dim3(256), 0, s, L, n, y, out);
+    return hipGetLastError();
+}
+
 #define MPDO_INST_T(T)                                                                                          \
     template hipError_t phys_left<T>(hipStream_t, const T*, int, int, int, const double*, int, T*);             \
     template hipError_t phys_right<T>(hipStream_t, const T*, int, int, int, const double*, int, T*);            \
@@ -633,6 +687,8 @@ hipError_t dot(hipStream_t s, const double* x, const double* y, int n, double* o
     template hipError_t transfer_right<T>(hipStream_t, const T*, int, int, int, const double*, const double*,   \
                                           double*);                                                             \
     template hipError_t sumsq<T>(hipStream_t, CView<T>, int, int, double*);                                      \
+    template hipError_t outer<T>(hipStream_t, const double*, int, T*);                                          \
+    template hipError_t bilinear<T>(hipStream_t, const T*, int, const double*, double*);                         \
     template hipError_t scale_cols<T>(hipStream_t, CView<T>, int, int, const double*);                          \
     template hipError_t ns_prep<T>(hipStream_t, const T*, int, T*);                                              \
     template hipError_t scale_rows<T>(hipStream_t, T*, int, int, long, const double*);                          \

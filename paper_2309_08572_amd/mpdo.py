@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_
 EXPORTS = (
     "mpdo_create", "mpdo_destroy", "mpdo_workspace_bytes", "mpdo_bind_workspace",
     "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus",
-    "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_trace", "mpdo_bond_dims",
+    "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_expect2", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
     "mpdo_profile_enable", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
 )
@@ -208,6 +208,20 @@ class MPDO:
                                          first.ctypes.data_as(C.POINTER(C.c_int)),
                                          lens.ctypes.data_as(C.POINTER(C.c_int)), _dptr(ops),
                                          int(normalize), _dptr(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def expect2(self, terms, normalize: bool = True) -> np.ndarray:
+        """Second-order terms: list of (first_site, [M_first, M_first+1, ...]), each M a D2 x D2
+        matrix on (eta, eta') of the two copies of vec(rho); other atoms are traced out."""
+        first = np.array([t[0] for t in terms], dtype=np.int32)
+        lens = np.array([len(t[1]) for t in terms], dtype=np.int32)
+        ops = _cplx(np.concatenate([np.stack([np.asarray(o) for o in t[1]]).reshape(-1)
+                                    for t in terms])) if terms else np.zeros(2)
+        out = np.zeros(2 * len(terms), dtype=np.float64)
+        self._check(self.lib.mpdo_expect2(self.ctx, len(terms),
+                                          first.ctypes.data_as(C.POINTER(C.c_int)),
+                                          lens.ctypes.data_as(C.POINTER(C.c_int)), _dptr(ops),
+                                          int(normalize), _dptr(out)))
         return out[0::2] + 1j * out[1::2]
 
     def trace(self) -> complex:

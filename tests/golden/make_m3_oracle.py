@@ -3,8 +3,8 @@ noisy QAOA workload N=100, d=4, chi_max=512, p=3, rates 1e-3, seed 0 (workloads.
 
     python tests/golden/make_m3_oracle.py      # ~4 min on 8 cores
 
-Stores the per-site energy, all per-atom populations, the all-qubit probability, the trace
-and the bond dimensions.  Only oracle/ and workloads/ are used.
+Stores the per-site energy, all per-atom populations, the all-qubit probability, the purity
+tr(rho^2)/tr(rho)^2 (as the vectorised 2-norm), the trace and the bond dimensions.  Only oracle/ and workloads/ are used.
 """
 import json
 import os
@@ -27,6 +27,7 @@ def main():
         "workload": "noisy QAOA N=100 d=4 chi_max=512 p=3 rates 1e-3 seed 0",
         "energy_per_site": float(o["energy_per_site"]),
         "p_success": float(o["p_success"]),
+        "purity": float(o["purity"]),
         "trace": [float(complex(o["trace"]).real), float(complex(o["trace"]).imag)],
         "populations": [[float(x) for x in row] for row in o["populations"]],
         "bond_dims": [int(b) for b in m.bond_dims()],

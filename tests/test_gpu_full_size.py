@@ -62,3 +62,16 @@ def test_m3_fp32_within_1e5_of_stored_oracle():
     print(f"[gpu] fp32 energy err {de:.2e} population err {dp:.2e}", flush=True)
     assert de <= 1e-5
     assert dp <= 1e-5
+
+
+def test_m3_purity_by_swap_transfer_matches_oracle_norm():
+    """Purity at the full-size workload: the GPU's doubled transfer matrix with the swap
+    operator against the oracle's vectorised 2-norm ||vec rho||^2 / tr(rho)^2 (two different
+    formulas of tr(rho^2) for Hermitian rho), FP64 1e-10 relative."""
+    circuits, mpdo = _gpu()
+    o = _golden()
+    spec = config_m3(0)
+    print("[gpu] M3 purity", flush=True)
+    m = circuits.run_circuit(spec)
+    p = circuits.purity(m)
+    assert abs(p - o["purity"]) <= 1e-10 * o["purity"]

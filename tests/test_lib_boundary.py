@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "mpdo.h")
 
 def _declared_symbols():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(mpdo_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mpdo_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
