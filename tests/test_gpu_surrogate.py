@@ -1,0 +1,141 @@
+"""GPU tests of the surrogate network (include/mpdo_mlp.h, through the C ABI) against the FP64
+MLP oracle (oracle/mlp.py), and of what the trained surrogate gains in the QAOA search.
+
+Tolerance of the BF16 products.  Every GEMM rounds its operands to BF16 (8-bit significand,
+relative rounding <= 2^-9 per operand, <= 2^-8 per product) and accumulates in FP32.  The
+error of a layer output relative to the scale of its terms is then about 2^-8 = 3.9e-3, and a
+chain of four such products (three hidden layers) stays below ~4 x 2^-8 = 1.6e-2.  The bars
+are 2e-2 relative (Frobenius) on outputs and 3e-2 on gradients, which pass through one
+more product, with gradient directions within a cosine of 0.999.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [9, 256, 256, 256, 2]
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08572_amd import surrogate
+    return surrogate
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
+
+
+def _cos(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def test_forward_and_parameter_gradient_match_oracle():
+    sur = _gpu()
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    p = mlp.init(WIDTHS, seed=1)
+    x = rng.uniform(-1, 1, size=(300, WIDTHS[0]))     # spans several 64-row tiles and a ragged tail
+    t = rng.standard_normal((300, 2))
+    print("[gpu] mlp forward/grad 9-256-256-256-2, batch 300", flush=True)
+    net = sur.MLP(WIDTHS, max_batch=512)
+    net.set_params(p)
+    y = net.forward(x)
+    y_ref, _ = mlp.forward(p, WIDTHS, x)
+    assert _rel(y, y_ref) <= 2e-2
+    loss, g = net.loss_grad(x, t)
+    loss_ref, g_ref = mlp.loss_and_grad(p, WIDTHS, x, t)
+    assert abs(loss - loss_ref) <= 2e-2 * loss_ref
+    assert _rel(g, g_ref) <= 3e-2
+    assert _cos(g, g_ref) >= 0.999
+    # every layer's weight and bias block separately
+    pos = 0
+    for o, i in mlp.shapes(WIDTHS):
+        for size in (o * i, o):
+            blk = slice(pos, pos + size)
+            assert _rel(g[blk], g_ref[blk]) <= 3e-2, (o, i, size)
+            pos += size
+    net.close()
+
+
+def test_input_gradient_matches_oracle():
+    sur = _gpu()
+    from oracle import mlp
+    rng = np.random.default_rng(2)
+    p = mlp.init(WIDTHS, seed=3)
+    x = rng.uniform(-1, 1, size=(70, WIDTHS[0]))
+    w = np.array([1.0, -0.3])
+    net = sur.MLP(WIDTHS, max_batch=128)
+    net.set_params(p)
+    y, dx = net.input_grad(x, w)
+    y_ref, dx_ref = mlp.input_grad(p, WIDTHS, x, w)
+    assert _rel(y, y_ref) <= 2e-2
+    assert _rel(dx, dx_ref) <= 3e-2
+    assert _cos(dx.reshape(-1), dx_ref.reshape(-1)) >= 0.999
+    net.close()
+
+
+def test_adam_step_matches_oracle_first_step():
+    sur = _gpu()
+    from oracle import mlp
+    rng = np.random.default_rng(4)
+    widths = [9, 64, 64, 2]
+    p = mlp.init(widths, seed=5)
+    x = rng.uniform(-1, 1, size=(128, 9))
+    t = rng.standard_normal((128, 2))
+    net = sur.MLP(widths, max_batch=128)
+    net.set_params(p)
+    lr = 1e-3
+    net.train_step(x, t, lr)
+    p1 = net.get_params().astype(np.float64)
+    _, g = mlp.loss_and_grad(p, widths, x, t)
+    p1_ref, _, _ = mlp.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), step=1, lr=lr)
+    # the first step moves each parameter by ~lr sign(g); compare where g is well above the
+    # BF16 noise of the gradient
+    big = np.abs(g) > 3e-2 * np.max(np.abs(g))
+    np.testing.assert_allclose(p1[big], p1_ref[big], rtol=0, atol=1e-6)
+    assert np.mean(np.abs(p1 - p) > 0.5 * lr) > 0.9
+    net.close()
+
+
+def test_training_fits_a_smooth_function():
+    sur = _gpu()
+    rng = np.random.default_rng(6)
+    widths = [3, 128, 128, 2]
+    x = rng.uniform(-1, 1, size=(2048, 3))
+    t = np.stack([np.sin(2 * x[:, 0]) * x[:, 1], x[:, 2] ** 2 - 0.5 * x[:, 0]], axis=1)
+    net = sur.MLP(widths, max_batch=256, seed=7)
+    first = None
+    for ep in range(60):
+        perm = rng.permutation(2048)
+        tot = 0.0
+        for s in range(0, 2048, 256):
+            idx = perm[s:s + 256]
+            tot += net.train_step(x[idx], t[idx], 3e-3) * len(idx)
+        if first is None:
+            first = tot / 2048
+    last = tot / 2048
+    print(f"[gpu] fit loss {first:.3e} -> {last:.3e}", flush=True)
+    assert last < 2e-2 * first
+    net.close()
+
+
+def test_mlp_rejects_bad_arguments():
+    sur = _gpu()
+    from paper_2309_08572_amd import mpdo
+    net = sur.MLP([4, 8, 2], max_batch=16)
+    bad = np.zeros((4, 4))
+    bad[1, 2] = np.nan
+    with pytest.raises(mpdo.MpdoError):
+        net.forward(bad)
+    x = sur._f32(np.zeros((17, 4)))
+    y = np.zeros((17, 2), dtype=np.float32)
+    assert net.lib.mpdo_mlp_forward(net.h, 17, sur._p(x), sur._p(y)) == 1   # batch above max_batch
+    with pytest.raises(mpdo.MpdoError):
+        net.train_step(np.zeros((4, 4)), np.zeros((4, 2)), -1.0)
+    net.close()

@@ -11,10 +11,11 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mpdo.h")
+MLP_HEADER = os.path.join(ROOT, "include", "mpdo_mlp.h")
 
 
-def _declared_symbols():
-    text = open(HEADER).read()
+def _declared_symbols(path=HEADER):
+    text = open(path).read()
     return sorted(set(re.findall(r"\b(mpdo_[a-z0-9_]+)\s*\(", text)))
 
 
@@ -34,8 +35,28 @@ def test_header_declares_the_paper_calls():
 
 
 def test_every_declared_symbol_is_exported(lib):
-    for name in _declared_symbols():
-        assert hasattr(lib, name), name
+    for path in (HEADER, MLP_HEADER):
+        for name in _declared_symbols(path):
+            assert hasattr(lib, name), name
+
+
+def test_surrogate_binding_covers_its_header(lib):
+    from paper_2309_08572_amd import surrogate
+    assert sorted(surrogate.EXPORTS) == _declared_symbols(MLP_HEADER)
+
+
+def test_mlp_argument_checks_without_gpu(lib):
+    """Size checks happen before any device call."""
+    ip = C.POINTER(C.c_int)
+    h = C.c_void_p()
+    lib.mpdo_mlp_create.argtypes = [C.c_int, ip, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
+    bad_widths = (C.c_int * 3)(4, 0, 2)
+    assert lib.mpdo_mlp_create(2, bad_widths, 8, None, C.byref(h)) == 1
+    ok_widths = (C.c_int * 3)(4, 8, 2)
+    assert lib.mpdo_mlp_create(2, ok_widths, 0, None, C.byref(h)) == 1
+    lib.mpdo_mlp_param_count.argtypes = [C.c_int, ip]
+    lib.mpdo_mlp_param_count.restype = C.c_size_t
+    assert lib.mpdo_mlp_param_count(2, ok_widths) == 8 * 4 + 8 + 2 * 8 + 2
 
 
 def test_binding_covers_header(lib):
