@@ -5,12 +5,20 @@ The network maps (QAOA angles gamma_1..p, beta_1..p, leak, dephasing and decay r
 the simulator's own batched outputs (mpdo_run_batch) by the library's GPU kernels
 (include/mpdo_mlp.h): FP32 weights, BF16 matrix-core products, FP32 accumulation.
 
-Search: minimise the energy per site over the 2p angles at fixed noise rates.
-  plain     Nelder-Mead on the simulator; every function value is one simulator call.
-  guided    the surrogate is minimised from many starts, by input gradients (free); its best
-            proposals are judged by the simulator (one call each); Nelder-Mead on the
-            simulator then refines the best judged point from a small simplex.  The simulator
-            is the judge of every reported value and the fallback when the surrogate is off.
+Every angle enters the circuit through exp(-i gamma Z(x)Z) or exp(-i beta X), which are -1 on
+the qubit levels at angle pi and leave the other levels alone, so the observables are periodic
+with period pi in each angle: the angles live on a torus and enter the network through the
+harmonics sin(2a), cos(2a), sin(4a), cos(4a).
+
+Search: minimise the energy per site over the 2p angles (taken modulo pi) at fixed noise rates.
+Both searches use the same local optimiser on the simulator (BFGS, finite-difference gradients;
+every function value is one simulator call) and restart it from random angles when it stops
+short of the target.  They differ in where the local runs start:
+  plain     from random angles;
+  guided    the surrogate is minimised from many starts by input gradients (no simulator
+            calls); its best distinct proposals are judged by the simulator in one batch, and
+            the local runs start from them, best judged first.  The simulator is the judge of
+            every reported value and the fallback when the surrogate is off.
 
 Nothing here runs without a GPU: the simulator and the network are the HIP library.
 """
@@ -165,17 +173,44 @@ class Task:
 
     @property
     def n_in(self) -> int:
-        return 2 * self.p + 3
+        return 8 * self.p + 3
+
+
+HARMONICS = (2.0, 4.0)   # frequencies of the angle features (period pi and pi/2)
 
 
 def features(task: Task, angles: np.ndarray, rates: np.ndarray) -> np.ndarray:
-    """Inputs in [-1, 1]: angles / (pi/2) - 1 and log-rates mapped from [rate_lo, rate_hi]."""
+    """Network inputs: sin(k a), cos(k a) for k in HARMONICS and every angle, then the log-rates
+    mapped from [rate_lo, rate_hi] to [-1, 1]."""
     angles = np.atleast_2d(angles)
     rates = np.atleast_2d(rates)
-    a = angles / (0.5 * math.pi) - 1.0
+    if rates.shape[0] == 1 and angles.shape[0] > 1:
+        rates = np.repeat(rates, angles.shape[0], axis=0)
+    parts = []
+    for k in HARMONICS:
+        parts += [np.sin(k * angles), np.cos(k * angles)]
     lo, hi = math.log(task.rate_lo), math.log(task.rate_hi)
-    r = 2.0 * (np.log(rates) - lo) / (hi - lo) - 1.0
-    return np.concatenate([a, r], axis=1)
+    parts.append(2.0 * (np.log(rates) - lo) / (hi - lo) - 1.0)
+    return np.concatenate(parts, axis=1)
+
+
+def angle_grad(angles: np.ndarray, dfeat: np.ndarray) -> np.ndarray:
+    """Chain rule of features(): gradient over the angles from the gradient over the inputs."""
+    angles = np.atleast_2d(angles)
+    m = angles.shape[1]
+    g = np.zeros_like(angles)
+    pos = 0
+    for k in HARMONICS:
+        g += dfeat[:, pos:pos + m] * k * np.cos(k * angles)
+        g -= dfeat[:, pos + m:pos + 2 * m] * k * np.sin(k * angles)
+        pos += 2 * m
+    return g
+
+
+def wrap_distance(a, b) -> np.ndarray:
+    """Largest per-angle distance on the torus of period pi."""
+    h = 0.5 * math.pi
+    return np.max(np.abs(np.mod(np.asarray(a) - np.asarray(b) + h, math.pi) - h), axis=-1)
 
 
 def spec_of(task: Task, angles, rates, seed: int = 0):
@@ -187,18 +222,31 @@ def spec_of(task: Task, angles, rates, seed: int = 0):
 
 
 class Simulator:
-    """Batched simulator calls with a counter (each circuit is one call)."""
+    """Simulator calls with a counter (each circuit is one call): one point runs on a context
+    kept for the task, several points go through the batch runtime."""
 
     def __init__(self, task: Task, n_workers: int = 16):
         self.task = task
         self.n_workers = n_workers
         self.calls = 0
+        self._m = None
+
+    def _one(self, a, r) -> np.ndarray:
+        t = self.task
+        if self._m is None:
+            self._m = mpdo.MPDO(t.n, t.d, t.chi)
+        circuits.run_circuit(spec_of(t, a, r), m=self._m)
+        o = circuits.observables(self._m)
+        return np.array([[o["energy_per_site"], o["p_success"]]])
 
     def __call__(self, angles: np.ndarray, rates: np.ndarray) -> np.ndarray:
         angles = np.atleast_2d(angles)
         rates = np.atleast_2d(rates)
         if rates.shape[0] == 1 and angles.shape[0] > 1:
             rates = np.repeat(rates, angles.shape[0], axis=0)
+        if angles.shape[0] == 1:
+            self.calls += 1
+            return self._one(angles[0], rates[0])
         descs = [circuits.describe(spec_of(self.task, a, r)) for a, r in zip(angles, rates)]
         res = mpdo.run_batch(descs, n_workers=min(self.n_workers, len(descs)))
         out = np.zeros((len(descs), 2))
@@ -211,12 +259,17 @@ class Simulator:
         return out
 
 
-def make_dataset(sim: Simulator, count: int, seed: int):
+def make_dataset(sim: Simulator, count: int, seed: int, chunk: int = 2048, log=None):
+    """Uniform angles on [0, pi) and log-uniform rates on [rate_lo, rate_hi], simulated in batches."""
     rng = np.random.default_rng(seed)
     t = sim.task
     angles = rng.uniform(0.0, math.pi, size=(count, 2 * t.p))
     rates = np.exp(rng.uniform(math.log(t.rate_lo), math.log(t.rate_hi), size=(count, 3)))
-    y = sim(angles, rates)
+    y = np.zeros((count, 2))
+    for s in range(0, count, chunk):
+        y[s:s + chunk] = sim(angles[s:s + chunk], rates[s:s + chunk])
+        if log is not None:
+            log("[surrogate] simulated %d of %d circuits" % (min(count, s + chunk), count))
     return features(t, angles, rates), y, angles, rates
 
 
@@ -256,80 +309,113 @@ class Surrogate:
         v = np.zeros_like(a)
         for k in range(1, steps + 1):
             _, dx = self.net.input_grad(features(t, a, r), w)
-            g = dx[:, :2 * t.p] / (0.5 * math.pi)             # chain rule of the feature map
+            g = angle_grad(a, dx.astype(np.float64))
             m = 0.9 * m + 0.1 * g
             v = 0.999 * v + 0.001 * g * g
             a = a - lr * (m / (1 - 0.9 ** k)) / (np.sqrt(v / (1 - 0.999 ** k)) + 1e-8)
-            a = np.clip(a, 0.0, math.pi)
+        a = np.mod(a, math.pi)
         e = self.predict(a, r)[:, 0]
         order = np.argsort(e)
         return a[order], e[order]
 
+    def proposals(self, rates, count: int, sep: float = 0.25, seed: int = 0) -> np.ndarray:
+        """The best `count` surrogate minima that differ by more than `sep` rad in some angle."""
+        cand, _ = self.minimise_energy(rates, seed=seed)
+        picks = []
+        for a in cand:
+            if all(wrap_distance(a, b) > sep for b in picks):
+                picks.append(a)
+            if len(picks) == count:
+                break
+        return np.array(picks)
+
 
 # ------------------------------------------------------------------------ searches
-def _nelder_mead(f, x0, scale, budget: int, target: float, xatol: float = 1e-4):
-    """Nelder-Mead on f (one simulator call per value); stops at the budget or once the best
-    value is <= target.  Returns (best_x, best_f, history of best values by call)."""
+class _Stop(Exception):
+    pass
+
+
+class Tracker:
+    """Counts simulator calls of one search and keeps the best value after each call."""
+
+    def __init__(self, sim: Simulator, rates, budget: int, target: float):
+        self.sim, self.rates, self.budget, self.target = sim, np.asarray(rates, dtype=float), budget, target
+        self.history = []
+        self.best_x, self.best = None, float("inf")
+
+    def done(self) -> bool:
+        return len(self.history) >= self.budget or self.best <= self.target
+
+    def record(self, xs, values):
+        for x, v in zip(xs, values):
+            if v < self.best:
+                self.best_x, self.best = np.mod(x, math.pi), float(v)
+            self.history.append(self.best)
+
+    def batch(self, xs) -> np.ndarray:
+        xs = np.mod(np.atleast_2d(xs), math.pi)[: max(0, self.budget - len(self.history))]
+        vals = self.sim(xs, self.rates)[:, 0] if len(xs) > 1 else \
+            np.array([self.sim(xs[0], self.rates)[0, 0]]) if len(xs) else np.zeros(0)
+        self.record(xs, vals)
+        return vals
+
+    def __call__(self, x) -> float:
+        if self.done():
+            raise _Stop
+        return float(self.batch(x)[0])
+
+
+def local_search(tr: Tracker, x0, gtol: float = 1e-7, fd_step: float = 1e-6):
+    """BFGS on the simulator from x0, stopping at the tracker's budget or target.  The gradient
+    is a forward difference: the point and its 2p shifted copies are one batch of simulator
+    calls (each circuit counts as one call)."""
     from scipy.optimize import minimize
-    hist = []
-    best = [None, float("inf")]
+    eye = np.eye(len(x0)) * fd_step
 
-    class Done(Exception):
-        pass
+    def value_and_grad(x):
+        if tr.done():
+            raise _Stop
+        pts = np.vstack([x, x + eye])
+        vals = tr.batch(pts)
+        if len(vals) < len(pts):
+            raise _Stop
+        return float(vals[0]), (vals[1:] - vals[0]) / fd_step
 
-    def fw(x):
-        if len(hist) >= budget:
-            raise Done
-        x = np.clip(x, 0.0, math.pi)
-        v = float(f(x))
-        if v < best[1]:
-            best[0], best[1] = x.copy(), v
-        hist.append(best[1])
-        if best[1] <= target:
-            raise Done
-        return v
-
-    dim = len(x0)
-    simplex = np.vstack([x0] + [x0 + scale * np.eye(dim)[i] for i in range(dim)])
     try:
-        minimize(fw, x0, method="Nelder-Mead",
-                 options={"initial_simplex": simplex, "xatol": xatol, "fatol": 1e-7, "maxfev": budget})
-    except Done:
+        minimize(value_and_grad, np.asarray(x0, dtype=float), jac=True, method="BFGS",
+                 options={"gtol": gtol, "maxiter": 10 ** 6})
+    except _Stop:
         pass
-    return best[0], best[1], hist
 
 
-def plain_search(sim: Simulator, rates, budget: int, target: float = -np.inf, seed: int = 0):
+def plain_search(sim: Simulator, rates, budget: int, target: float = -np.inf, seed: int = 0,
+                 log=None) -> dict:
+    """Local runs from random angles until the target or the budget is reached."""
     rng = np.random.default_rng(seed)
-    x0 = rng.uniform(0.0, math.pi, size=2 * sim.task.p)
-    start = sim.calls
-    x, e, hist = _nelder_mead(lambda a: sim(a, rates)[0, 0], x0, 0.4, budget, target)
-    return {"x": x, "energy": e, "calls": sim.calls - start, "history": hist}
+    tr = Tracker(sim, rates, budget, target)
+    while not tr.done():
+        local_search(tr, rng.uniform(0.0, math.pi, size=2 * sim.task.p))
+        if log is not None:
+            log("[surrogate]     plain: %d calls, best %.7f" % (len(tr.history), tr.best))
+    return {"x": tr.best_x, "energy": tr.best, "calls": len(tr.history), "history": tr.history}
 
 
 def guided_search(sim: Simulator, sur: Surrogate, rates, budget: int, target: float = -np.inf,
-                  proposals: int = 4, seed: int = 0):
-    start = sim.calls
-    cand, pred = sur.minimise_energy(rates, seed=seed)
-    # distinct proposals (angles differing by more than 0.05 rad somewhere)
-    picks = []
-    for a in cand:
-        if all(np.max(np.abs(a - b)) > 0.05 for b in picks):
-            picks.append(a)
-        if len(picks) == proposals:
-            break
-    judged = sim(np.array(picks), rates)[:, 0]          # the simulator judges the proposals
-    hist = list(np.minimum.accumulate(judged))
-    i = int(np.argmin(judged))
-    x0, e0 = picks[i], float(judged[i])
-    res = {"x": x0, "energy": e0, "proposal_error": float(abs(judged[i] - sur.predict(x0, rates)[0, 0]))}
-    if e0 > target and budget > len(picks):
-        x, e, h = _nelder_mead(lambda a: sim(a, rates)[0, 0], x0, 0.05, budget - len(picks), target)
-        if e < e0:
-            res["x"], res["energy"] = x, e
-        hist += [min(hist[-1], v) for v in h]
-    res["calls"] = sim.calls - start
-    res["history"] = hist
+                  proposals: int = 4, seed: int = 0, log=None) -> dict:
+    """Surrogate proposals judged in one batch, local runs from them (best judged first), then
+    the plain search's random restarts if the target is still not reached."""
+    tr = Tracker(sim, rates, budget, target)
+    picks = sur.proposals(rates, proposals, seed=seed)
+    judged = tr.batch(picks)
+    pred = sur.predict(picks, rates)[:, 0]
+    res = {"proposal_max_abs_err": float(np.max(np.abs(judged - pred[:len(judged)]))) if len(judged) else None}
+    rng = np.random.default_rng(seed)
+    starts = [picks[i] for i in np.argsort(judged)]
+    while not tr.done():
+        local_search(tr, starts.pop(0) if starts else rng.uniform(0.0, math.pi, size=2 * sim.task.p))
+        if log is not None:
+            log("[surrogate]     guided: %d calls, best %.7f" % (len(tr.history), tr.best))
+    res.update({"x": tr.best_x, "energy": tr.best, "calls": len(tr.history), "history": tr.history})
     return res
 
 
@@ -340,42 +426,55 @@ def calls_to_reach(hist, target: float) -> Optional[int]:
     return None
 
 
-def experiment(task: Task, n_data: int, epochs: int, rates, budget: int, seed: int = 0,
-               widths=None, n_workers: int = 16) -> dict:
-    """Dataset -> training -> reference optimum -> calls of the plain and guided searches."""
+def experiment(task: Task, n_data: int, epochs: int, rate_sets, budget: int, runs: int = 3,
+               proposals: int = 4, seed: int = 0, widths=None, n_workers: int = 16, log=print) -> dict:
+    """Dataset -> training -> for each noise setting: reference optimum, then the simulator calls
+    the plain and the guided search need to come within 1e-3 of it."""
+    def say(msg):
+        log("[surrogate] " + msg)
+
     t0 = time.time()
     sim = Simulator(task, n_workers)
-    X, Y, _, _ = make_dataset(sim, n_data, seed)
+    X, Y, _, _ = make_dataset(sim, n_data, seed, log=log)
     t_data = time.time() - t0
+    say("dataset of %d circuits in %.1f s" % (n_data, t_data))
     widths = widths or [task.n_in, 256, 256, 256, 2]
     net = MLP(widths, max_batch=1024, seed=seed)
     t0 = time.time()
     mu, sd, hist = train(net, X, Y, epochs=epochs, seed=seed)
     t_train = time.time() - t0
+    say("trained %d epochs in %.1f s, loss %.3e" % (epochs, t_train, hist[-1]))
     sur = Surrogate(net, task, mu, sd)
-    # held-out error
-    Xt, Yt, at, rt = make_dataset(Simulator(task, n_workers), 256, seed + 1)
-    pred = sur.predict(at, rt)
-    err = np.abs(pred - Yt).max(axis=0)
-    rates = np.asarray(rates, dtype=float)
-    # reference optimum: the best of long plain searches and of the guided search's best point
-    ref = []
-    for s in range(3):
-        ref.append(plain_search(Simulator(task, n_workers), rates, budget=4 * budget, seed=100 + s)["energy"])
-    g_ref = guided_search(Simulator(task, n_workers), sur, rates, budget=4 * budget, seed=seed)
-    e_star = min(min(ref), g_ref["energy"])
-    target = e_star + 1e-3
-    plain_calls, guided_calls = [], []
-    for s in range(3):
-        pr = plain_search(Simulator(task, n_workers), rates, budget=budget, target=target, seed=200 + s)
-        gr = guided_search(Simulator(task, n_workers), sur, rates, budget=budget, target=target, seed=300 + s)
-        plain_calls.append(calls_to_reach(pr["history"], target))
-        guided_calls.append(calls_to_reach(gr["history"], target))
-    return {"task": task.__dict__, "rates": rates.tolist(), "n_data": n_data, "data_seconds": t_data,
-            "train_seconds": t_train, "final_train_loss": hist[-1], "heldout_max_abs_err": err.tolist(),
-            "optimum_energy_per_site": e_star, "target": target, "budget": budget,
-            "plain_calls": plain_calls, "guided_calls": guided_calls,
-            "simulator_calls_for_data": n_data}
+    _, Yt, at, rt = make_dataset(Simulator(task, n_workers), 256, seed + 1)
+    err = np.abs(sur.predict(at, rt) - Yt)
+    say("held-out |error|: energy rms %.2e max %.2e, success max %.2e"
+        % (math.sqrt(np.mean(err[:, 0] ** 2)), err[:, 0].max(), err[:, 1].max()))
+    out = {"task": task.__dict__, "n_data": n_data, "epochs": epochs, "widths": widths,
+           "data_seconds": t_data, "train_seconds": t_train, "final_train_loss": hist[-1],
+           "heldout_rms_err_energy": float(math.sqrt(np.mean(err[:, 0] ** 2))),
+           "heldout_max_abs_err": err.max(axis=0).tolist(), "budget": budget, "searches": []}
+    for rates in rate_sets:
+        rates = np.asarray(rates, dtype=float)
+        # every run spends its whole budget; the optimum is the best value any run found, and
+        # each run is scored by the calls it needed to come within 1e-3 of it
+        runs_p, runs_g = [], []
+        for s in range(runs):
+            runs_p.append(plain_search(Simulator(task, n_workers), rates, budget, seed=200 + s, log=log))
+            runs_g.append(guided_search(Simulator(task, n_workers), sur, rates, budget, proposals=proposals,
+                                        seed=300 + s, log=log))
+            say("rates %s run %d: plain best %.7f, guided best %.7f"
+                % (rates.tolist(), s, runs_p[-1]["energy"], runs_g[-1]["energy"]))
+        e_star = min(r["energy"] for r in runs_p + runs_g)
+        target = e_star + 1e-3
+        pc = [calls_to_reach(r["history"], target) for r in runs_p]
+        gc = [calls_to_reach(r["history"], target) for r in runs_g]
+        say("rates %s: optimum %.7f; calls to within 1e-3: plain %s, guided %s" % (rates.tolist(), e_star, pc, gc))
+        out["searches"].append({"rates": rates.tolist(), "optimum_energy_per_site": e_star, "target": target,
+                                "plain_calls": pc, "guided_calls": gc,
+                                "plain_best": [r["energy"] for r in runs_p],
+                                "guided_best": [r["energy"] for r in runs_g],
+                                "proposal_max_abs_err": [r["proposal_max_abs_err"] for r in runs_g]})
+    return out
 
 
 def main():
@@ -385,12 +484,17 @@ def main():
     ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--data", type=int, default=2048)
     ap.add_argument("--epochs", type=int, default=200)
-    ap.add_argument("--budget", type=int, default=400)
+    ap.add_argument("--budget", type=int, default=1500)
+    ap.add_argument("--runs", type=int, default=3)
+    ap.add_argument("--rates", type=float, nargs=3, action="append",
+                    help="noise setting (leak, dephasing, decay); repeat for several")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     task = Task(n=a.n, p=a.p, chi=a.chi)
-    res = experiment(task, a.data, a.epochs, rates=[1e-3, 1e-3, 1e-3], budget=a.budget, seed=a.seed)
+    rate_sets = a.rates or [[1e-3, 1e-3, 1e-3]]
+    res = experiment(task, a.data, a.epochs, rate_sets, budget=a.budget, runs=a.runs, seed=a.seed,
+                     log=lambda m: print(m, flush=True))
     line = json.dumps(res)
     print(line)
     if a.out:
