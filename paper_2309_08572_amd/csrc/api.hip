@@ -16,6 +16,7 @@
 //  6. the isometric factor and the rescaled centre factor become the new site tensors.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -87,6 +88,7 @@ struct Scratch {
     int nmax = 0;        // largest matrix side handled
     T *bA, *bB, *bT1, *bQ, *bK, *bC, *bR, *bU, *bB2, *bG, *bZ, *bW, *bVT, *bQ2, *bK2, *bU2;
     double *Gd, *Vd, *evals, *sig, *inv, *st, *sums, *lvec, *rvec, *tl, *tr, *fac, *pout, *sc, *vtmp, *vtmp2;
+    double* odev;   // ||Q||_F^2 and non-finite count of recent orthonormal bases (64 pairs)
     int* cnt;
     void* eigwork;
 
@@ -95,7 +97,7 @@ struct Scratch {
         size_t b = 0;
         b += 16 * (n2 * sizeof(T) + 256);
         b += 2 * (n2 * sizeof(double) + 256);
-        b += 14 * ((size_t)nmax * 2 * sizeof(double) + 256) + 4096;
+        b += 14 * ((size_t)nmax * 2 * sizeof(double) + 256) + 4096 + 2048;
         b += eigh_work_bytes(nmax) + 256;
         return b;
     }
@@ -134,6 +136,7 @@ struct Scratch {
         sums = a.take<double>(64);
         pout = a.take<double>(64);
         sc = a.take<double>(64);
+        odev = a.take<double>(128);
         cnt = a.take<int>(64);
         eigwork = (void*)a.take<char>(eigh_work_bytes(n));
     }
@@ -363,6 +366,44 @@ struct Engine {
     // relative eigenvalue noise of a Gram matrix of order n formed in this precision
     double noise_of(int n) const { return std::max(64.0, 4.0 * n) * eps(); }
 
+    // Every orthonormal basis the split builds is checked: ||Q||_F^2 of its q columns is reduced
+    // on the device (orth_check) and compared with q at the end of the update (orth_verify, one
+    // read for all of them).  A basis off by more than 1e-9 (FP64) or 1e-3 (FP32), or with
+    // non-finite entries, means the eigenvectors it came from were not accurate enough for the
+    // range refinement and Newton-Schulz steps: the update fails with E_NUMERIC instead of
+    // writing a wrong state.  MPDO_DEBUG_CHECKS=1 prints every check to stderr.
+    static constexpr int NCHK = 64;
+    int nchk = 0;
+    int chk_q[NCHK], chk_order[NCHK], chk_level[NCHK];
+    const char* chk_stage[NCHK];
+    void orth_check(const char* stage, T* Q, long ldq, int n, int q, int level, int order) {
+        if (q <= 0) return;
+        if (nchk == NCHK) orth_verify();
+        HIPCHK(sumsq<T>(st, V<T>(Q, ldq, 1), n, q, s.odev + 2 * nchk));
+        chk_q[nchk] = q;
+        chk_order[nchk] = order;
+        chk_level[nchk] = level;
+        chk_stage[nchk] = stage;
+        ++nchk;
+    }
+    void orth_verify() {
+        static const int dbg = getenv("MPDO_DEBUG_CHECKS") != nullptr;
+        if (nchk == 0) return;
+        const int m = nchk;
+        nchk = 0;
+        double buf[2 * NCHK];
+        read_doubles(s.odev, 2 * m, buf);
+        const double tol = std::is_same<T, double>::value ? 1e-9 : 1e-3;
+        for (int k = 0; k < m; ++k) {
+            const double dev = buf[2 * k] / chk_q[k] - 1.0;
+            if (dbg)
+                fprintf(stderr, "[mpdo check] %s level %d order %d cols %d |Q|^2/q - 1 = %.3e nonfinite %g\n",
+                        chk_stage[k], chk_level[k], chk_order[k], chk_q[k], dev, buf[2 * k + 1]);
+            if (buf[2 * k + 1] != 0.0 || !(fabs(dev) <= tol))
+                throw Fail{MPDO_E_NUMERIC, "orthonormal basis lost accuracy in the split (eigensolver accuracy)"};
+        }
+    }
+
     // Newton-Schulz: make the n x q columns of Q (view, dense storage in buffer with ld) orthonormal
     void ns_orth(T* Q, long ldq, int n, int q, int iters) {
         for (int it = 0; it < iters; ++it) {
@@ -402,6 +443,7 @@ struct Engine {
                 gemm(n, acc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Qn, cc, 1));
             }
             ns_orth(Qn, cc, n, acc, 3);
+            orth_check("orth2", Qn, cc, n, acc, lev, cc);
             gemm(acc, cc, n, C1(), adj(V<T>(Qn, cc, 1)), F, C0(), V<T>(Kb + 2 * (long)q * cc, cc, 1));
             q += acc;
             if (q >= qmax || lev == 2) break;
@@ -454,6 +496,7 @@ struct Engine {
                 gemm(a, acc, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Vn, ldu, 1));
             }
             ns_orth(Vn, ldu, a, acc, 3);
+            orth_check("split", Vn, ldu, a, acc, lev, a);
             kacc += acc;
             if (kacc >= chi || kacc >= a || lev == 2) break;
             // residual R = F - U (U^H F)
@@ -667,6 +710,7 @@ struct Engine {
             HIPCHK(scale_rows<T>(st, Right, kept, nR, nR, s.fac));
         else
             HIPCHK(scale_cols<T>(st, V<T>(Left, kept, 1), nL, kept, s.fac));
+        orth_verify();   // before the new sites are committed
         swap_site(i, 0);
         swap_site(i + 1, 1);
         c.dims[i + 1] = kept;
@@ -866,6 +910,7 @@ GateFactor factorize(mpdo_ctx c, const std::vector<zc>& S) {
     upload(c, g.bA, R.data(), R.size() * sizeof(zc));
     Engine<double> E(*c, g);
     const int r = E.orth2(V<double>(g.bA, m2, 1), m2, m2, g.bQ, g.bK);
+    E.orth_verify();
     GateFactor gf;
     gf.r = r;
     if (r > MAX_FACTOR_RANK || r <= 0) {

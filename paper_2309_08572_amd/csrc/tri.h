@@ -6,7 +6,7 @@
 namespace mpdo {
 
 // Largest order the tridiagonal solver takes (one workgroup holds its vectors in LDS).
-constexpr int TRI_MAX = 512;
+constexpr int TRI_MAX = 1024;
 
 // Device scratch bytes eigh_top() needs for order n (n <= TRI_MAX).
 size_t tri_work_bytes(int n);

@@ -26,8 +26,10 @@ namespace {
 
 constexpr int TB = 1024;      // threads of the one-workgroup kernels
 constexpr int NW = TB / 64;   // waves
-constexpr int BK_COLS = 8;    // columns per back-transform workgroup
+constexpr int BK_COLS = 4;    // columns per back-transform workgroup (LDS: (BK_COLS + 3) x 16 TRI_MAX bytes)
 constexpr int BK_THREADS = 256;
+constexpr int BK_LANES = BK_THREADS / BK_COLS;   // lanes per column (one wave)
+static_assert(BK_LANES == 64, "one wave per back-transform column");
 constexpr double EPS = 2.220446049250313e-16;
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -816,7 +818,7 @@ __global__ __launch_bounds__(TB) void tri_mgs_kernel(int n, const int* __restric
 }
 
 // ------------------------------------------------------------------ back-transform
-// V[:, k] = H_0 ... H_{n-2} z_k for k < cnt[0]; workgroup b owns columns [8b, 8b+8).  The
+// V[:, k] = H_0 ... H_{n-2} z_k for k < cnt[0]; workgroup b owns columns [BK_COLS b, BK_COLS (b+1)).  The
 // reflector of the next step is loaded into registers while the current one is applied.
 __global__ __launch_bounds__(BK_THREADS) void tri_back_kernel(const double* __restrict__ refl,
                                                               const double* __restrict__ tau, int n,
@@ -838,7 +840,7 @@ __global__ __launch_bounds__(BK_THREADS) void tri_back_kernel(const double* __re
         zb[c][2 * i] = c < kc ? Z[(long)(k0 + c) * n + i] : 0.0;
         zb[c][2 * i + 1] = 0.0;
     }
-    const int c = tid >> 5, part = tid & 31;   // 32 lanes per column
+    const int c = tid / BK_LANES, part = tid % BK_LANES;
     // reflector j occupies refl[2 j n .. 2 j n + 2 (n-1-j))
     double pf[PF];
     auto fetch = [&](int j) {
@@ -866,20 +868,20 @@ __global__ __launch_bounds__(BK_THREADS) void tri_back_kernel(const double* __re
             double sr = 0.0, si = 0.0;
             const double* zc = &zb[c][2 * (j + 1)];
             const double* vv = vb[buf];
-            for (int i = part; i < L; i += 32) {
+            for (int i = part; i < L; i += BK_LANES) {
                 const double vr = vv[2 * i], vi = vv[2 * i + 1], zr = zc[2 * i], zi = zc[2 * i + 1];
                 sr += vr * zr + vi * zi;
                 si += vr * zi - vi * zr;
             }
 #pragma unroll
-            for (int o = 16; o > 0; o >>= 1) {
+            for (int o = BK_LANES / 2; o > 0; o >>= 1) {
                 sr += __shfl_xor(sr, o, 64);
                 si += __shfl_xor(si, o, 64);
             }
             // z -= tau s v
             const double fr = tr * sr - ti * si, fi = tr * si + ti * sr;
             double* zw = &zb[c][2 * (j + 1)];
-            for (int i = part; i < L; i += 32) {
+            for (int i = part; i < L; i += BK_LANES) {
                 const double vr = vv[2 * i], vi = vv[2 * i + 1];
                 zw[2 * i] -= fr * vr - fi * vi;
                 zw[2 * i + 1] -= fr * vi + fi * vr;
