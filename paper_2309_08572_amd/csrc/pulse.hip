@@ -1,0 +1,253 @@
+// Pulse-level two-atom channel (gfx950, FP64): Trotterised Lindblad evolution of the basis
+// inputs |a><b| of a pair of atoms through one laser pulse (Sec. II; Sec. III.A).
+//
+//   pulse_drive_kernel   one thread per step: the single-atom propagator exp(-i tau H) on the
+//                        {|1>, |r>} block in closed form (the other levels are untouched)
+//   pulse_evolve_kernel  one workgroup per basis input |a><b|, one thread per entry of the
+//                        pair's density matrix (d^4 <= 256), the matrix held in LDS through all
+//                        steps.  Per step two passes, each ended by a barrier:
+//                          1. dissipators of both atoms and the blockade phase, entry-wise:
+//                             an entry keeps a decay/dephasing factor and, on a sink's diagonal,
+//                             receives the r-r entry it is fed from;
+//                          2. conjugation by u (x) u, u mixing only |1> and |r>: at most 16
+//                             terms per entry.
+//
+// Dissipators in closed form (each is the exact exponential of its generator).  Decay r -> j
+// with rate k_j = gamma b_j: rho_rr *= e_j, rho_jj += (1 - e_j) rho_rr, coherences with one r
+// index *= sqrt(e_j), e_j = exp(-k_j tau); applied for j = 0, 1, dark in that order, the step
+// keeps E = e_0 e_1 e_dark of rho_rr and moves (1 - e_0), e_0 (1 - e_1), e_0 e_1 (1 - e_dark)
+// of it to 0, 1, dark.  Dephasing multiplies rho_01 by exp(-g^2 tau) and a coherence between a
+// qubit level and r or dark by exp(-g^2 tau / 4), g = gamma_deph; populations stay.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "../../include/mpdo_pulse.h"
+
+namespace {
+
+constexpr int LR = 2;      // Rydberg level
+constexpr int LDARK = 3;   // dark level (d = 4)
+constexpr int EVOLVE_THREADS = 256;
+
+thread_local std::string g_err;
+
+// per step: u11, u1r (= ur1), urr as re/im pairs
+__global__ __launch_bounds__(256) void pulse_drive_kernel(const double* __restrict__ om, const double* __restrict__ de,
+                                                          int n, double tau, double* __restrict__ tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double O = om[k], D = de[k];
+    // exp(-i tau M), M = [[0, O/2], [O/2, D]] on (|1>, |r>):
+    //   = exp(-i tau D/2) [cos(w tau) I - i sin(w tau)/w (M - D/2 I)],  w = sqrt(O^2 + D^2) / 2
+    const double w = 0.5 * sqrt(O * O + D * D);
+    const double c = cos(w * tau);
+    const double s = w > 0.0 ? sin(w * tau) / w : tau;
+    const double pr = cos(0.5 * D * tau), pi = -sin(0.5 * D * tau);
+    // a11 = c + i s D/2, a1r = -i s O/2, arr = c - i s D/2; u = phase * a
+    const double a11r = c, a11i = 0.5 * s * D;
+    const double a1ri = -0.5 * s * O;
+    const double arrr = c, arri = -0.5 * s * D;
+    double* t = tab + 6 * (long)k;
+    t[0] = pr * a11r - pi * a11i;
+    t[1] = pr * a11i + pi * a11r;
+    t[2] = -pi * a1ri;
+    t[3] = pr * a1ri;
+    t[4] = pr * arrr - pi * arri;
+    t[5] = pr * arri + pi * arrr;
+}
+
+struct SiteNoise {
+    double sqrtE;      // survival of one r index per step
+    double tr[4];      // transfer into level j's population (0 for non-sinks)
+    double dq;         // dephasing of a 0-1 coherence
+    double dh;         // dephasing of a qubit / (r or dark) coherence
+};
+
+__device__ inline double site_factor(const SiteNoise& z, int x, int y) {
+    double f = 1.0;
+    if (x == LR) f *= z.sqrtE;
+    if (y == LR) f *= z.sqrtE;
+    const bool qx = x < 2, qy = y < 2;
+    if (qx && qy && x != y) f *= z.dq;
+    else if (qx != qy) f *= z.dh;
+    return f;
+}
+
+template <int DL>
+__global__ __launch_bounds__(EVOLVE_THREADS) void pulse_evolve_kernel(const double* __restrict__ tab, int n,
+                                                                      double tau, double blockade, SiteNoise z,
+                                                                      double* __restrict__ out) {
+    constexpr int DIM = DL * DL;   // pair Hilbert dimension
+    constexpr int NE = DIM * DIM;  // entries of rho = basis inputs = superoperator order
+    static_assert(NE <= EVOLVE_THREADS, "one thread per entry");
+    __shared__ double sr[2][NE], si[2][NE];
+    const int col = blockIdx.x;
+    const int a = col / DIM, b = col - (col / DIM) * DIM;
+    const int t = threadIdx.x;
+    const bool act = t < NE;
+    const int x = act ? t / DIM : 0, y = act ? t - (t / DIM) * DIM : 0;
+    const int x1 = x / DL, x2 = x - (x / DL) * DL, y1 = y / DL, y2 = y - (y / DL) * DL;
+    if (act) {
+        sr[0][t] = (x == a && y == b) ? 1.0 : 0.0;
+        si[0][t] = 0.0;
+    }
+    // pass-1 constants
+    const double f1 = site_factor(z, x1, y1), f2 = site_factor(z, x2, y2);
+    const double t1 = (x1 == y1) ? z.tr[x1] : 0.0, t2 = (x2 == y2) ? z.tr[x2] : 0.0;
+    const int src1 = (LR * DL + x2) * DIM + (LR * DL + y2);
+    const int src2 = (x1 * DL + LR) * DIM + (y1 * DL + LR);
+    const int src12 = (LR * DL + LR) * DIM + (LR * DL + LR);
+    const int rr = LR * DL + LR;
+    const double bph = -tau * blockade * ((x == rr ? 1.0 : 0.0) - (y == rr ? 1.0 : 0.0));
+    const double bc = cos(bph), bs = sin(bph);
+    // pass-2 partners: level l in {1, r} mixes with the other one of the pair
+    const bool m1x = x1 == 1 || x1 == LR, m2x = x2 == 1 || x2 == LR;
+    const bool m1y = y1 == 1 || y1 == LR, m2y = y2 == 1 || y2 == LR;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        // ---- pass 1: dissipators of both atoms, then the blockade phase (buffer 0 -> 1)
+        if (act) {
+            double vr = f1 * f2 * sr[0][t], vi = f1 * f2 * si[0][t];
+            if (t1 != 0.0) {
+                vr += t1 * f2 * sr[0][src1];
+                vi += t1 * f2 * si[0][src1];
+            }
+            if (t2 != 0.0) {
+                vr += f1 * t2 * sr[0][src2];
+                vi += f1 * t2 * si[0][src2];
+            }
+            if (t1 != 0.0 && t2 != 0.0) {
+                vr += t1 * t2 * sr[0][src12];
+                vi += t1 * t2 * si[0][src12];
+            }
+            sr[1][t] = bc * vr - bs * vi;
+            si[1][t] = bc * vi + bs * vr;
+        }
+        __syncthreads();
+        // ---- pass 2: rho <- (u (x) u) rho (u (x) u)^+ (buffer 1 -> 0)
+        if (act) {
+            const double* u = tab + 6 * (long)k;
+            // u[l][l'] for l, l' in {1, r}: u11, u1r, ur1 = u1r, urr
+            const double ur[2][2] = {{u[0], u[2]}, {u[2], u[4]}};
+            const double ui[2][2] = {{u[1], u[3]}, {u[3], u[5]}};
+            const int nx1 = m1x ? 2 : 1, nx2 = m2x ? 2 : 1, ny1 = m1y ? 2 : 1, ny2 = m2y ? 2 : 1;
+            double accr = 0.0, acci = 0.0;
+            for (int p1 = 0; p1 < nx1; ++p1) {
+                const int xs1 = m1x ? (p1 == 0 ? 1 : LR) : x1;
+                const double c1r = m1x ? ur[x1 == LR][p1] : 1.0, c1i = m1x ? ui[x1 == LR][p1] : 0.0;
+                for (int p2 = 0; p2 < nx2; ++p2) {
+                    const int xs2 = m2x ? (p2 == 0 ? 1 : LR) : x2;
+                    const double c2r = m2x ? ur[x2 == LR][p2] : 1.0, c2i = m2x ? ui[x2 == LR][p2] : 0.0;
+                    const double cxr = c1r * c2r - c1i * c2i, cxi = c1r * c2i + c1i * c2r;
+                    const int xs = xs1 * DL + xs2;
+                    for (int q1 = 0; q1 < ny1; ++q1) {
+                        const int ys1 = m1y ? (q1 == 0 ? 1 : LR) : y1;
+                        const double d1r = m1y ? ur[y1 == LR][q1] : 1.0, d1i = m1y ? -ui[y1 == LR][q1] : 0.0;
+                        for (int q2 = 0; q2 < ny2; ++q2) {
+                            const int ys2 = m2y ? (q2 == 0 ? 1 : LR) : y2;
+                            const double d2r = m2y ? ur[y2 == LR][q2] : 1.0, d2i = m2y ? -ui[y2 == LR][q2] : 0.0;
+                            const double dyr = d1r * d2r - d1i * d2i, dyi = d1r * d2i + d1i * d2r;
+                            const double cr = cxr * dyr - cxi * dyi, ci = cxr * dyi + cxi * dyr;
+                            const int e = xs * DIM + (ys1 * DL + ys2);
+                            const double rr_ = sr[1][e], ri_ = si[1][e];
+                            accr += cr * rr_ - ci * ri_;
+                            acci += cr * ri_ + ci * rr_;
+                        }
+                    }
+                }
+            }
+            sr[0][t] = accr;
+            si[0][t] = acci;
+        }
+        __syncthreads();
+    }
+    if (act) {
+        // per-atom layout: row (x1 d + y1) D2 + (x2 d + y2), column likewise from (a, b)
+        const int a1 = a / DL, a2 = a - (a / DL) * DL, b1 = b / DL, b2 = b - (b / DL) * DL;
+        const long row = (long)(x1 * DL + y1) * DIM + (x2 * DL + y2);
+        const long cidx = (long)(a1 * DL + b1) * DIM + (a2 * DL + b2);
+        out[2 * (row * NE + cidx)] = sr[0][t];
+        out[2 * (row * NE + cidx) + 1] = si[0][t];
+    }
+}
+
+bool finite_all(const double* p, long n) {
+    for (long i = 0; i < n; ++i)
+        if (!isfinite(p[i])) return false;
+    return true;
+}
+
+mpdo_status fail(mpdo_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+}  // namespace
+
+extern "C" mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* p, const double* omega, const double* delta,
+                                          double* superop, void* hip_stream) {
+    if (!p || !omega || !delta || !superop) return fail(MPDO_E_ARG, "null pointer");
+    const int d = p->d, n = p->n_steps;
+    if (d != 3 && d != 4) return fail(MPDO_E_ARG, "d must be 3 or 4");
+    if (n < 1) return fail(MPDO_E_ARG, "n_steps must be >= 1");
+    const double rates[7] = {p->tau, p->blockade, p->gamma_diss, p->branch[0], p->branch[1], p->branch[2],
+                             p->gamma_deph};
+    if (!finite_all(rates, 7)) return fail(MPDO_E_ARG, "non-finite parameter");
+    if (!(p->tau > 0.0)) return fail(MPDO_E_ARG, "tau must be > 0");
+    if (p->gamma_diss < 0.0 || p->branch[0] < 0.0 || p->branch[1] < 0.0 || p->branch[2] < 0.0)
+        return fail(MPDO_E_ARG, "negative rate or branch ratio");
+    if (d == 3 && p->branch[2] != 0.0) return fail(MPDO_E_ARG, "a dark branch needs d = 4");
+    if (!finite_all(omega, n) || !finite_all(delta, n)) return fail(MPDO_E_ARG, "non-finite pulse sample");
+
+    const double tau = p->tau;
+    SiteNoise z{};
+    const double e0 = exp(-p->gamma_diss * p->branch[0] * tau);
+    const double e1 = exp(-p->gamma_diss * p->branch[1] * tau);
+    const double ed = exp(-p->gamma_diss * p->branch[2] * tau);
+    z.sqrtE = sqrt(e0 * e1 * ed);
+    z.tr[0] = 1.0 - e0;
+    z.tr[1] = e0 * (1.0 - e1);
+    z.tr[2] = 0.0;
+    z.tr[3] = d == 4 ? e0 * e1 * (1.0 - ed) : 0.0;
+    const double g2 = p->gamma_deph * p->gamma_deph;
+    z.dq = exp(-g2 * tau);
+    z.dh = exp(-0.25 * g2 * tau);
+
+    const int ne = d * d * d * d;
+    hipStream_t s = (hipStream_t)hip_stream;
+    double *dsamp = nullptr, *dtab = nullptr, *dout = nullptr;
+    mpdo_status st = MPDO_OK;
+    const size_t samp_b = 2 * (size_t)n * sizeof(double), tab_b = 6 * (size_t)n * sizeof(double);
+    const size_t out_b = 2 * (size_t)ne * ne * sizeof(double);
+    if (hipMalloc(&dsamp, samp_b) != hipSuccess || hipMalloc(&dtab, tab_b) != hipSuccess ||
+        hipMalloc(&dout, out_b) != hipSuccess) {
+        st = fail(MPDO_E_NOMEM, "device allocation failed");
+    } else {
+        hipError_t e = hipMemcpyAsync(dsamp, omega, n * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dsamp + n, delta, n * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(pulse_drive_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dsamp, dsamp + n, n, tau,
+                               dtab);
+            if (d == 4)
+                hipLaunchKernelGGL(pulse_evolve_kernel<4>, dim3(ne), dim3(EVOLVE_THREADS), 0, s, dtab, n, tau,
+                                   p->blockade, z, dout);
+            else
+                hipLaunchKernelGGL(pulse_evolve_kernel<3>, dim3(ne), dim3(EVOLVE_THREADS), 0, s, dtab, n, tau,
+                                   p->blockade, z, dout);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(superop, dout, out_b, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(MPDO_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+    }
+    if (dsamp) (void)hipFree(dsamp);
+    if (dtab) (void)hipFree(dtab);
+    if (dout) (void)hipFree(dout);
+    if (st == MPDO_OK) g_err.clear();
+    return st;
+}
+
+extern "C" const char* mpdo_pulse_last_error(void) { return g_err.c_str(); }

@@ -12,6 +12,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mpdo.h")
 MLP_HEADER = os.path.join(ROOT, "include", "mpdo_mlp.h")
+PULSE_HEADER = os.path.join(ROOT, "include", "mpdo_pulse.h")
 
 
 def _declared_symbols(path=HEADER):
@@ -35,7 +36,7 @@ def test_header_declares_the_paper_calls():
 
 
 def test_every_declared_symbol_is_exported(lib):
-    for path in (HEADER, MLP_HEADER):
+    for path in (HEADER, MLP_HEADER, PULSE_HEADER):
         for name in _declared_symbols(path):
             assert hasattr(lib, name), name
 
@@ -43,6 +44,35 @@ def test_every_declared_symbol_is_exported(lib):
 def test_surrogate_binding_covers_its_header(lib):
     from paper_2309_08572_amd import surrogate
     assert sorted(surrogate.EXPORTS) == _declared_symbols(MLP_HEADER)
+
+
+def test_pulse_binding_covers_its_header(lib):
+    from paper_2309_08572_amd import pulse
+    assert sorted(pulse.EXPORTS) == _declared_symbols(PULSE_HEADER)
+
+
+def test_pulse_argument_checks_without_gpu(lib):
+    """Parameter checks happen before any device call."""
+    from paper_2309_08572_amd import pulse
+    lib = pulse._lib()
+    om = np.zeros(4)
+    out = np.zeros(2 * 256 * 256)
+    dp = C.POINTER(C.c_double)
+
+    def call(**kw):
+        base = dict(d=4, n_steps=4, tau=0.1, blockade=1.0, gamma_diss=0.0, branch=(0.0, 0.0, 0.0), gamma_deph=0.0)
+        base.update(kw)
+        p = pulse.PulseParams(base["d"], base["n_steps"], base["tau"], base["blockade"], base["gamma_diss"],
+                              (C.c_double * 3)(*base["branch"]), base["gamma_deph"])
+        return lib.mpdo_pulse_channel(C.byref(p), om.ctypes.data_as(dp), om.ctypes.data_as(dp),
+                                      out.ctypes.data_as(dp), None)
+    assert call(d=5) == 1
+    assert call(n_steps=0) == 1
+    assert call(tau=0.0) == 1
+    assert call(tau=float("nan")) == 1
+    assert call(gamma_diss=-1.0) == 1
+    assert call(d=3, branch=(0.5, 0.4, 0.1)) == 1
+    assert b"d = 4" in lib.mpdo_pulse_last_error()
 
 
 def test_mlp_argument_checks_without_gpu(lib):
