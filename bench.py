@@ -91,6 +91,22 @@ def _batch(count: int, workers: int) -> dict:
             "max_bond": max(max(r["bonds"]) for r in res)}
 
 
+def _pulse_gate(n_steps: int) -> dict:
+    """The pulse-level gate builder on the paper's Gaussian CZ pulse (d=4, dissipation 0.001/T,
+    branching 1/16, 1/16, 7/8): wall time of one call, host in and host out."""
+    from paper_2309_08572_amd import pulse
+    gd = 0.001 / 2.165
+    pulse.gaussian_cz(n_steps=64, gamma_diss=gd)            # load and warm up
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        pulse.gaussian_cz(n_steps=n_steps, gamma_diss=gd)
+        times.append(time.perf_counter() - t0)
+    t = sorted(times)[1]
+    return {"workload": "Gaussian CZ pulse T=2.165 us, d=4, 256 basis inputs, gamma_diss=0.001/T",
+            "steps": n_steps, "ms_per_channel": 1e3 * t, "us_per_step": 1e6 * t / n_steps}
+
+
 PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp64_vector": 78.6, "hbm_gbs": 8000.0}
 
 
@@ -98,6 +114,29 @@ PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp64_vector": 78.6, "hbm_gbs": 8
 # average is a kernel duration only for launches well above that; the roofline kernel is the
 # family with the most event time among those averaging >= MIN_LAUNCH_US per launch.
 MIN_LAUNCH_US = 50.0
+
+
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on the FP64 run of
+# this workload, each counter scaled by what it reads for a plain 256 MiB device copy (fetch
+# x 2.00, write x 1.00).  Valid only for the kernel source it was taken on: the entry names the
+# file and the first 16 hex digits of its SHA-256, and traffic is null when the file differs.
+TRAFFIC = {
+    "tri_reduce": {"source": "paper_2309_08572_amd/csrc/tri.hip", "sha256_16": "48cf5d2f3067049c",
+                   "bytes_per_launch": 450565.0},
+}
+
+
+def _traffic(fam: str):
+    import hashlib
+    t = TRAFFIC.get(fam)
+    if t is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
+    try:
+        h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return t["bytes_per_launch"] if h == t["sha256_16"] else None
 
 
 def roofline_of(prof: dict, fp64: bool) -> dict:
@@ -123,7 +162,7 @@ def roofline_of(prof: dict, fp64: bool) -> dict:
         # one workgroup on one of the 256 compute units: its own FP64 ceiling is peak / 256
         rf["workgroups"] = 1
         rf["frac_of_one_cu"] = rf["achieved"] / (rf["peak"] / 256.0)
-    rf["traffic"] = None
+    rf["traffic"] = _traffic(fam)
     rf["kernel_family"] = fam
     rf["launches"] = d["launches"]
     rf["avg_launch_us"] = avg_s * 1e6
@@ -145,6 +184,8 @@ def main() -> int:
                     help="also time this many circuits of the 256-circuit batch workload "
                          "(one per worker stream vs one at a time)")
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--pulse-steps", type=int, default=20000,
+                    help="also time the pulse-level CZ gate builder with this many steps (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
@@ -223,6 +264,8 @@ def main() -> int:
                           "trace": [r["obs"]["trace"].real, r["obs"]["trace"].imag]}
     if args.batch_circuits > 0:
         out["batch"] = _batch(args.batch_circuits, args.workers)
+    if args.pulse_steps > 0:
+        out["pulse_gate"] = _pulse_gate(args.pulse_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(spec, args.cpu_baseline_seconds)
     print(json.dumps(out))

@@ -3,7 +3,7 @@
 //
 //   pulse_drive_kernel   one thread per step: the single-atom propagator exp(-i tau H) on the
 //                        {|1>, |r>} block in closed form (the other levels are untouched)
-//   pulse_evolve_kernel  one workgroup per basis input |a><b|, one thread per entry of the
+//   pulse_evolve_kernel  one workgroup per (time segment, basis input |a><b|), one thread per entry of the
 //                        pair's density matrix (d^4 <= 256), the matrix held in LDS through all
 //                        steps.  Per step two passes, each ended by a barrier:
 //                          1. dissipators of both atoms and the blockade phase, entry-wise:
@@ -11,6 +11,13 @@
 //                             receives the r-r entry it is fed from;
 //                          2. conjugation by u (x) u, u mixing only |1> and |r>: at most 16
 //                             terms per entry.
+//                        The per-step coefficients are staged in LDS, CHUNK steps at a time
+//                        (one coalesced load per chunk instead of a dependent load per step).
+//   segment products     the steps are cut into up to MAX_SEG consecutive segments whose
+//                        channels are built concurrently (d^4 basis inputs alone give one
+//                        workgroup per compute unit, too few to hide the per-step barriers);
+//                        the segment channels are then multiplied in time order, pairwise in a
+//                        tree, by the library's complex FP64 matrix-core GEMM.
 //
 // Dissipators in closed form (each is the exact exponential of its generator).  Decay r -> j
 // with rate k_j = gamma b_j: rho_rr *= e_j, rho_jj += (1 - e_j) rho_rr, coherences with one r
@@ -22,15 +29,20 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/mpdo_pulse.h"
+#include "gemm.h"
 
 namespace {
 
 constexpr int LR = 2;      // Rydberg level
 constexpr int LDARK = 3;   // dark level (d = 4)
 constexpr int EVOLVE_THREADS = 256;
+constexpr int CHUNK = 256;   // steps whose drive coefficients are staged in LDS at a time
+constexpr int MAX_SEG = 16;  // time segments built concurrently
+constexpr int SEG_MIN_STEPS = 512;
 
 thread_local std::string g_err;
 
@@ -76,15 +88,23 @@ __device__ inline double site_factor(const SiteNoise& z, int x, int y) {
     return f;
 }
 
+__device__ inline double sink_fraction(const SiteNoise& z, int l) {
+    return l == 0 ? z.tr[0] : l == 1 ? z.tr[1] : l == LDARK ? z.tr[3] : 0.0;
+}
+
 template <int DL>
 __global__ __launch_bounds__(EVOLVE_THREADS) void pulse_evolve_kernel(const double* __restrict__ tab, int n,
-                                                                      double tau, double blockade, SiteNoise z,
-                                                                      double* __restrict__ out) {
+                                                                      int nseg, double tau, double blockade,
+                                                                      SiteNoise z, double* __restrict__ out) {
     constexpr int DIM = DL * DL;   // pair Hilbert dimension
     constexpr int NE = DIM * DIM;  // entries of rho = basis inputs = superoperator order
     static_assert(NE <= EVOLVE_THREADS, "one thread per entry");
     __shared__ double sr[2][NE], si[2][NE];
+    __shared__ double ut[6 * CHUNK];
     const int col = blockIdx.x;
+    const int seg = blockIdx.y;
+    const int k0 = (int)((long)seg * n / nseg), k1 = (int)((long)(seg + 1) * n / nseg);
+    out += 2 * (long)seg * NE * NE;
     const int a = col / DIM, b = col - (col / DIM) * DIM;
     const int t = threadIdx.x;
     const bool act = t < NE;
@@ -96,18 +116,41 @@ __global__ __launch_bounds__(EVOLVE_THREADS) void pulse_evolve_kernel(const doub
     }
     // pass-1 constants
     const double f1 = site_factor(z, x1, y1), f2 = site_factor(z, x2, y2);
-    const double t1 = (x1 == y1) ? z.tr[x1] : 0.0, t2 = (x2 == y2) ? z.tr[x2] : 0.0;
+    const double t1 = (x1 == y1) ? sink_fraction(z, x1) : 0.0, t2 = (x2 == y2) ? sink_fraction(z, x2) : 0.0;
     const int src1 = (LR * DL + x2) * DIM + (LR * DL + y2);
     const int src2 = (x1 * DL + LR) * DIM + (y1 * DL + LR);
     const int src12 = (LR * DL + LR) * DIM + (LR * DL + LR);
     const int rr = LR * DL + LR;
     const double bph = -tau * blockade * ((x == rr ? 1.0 : 0.0) - (y == rr ? 1.0 : 0.0));
     const double bc = cos(bph), bs = sin(bph);
-    // pass-2 partners: level l in {1, r} mixes with the other one of the pair
+    // pass-2 partners: a level l in {1, r} mixes with both levels of the pair, any other level
+    // only with itself.  Partner p of l is level 1 (p = 0) or r (p = 1) and its coefficient is
+    // u_{l,partner}, stored at slot 0 (u11), 1 (u1r = ur1) or 2 (urr) of the step's table;
+    // slot -1 is the identity.
     const bool m1x = x1 == 1 || x1 == LR, m2x = x2 == 1 || x2 == LR;
     const bool m1y = y1 == 1 || y1 == LR, m2y = y2 == 1 || y2 == LR;
+    const int nx1 = m1x ? 2 : 1, nx2 = m2x ? 2 : 1, ny1 = m1y ? 2 : 1, ny2 = m2y ? 2 : 1;
+    int px1[2], px2[2], py1[2], py2[2], sx1[2], sx2[2], sy1[2], sy2[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int lev = p == 0 ? 1 : LR;
+        px1[p] = m1x ? lev : x1;
+        px2[p] = m2x ? lev : x2;
+        py1[p] = m1y ? lev : y1;
+        py2[p] = m2y ? lev : y2;
+        sx1[p] = m1x ? (x1 == 1 ? p : 1 + p) : -1;
+        sx2[p] = m2x ? (x2 == 1 ? p : 1 + p) : -1;
+        sy1[p] = m1y ? (y1 == 1 ? p : 1 + p) : -1;
+        sy2[p] = m2y ? (y2 == 1 ? p : 1 + p) : -1;
+    }
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
+    for (int k = k0; k < k1; ++k) {
+        const int kc = (k - k0) % CHUNK;
+        if (kc == 0) {
+            // the previous chunk's last pass-2 reads of ut ended at the barrier below
+            const int m = min(CHUNK, k1 - k);
+            for (int i = threadIdx.x; i < 6 * m; i += EVOLVE_THREADS) ut[i] = tab[6 * (long)k + i];
+        }
         // ---- pass 1: dissipators of both atoms, then the blockade phase (buffer 0 -> 1)
         if (act) {
             double vr = f1 * f2 * sr[0][t], vi = f1 * f2 * si[0][t];
@@ -129,32 +172,35 @@ __global__ __launch_bounds__(EVOLVE_THREADS) void pulse_evolve_kernel(const doub
         __syncthreads();
         // ---- pass 2: rho <- (u (x) u) rho (u (x) u)^+ (buffer 1 -> 0)
         if (act) {
-            const double* u = tab + 6 * (long)k;
-            // u[l][l'] for l, l' in {1, r}: u11, u1r, ur1 = u1r, urr
-            const double ur[2][2] = {{u[0], u[2]}, {u[2], u[4]}};
-            const double ui[2][2] = {{u[1], u[3]}, {u[3], u[5]}};
-            const int nx1 = m1x ? 2 : 1, nx2 = m2x ? 2 : 1, ny1 = m1y ? 2 : 1, ny2 = m2y ? 2 : 1;
+            const double* u = ut + 6 * kc;
             double accr = 0.0, acci = 0.0;
-            for (int p1 = 0; p1 < nx1; ++p1) {
-                const int xs1 = m1x ? (p1 == 0 ? 1 : LR) : x1;
-                const double c1r = m1x ? ur[x1 == LR][p1] : 1.0, c1i = m1x ? ui[x1 == LR][p1] : 0.0;
-                for (int p2 = 0; p2 < nx2; ++p2) {
-                    const int xs2 = m2x ? (p2 == 0 ? 1 : LR) : x2;
-                    const double c2r = m2x ? ur[x2 == LR][p2] : 1.0, c2i = m2x ? ui[x2 == LR][p2] : 0.0;
+#pragma unroll
+            for (int p1 = 0; p1 < 2; ++p1) {
+                if (p1 >= nx1) continue;
+                const double c1r = sx1[p1] < 0 ? 1.0 : u[2 * sx1[p1]], c1i = sx1[p1] < 0 ? 0.0 : u[2 * sx1[p1] + 1];
+#pragma unroll
+                for (int p2 = 0; p2 < 2; ++p2) {
+                    if (p2 >= nx2) continue;
+                    const double c2r = sx2[p2] < 0 ? 1.0 : u[2 * sx2[p2]], c2i = sx2[p2] < 0 ? 0.0 : u[2 * sx2[p2] + 1];
                     const double cxr = c1r * c2r - c1i * c2i, cxi = c1r * c2i + c1i * c2r;
-                    const int xs = xs1 * DL + xs2;
-                    for (int q1 = 0; q1 < ny1; ++q1) {
-                        const int ys1 = m1y ? (q1 == 0 ? 1 : LR) : y1;
-                        const double d1r = m1y ? ur[y1 == LR][q1] : 1.0, d1i = m1y ? -ui[y1 == LR][q1] : 0.0;
-                        for (int q2 = 0; q2 < ny2; ++q2) {
-                            const int ys2 = m2y ? (q2 == 0 ? 1 : LR) : y2;
-                            const double d2r = m2y ? ur[y2 == LR][q2] : 1.0, d2i = m2y ? -ui[y2 == LR][q2] : 0.0;
+                    const int xs = px1[p1] * DL + px2[p2];
+#pragma unroll
+                    for (int q1 = 0; q1 < 2; ++q1) {
+                        if (q1 >= ny1) continue;
+                        // conj(u) on the bra side
+                        const double d1r = sy1[q1] < 0 ? 1.0 : u[2 * sy1[q1]];
+                        const double d1i = sy1[q1] < 0 ? 0.0 : -u[2 * sy1[q1] + 1];
+#pragma unroll
+                        for (int q2 = 0; q2 < 2; ++q2) {
+                            if (q2 >= ny2) continue;
+                            const double d2r = sy2[q2] < 0 ? 1.0 : u[2 * sy2[q2]];
+                            const double d2i = sy2[q2] < 0 ? 0.0 : -u[2 * sy2[q2] + 1];
                             const double dyr = d1r * d2r - d1i * d2i, dyi = d1r * d2i + d1i * d2r;
                             const double cr = cxr * dyr - cxi * dyi, ci = cxr * dyi + cxi * dyr;
-                            const int e = xs * DIM + (ys1 * DL + ys2);
-                            const double rr_ = sr[1][e], ri_ = si[1][e];
-                            accr += cr * rr_ - ci * ri_;
-                            acci += cr * ri_ + ci * rr_;
+                            const int e = xs * DIM + (py1[q1] * DL + py2[q2]);
+                            const double vr = sr[1][e], vi = si[1][e];
+                            accr += cr * vr - ci * vi;
+                            acci += cr * vi + ci * vr;
                         }
                     }
                 }
@@ -217,13 +263,14 @@ extern "C" mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* p, const doub
     z.dh = exp(-0.25 * g2 * tau);
 
     const int ne = d * d * d * d;
+    const int nseg = std::max(1, std::min(MAX_SEG, n / SEG_MIN_STEPS));
     hipStream_t s = (hipStream_t)hip_stream;
-    double *dsamp = nullptr, *dtab = nullptr, *dout = nullptr;
+    double *dsamp = nullptr, *dtab = nullptr, *dout = nullptr, *dtmp = nullptr;
     mpdo_status st = MPDO_OK;
     const size_t samp_b = 2 * (size_t)n * sizeof(double), tab_b = 6 * (size_t)n * sizeof(double);
-    const size_t out_b = 2 * (size_t)ne * ne * sizeof(double);
+    const size_t one_b = 2 * (size_t)ne * ne * sizeof(double);
     if (hipMalloc(&dsamp, samp_b) != hipSuccess || hipMalloc(&dtab, tab_b) != hipSuccess ||
-        hipMalloc(&dout, out_b) != hipSuccess) {
+        hipMalloc(&dout, one_b * nseg) != hipSuccess || hipMalloc(&dtmp, one_b * ((nseg + 1) / 2)) != hipSuccess) {
         st = fail(MPDO_E_NOMEM, "device allocation failed");
     } else {
         hipError_t e = hipMemcpyAsync(dsamp, omega, n * sizeof(double), hipMemcpyHostToDevice, s);
@@ -232,20 +279,36 @@ extern "C" mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* p, const doub
             hipLaunchKernelGGL(pulse_drive_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dsamp, dsamp + n, n, tau,
                                dtab);
             if (d == 4)
-                hipLaunchKernelGGL(pulse_evolve_kernel<4>, dim3(ne), dim3(EVOLVE_THREADS), 0, s, dtab, n, tau,
-                                   p->blockade, z, dout);
+                hipLaunchKernelGGL(pulse_evolve_kernel<4>, dim3(ne, nseg), dim3(EVOLVE_THREADS), 0, s, dtab, n, nseg,
+                                   tau, p->blockade, z, dout);
             else
-                hipLaunchKernelGGL(pulse_evolve_kernel<3>, dim3(ne), dim3(EVOLVE_THREADS), 0, s, dtab, n, tau,
-                                   p->blockade, z, dout);
+                hipLaunchKernelGGL(pulse_evolve_kernel<3>, dim3(ne, nseg), dim3(EVOLVE_THREADS), 0, s, dtab, n, nseg,
+                                   tau, p->blockade, z, dout);
             e = hipGetLastError();
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(superop, dout, out_b, hipMemcpyDeviceToHost, s);
+        // product of the segment channels in time order: S = S_{nseg-1} ... S_1 S_0, pairwise
+        double* cur = dout;
+        double* nxt = dtmp;
+        int cnt = nseg;
+        const long one = (long)ne * ne;   // complex elements of one channel
+        while (e == hipSuccess && cnt > 1) {
+            const int pairs = cnt / 2;
+            e = mpdo::cgemm<double>(s, ne, ne, ne, mpdo::cd{1.0, 0.0}, mpdo::view<double>(cur + 2 * one, ne, 1),
+                                    mpdo::view<double>(cur, ne, 1), mpdo::cd{0.0, 0.0}, mpdo::view<double>(nxt, ne, 1),
+                                    pairs, 2 * one, 2 * one, one);
+            if (e == hipSuccess && (cnt & 1))
+                e = hipMemcpyAsync(nxt + 2 * one * pairs, cur + 2 * one * (cnt - 1), one_b, hipMemcpyDeviceToDevice, s);
+            cnt = pairs + (cnt & 1);
+            std::swap(cur, nxt);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(superop, cur, one_b, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = fail(MPDO_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
     }
     if (dsamp) (void)hipFree(dsamp);
     if (dtab) (void)hipFree(dtab);
     if (dout) (void)hipFree(dout);
+    if (dtmp) (void)hipFree(dtmp);
     if (st == MPDO_OK) g_err.clear();
     return st;
 }

@@ -3,7 +3,8 @@ against the pulse oracle (oracle/pulse.py) and the properties every such channel
 
 Bars: FP64 throughout; entries of the channel are O(1) and the kernel applies the same exact
 factors in the same order as the oracle (closed forms there, expm here), so parity is 1e-12
-per entry after a few hundred steps and 1e-10 after 12000 (rounding grows with the steps).
+per entry after a few hundred steps, 1e-11 after 1600 (three time segments whose channels are
+multiplied by the GEMM) and 1e-10 after 12000 (rounding grows with the steps).
 """
 import math
 
@@ -23,7 +24,7 @@ def _gpu():
     return pulse
 
 
-@pytest.mark.parametrize("d,n", [(3, 37), (4, 50)])
+@pytest.mark.parametrize("d,n", [(3, 37), (4, 50), (3, 1600)])
 def test_noisy_channel_matches_oracle(d, n):
     pulse = _gpu()
     from oracle import pulse as opulse
@@ -37,7 +38,7 @@ def test_noisy_channel_matches_oracle(d, n):
     ref = opulse.to_site_layout(opulse.pulse_channel(om, de, tau, d, B, gd, br, gp), d)
     err = np.abs(S - ref).max()
     print(f"[gpu] max |S - S_oracle| = {err:.2e}", flush=True)
-    assert err <= 1e-12
+    assert err <= 1e-12 if n < 1000 else err <= 1e-11    # 1600 steps: three segments, multiplied
 
 
 def test_gaussian_cz_matches_oracle_unitary():
