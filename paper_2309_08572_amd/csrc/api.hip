@@ -42,6 +42,21 @@ constexpr double EPS64 = 2.220446049250313e-16;
 constexpr double EPS32 = 1.1920928955078125e-07;
 constexpr int MAX_FACTOR_RANK = 16;   // operator-Schmidt terms kept in LDS by phys_* kernels
 constexpr int EIG_MAX_SWEEPS = 40;
+// Range bases whose exact construction would need an eigenproblem above TRI_MAX are found by
+// block subspace iteration on theta theta^H: SUB_OVER extra directions beyond chi, at most
+// SUB_ITERS passes, stopping once the captured weight ||Q^H theta||_F^2 grows by less than the
+// tolerance (relative; FP64 1e-12, FP32 1e-6).
+constexpr int SUB_OVER = 256;
+constexpr int SUB_ITERS = 12;
+
+// Order above which a split uses the subspace iteration: TRI_MAX, or MPDO_SUBSPACE_MIN_ORDER
+// from the environment (lower values let tests run the subspace path where the exact path
+// also works).
+int subspace_min_order() {
+    const char* e = getenv("MPDO_SUBSPACE_MIN_ORDER");
+    const int v = e ? atoi(e) : 0;
+    return v > 0 ? std::min(v, TRI_MAX) : TRI_MAX;
+}
 
 struct Fail {
     mpdo_status st;
@@ -273,6 +288,7 @@ struct Engine {
     Scratch<T>& s;
     hipStream_t st;
     int eig_calls = 0;
+    int sub_iters = 0;   // subspace-iteration passes of the current update
 
     Engine(mpdo_ctx_s& ctx, Scratch<T>& sc) : c(ctx), s(sc), st(ctx.st) {}
 
@@ -463,6 +479,74 @@ struct Engine {
         return q;
     }
 
+    // Orthonormal basis Q (na x q) of the dominant left singular subspace of theta = Fa Fb
+    // (Fb null: theta = Fa, na x nb), for splits whose exact range basis would need an
+    // eigenproblem above TRI_MAX (the saturated regime: theta up to 8192 x 8192 of rank 4608).
+    // Block subspace iteration from a seeded random block of m = min(chi + SUB_OVER, na, nb,
+    // rank bound) columns: Q = orth(theta X); then repeatedly Z = orth(theta^H Q),
+    // Q = orth(theta Z).  Every application of theta or theta^H is orthonormalised by orth2
+    // (eigenproblems of order <= m), so a block never spans more than the sigma_max / sigma_j
+    // of one application and directions down to orth2's rounding floor survive.  Stops when
+    // ||Q^H theta||_F^2, the weight of theta captured by Q, grows by less than the tolerance,
+    // or at once when m reaches the rank bound (one pass then spans range(theta)).  The later
+    // cut keeps at most chi directions of this basis, so what the basis misses lies below the
+    // truncation; ||theta||^2 seen by PPT is the captured weight.
+    // Outputs: Q -> Qout (ld ldq), Q^H Fa -> Kout (q x k, ld ldk; with Fb null, k = nb).
+    int subspace_basis(CView<T> Fa, const CView<T>* Fb, int na, int k, int nb, int chi, uint64_t seed, T* Qout,
+                       long ldq, T* Kout, long ldk) {
+        const int rank_bound = Fb ? std::min(k, std::min(na, nb)) : std::min(na, nb);
+        const int m = std::min(chi + SUB_OVER, rank_bound);
+        const double tol = std::is_same<T, double>::value ? 1e-12 : 1e-6;
+        T* X = s.bR;     // nb x cols: random start block, then orth(theta^H Q)
+        T* T1 = s.bU;    // k x cols, Fb X
+        T* Y = s.bC;     // na x cols
+        T* Qt = s.bQ2;   // orth2's basis of Y (ld cols)
+        T* Kt = s.bK2;   // orth2's coefficients (unused)
+        T* Kq = s.bB2;   // Q^H Fa (q x k, ld k)
+        T* Cq = s.bU2;   // Q^H theta (q x nb, ld nb)
+        auto apply = [&](CView<T> Xv, int cols) {   // Y = theta Xv (nb x cols)
+            if (Fb) {
+                gemm(k, cols, nb, C1(), *Fb, Xv, C0(), V<T>(T1, cols, 1));
+                gemm(na, cols, k, C1(), Fa, V<T>(T1, cols, 1), C0(), V<T>(Y, cols, 1));
+            } else {
+                gemm(na, cols, nb, C1(), Fa, Xv, C0(), V<T>(Y, cols, 1));
+            }
+        };
+        HIPCHK(fill_random<T>(st, V<T>(X, m, 1), nb, m, seed));
+        apply(V<T>(X, m, 1), m);
+        int cols = m, q = 0;
+        double w_old = -1.0;
+        for (int it = 0;; ++it) {
+            q = orth2(V<T>(Y, cols, 1), na, cols, Qt, Kt);
+            if (q <= 0) return 0;
+            if (Fb) {
+                gemm(q, k, na, C1(), adj(V<T>(Qt, cols, 1)), Fa, C0(), V<T>(Kq, k, 1));
+                gemm(q, nb, k, C1(), V<T>(Kq, k, 1), *Fb, C0(), V<T>(Cq, nb, 1));
+            } else {
+                gemm(q, nb, na, C1(), adj(V<T>(Qt, cols, 1)), Fa, C0(), V<T>(Cq, nb, 1));
+            }
+            ++sub_iters;
+            if (m >= rank_bound) break;
+            HIPCHK(sumsq<T>(st, V<T>(Cq, nb, 1), q, nb, s.sums));
+            double w[2];
+            read_doubles(s.sums, 2, w);
+            if (w[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the subspace iteration"};
+            if ((w_old >= 0.0 && w[0] - w_old <= tol * w[0]) || it + 1 >= SUB_ITERS) break;
+            w_old = w[0];
+            // Z = orth(theta^H Q) (nb x z), then Y = theta Z
+            const int z = orth2(adj(V<T>(Cq, nb, 1)), nb, q, X, Kt);
+            if (z <= 0) return 0;
+            apply(V<T>(X, q, 1), z);
+            cols = z;
+        }
+        HIPCHK((geam<T, T>(st, na, q, C1(), V<T>(Qt, cols, 1), C0(), V<T>(Qout, ldq, 1))));
+        if (Fb)
+            HIPCHK((geam<T, T>(st, q, k, C1(), V<T>(Kq, k, 1), C0(), V<T>(Kout, ldk, 1))));
+        else
+            HIPCHK((geam<T, T>(st, q, nb, C1(), V<T>(Cq, nb, 1), C0(), V<T>(Kout, ldk, 1))));
+        return q;
+    }
+
     // Left split of the a x b view F: U (a x kept) into Ub (ld chi_cap), Schmidt values in
     // s.sig, B = U^H F (kept x b) into Bb (ld b).  Up to three deflation levels.
     int split_left(CView<T> F, int a, int b, int chi, T* Ub, long ldu, T* Bb) {
@@ -609,6 +693,7 @@ struct Engine {
     // ------------------------------------------------------------ the two-site update
     void update(int i, const GateFactor* gf, int chi, mpdo_trunc_info* info) {
         eig_calls = 0;
+        sub_iters = 0;
         const int D2 = c.D2;
         if (c.centre < i) c.dir = 1;
         else if (c.centre > i + 1) c.dir = -1;
@@ -650,7 +735,9 @@ struct Engine {
             HIPCHK(dot(st, s.vtmp, s.vtmp2, k, s.sc));
             CView<T> Fa = dir > 0 ? ML : adj(MR);
             CView<T> Fb = dir > 0 ? MR : adj(ML);
-            const int q = orth2(Fa, na, k, s.bQ, s.bK);
+            const int q = k > subspace_min_order() ? subspace_basis(Fa, &Fb, na, k, nb, chi, 0x5EED0000ull + (uint64_t)i, s.bQ, k,
+                                                       s.bK, k)
+                                      : orth2(Fa, na, k, s.bQ, s.bK);
             if (q <= 0) throw Fail{MPDO_E_NUMERIC, "merged tensor vanished"};
             // core C = K Fb (q x nb)
             gemm(q, nb, k, C1(), V<T>(s.bK, k, 1), Fb, C0(), V<T>(s.bC, nb, 1));
@@ -685,7 +772,18 @@ struct Engine {
             if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
             n2 = sums[0];
             CView<T> Fa = dir > 0 ? Th : adj(Th);
-            kept = svd_left(Fa, na, nb, chi, s.bU2);
+            if (std::min(na, nb) > subspace_min_order()) {
+                // range basis by subspace iteration, then the exact split of the q x nb core
+                const int q = subspace_basis(Fa, nullptr, na, nb, nb, chi, 0x5EED0000ull + (uint64_t)i, s.bQ, nb,
+                                             s.bK, nb);
+                if (q <= 0) throw Fail{MPDO_E_NUMERIC, "merged tensor vanished"};
+                kept = svd_left(V<T>(s.bK, nb, 1), q, nb, chi, s.bU2);
+                if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
+                gemm(na, kept, q, C1(), V<T>(s.bQ, nb, 1), V<T>(s.bU2, kept, 1), C0(), V<T>(s.bR, kept, 1));
+                HIPCHK((geam<T, T>(st, na, kept, C1(), V<T>(s.bR, kept, 1), C0(), V<T>(s.bU2, kept, 1))));
+            } else {
+                kept = svd_left(Fa, na, nb, chi, s.bU2);
+            }
             if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
             if (dir > 0) {
                 HIPCHK((geam<T, T>(st, nL, kept, C1(), V<T>(s.bU2, kept, 1), C0(), V<T>(outL, kept, 1))));

@@ -51,6 +51,10 @@ hipError_t spectrum_cut(hipStream_t s, const double* lam, int n, int level, doub
 template <typename T>
 hipError_t scale_cols(hipStream_t s, CView<T> X, int M, int N, const double* f);
 
+// X (M x N view) <- seeded uniform [-1, 1) entries (re and im), reproducible for a seed.
+template <typename T>
+hipError_t fill_random(hipStream_t s, CView<T> X, int M, int N, uint64_t seed);
+
 // Z = 1.5 I - 0.5 G  (q x q, dense row-major): one Newton-Schulz step for orthonormal columns.
 template <typename T>
 hipError_t ns_prep(hipStream_t s, const T* G, int q, T* Z);

@@ -268,6 +268,27 @@ __global__ void spectrum_cut_kernel(const double* __restrict__ lam, int n, int l
     }
 }
 
+// Seeded random start block: entry (r, c) of X gets re, im uniform in [-1, 1) from the
+// SplitMix64 sequence at counter (seed, r * cols + c) (Steele, Lea, Flood 2014).
+__device__ inline uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void fill_random_kernel(CView<T> X, int M, int N, uint64_t seed) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)M * N) return;
+    const long r = idx / N, c = idx - (idx / N) * N;
+    const uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)idx));
+    const double u0 = (double)(h >> 40) * (1.0 / 16777216.0), u1 = (double)((h >> 16) & 0xFFFFFF) * (1.0 / 16777216.0);
+    T* p = X.p + 2 * (r * X.rs + c * X.cs);
+    p[0] = (T)(2.0 * u0 - 1.0);
+    p[1] = (T)(2.0 * u1 - 1.0);
+}
+
 template <typename T>
 __global__ void scale_cols_kernel(CView<T> X, int M, int N, const double* __restrict__ f) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -616,6 +637,13 @@ hipError_t spectrum_cut(hipStream_t s, const double* lam, int n, int level, doub
 }
 
 template <typename T>
+hipError_t fill_random(hipStream_t s, CView<T> X, int M, int N, uint64_t seed) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_random_kernel<T>, dim3(blocks_for((long)M * N)), dim3(256), 0, s, X, M, N, seed);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t scale_cols(hipStream_t s, CView<T> X, int M, int N, const double* f) {
     if (M <= 0 || N <= 0) return hipSuccess;
     hipLaunchKernelGGL(scale_cols_kernel<T>, dim3(blocks_for((long)M * N)), dim3(256), 0, s, X, M, N, f);
@@ -690,6 +718,7 @@ hipError_t bilinear(hipStream_t s, const T* L, int n, const double* y, double* o
     template hipError_t outer<T>(hipStream_t, const double*, int, T*);                                          \
     template hipError_t bilinear<T>(hipStream_t, const T*, int, const double*, double*);                         \
     template hipError_t scale_cols<T>(hipStream_t, CView<T>, int, int, const double*);                          \
+    template hipError_t fill_random<T>(hipStream_t, CView<T>, int, int, uint64_t);                               \
     template hipError_t ns_prep<T>(hipStream_t, const T*, int, T*);                                              \
     template hipError_t scale_rows<T>(hipStream_t, T*, int, int, long, const double*);                          \
     template hipError_t gemv_left<T>(hipStream_t, CView<T>, int, int, const double*, double*);                  \

@@ -1,7 +1,7 @@
 // Hermitian eigensolver for Gram matrices of order 65..TRI_MAX in FP64 (gfx950), restricted to
 // the eigenpairs one deflation level of the split accepts.
 //
-//   tri_reduce_kernel  one workgroup: Householder reduction H = Q T Q^H to a real symmetric
+//   tri_reduce_*       Householder reduction H = Q T Q^H to a real symmetric
 //                      tridiagonal T (complex reflectors chosen so the off-diagonal is real);
 //                      the reflectors are copied to contiguous rows for the back-transform
 //   tri_top_kernel     one wave: the largest eigenvalue by multisection of Sturm counts, the
@@ -82,152 +82,203 @@ __device__ __forceinline__ void block_maxmin(double& a, double& b, double* red) 
     b = sb;
 }
 
-// ------------------------------------------------------------------ reduction
+// ------------------------------------------------------------------ reduction, orders > RMAX
 // H (n x n complex, row-major, leading dimension ld) is overwritten.  Outputs: dg[0..n) and
 // off[0..n-1) (T), tau[j] (complex) and refl row j = v_j (length n-1-j, v_j[0] = 1) of
 // H_j = I - tau_j v_j v_j^H acting on rows j+1..n-1, so that H = H_0 ... H_{n-2} T (...)^H;
 // trace[0] = sum of the diagonal of H.
-__global__ __launch_bounds__(TB) void tri_reduce_kernel(double* __restrict__ H, int ld, int n,
-                                                        double* __restrict__ dg, double* __restrict__ off,
-                                                        double* __restrict__ tau, double* __restrict__ refl,
-                                                        double* __restrict__ trace) {
+//
+// The trailing matrix does not fit on chip above RMAX, and one workgroup streaming it through
+// L2 once per column is bound by that one compute unit.  So each column is two launches over
+// many workgroups, the rows of the trailing matrix split between their waves (ROWS_PER_WAVE
+// rows at a time):
+//   tri_hh_symv_kernel  every workgroup forms the Householder vector of column j itself (the
+//                       same arithmetic in the same order, so all agree), workgroup 0 writes the
+//                       outputs of column j and v; then p = tau A22 v for the workgroup's rows
+//   tri_rank2_kernel    every workgroup forms w = p - (tau/2)(p^H v) v and applies
+//                       A22 -= v w^H + w v^H to its rows.
+constexpr int RW = 256;                 // threads of the multi-workgroup reduction kernels
+constexpr int RWV = RW / 64;
+constexpr int ROWS_PER_WAVE = 4;
+constexpr int MAX_RGROUPS = 256;
+
+int reduce_groups(int m) {
+    const int g = (m + RWV * ROWS_PER_WAVE - 1) / (RWV * ROWS_PER_WAVE);
+    return g < 1 ? 1 : (g > MAX_RGROUPS ? MAX_RGROUPS : g);
+}
+
+// Hermitian part (average of the two triangles, real diagonal), rows spread over the grid
+__global__ __launch_bounds__(RW) void tri_herm_kernel(double* __restrict__ H, int ld, int n) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int x = blockIdx.x * RWV + w; x < n; x += gridDim.x * RWV)
+        for (int y = x + lane; y < n; y += 64) {
+            double* a = H + 2 * ((long)x * ld + y);
+            if (y == x) {
+                a[1] = 0.0;
+                continue;
+            }
+            double* b = H + 2 * ((long)y * ld + x);
+            const double r = 0.5 * (a[0] + b[0]), im = 0.5 * (a[1] - b[1]);
+            a[0] = r;
+            a[1] = im;
+            b[0] = r;
+            b[1] = -im;
+        }
+}
+
+__global__ __launch_bounds__(RW) void tri_trace_kernel(const double* __restrict__ H, int ld, int n,
+                                                       double* __restrict__ trace) {
+    __shared__ double red[2 * RWV];
+    double tr = 0.0, unused = 0.0;
+    for (int i = threadIdx.x; i < n; i += RW) tr += H[2 * ((long)i * ld + i)];
+    block_sum2<RWV>(tr, unused, red);
+    if (threadIdx.x == 0) trace[0] = tr;
+}
+
+__global__ __launch_bounds__(RW) void tri_hh_symv_kernel(const double* __restrict__ H, int ld, int n, int j,
+                                                         double* __restrict__ dg, double* __restrict__ off,
+                                                         double* __restrict__ tau, double* __restrict__ refl,
+                                                         double* __restrict__ vbuf, double* __restrict__ pbuf) {
     __shared__ double v[2 * TRI_MAX];
-    __shared__ double p[2 * TRI_MAX];
-    __shared__ double red[2 * NW];
+    __shared__ double red[2 * RWV];
     __shared__ double sc[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-
-    // Hermitian part (average of the two triangles, real diagonal) and the trace
-    {
-        double tr = 0.0, unused = 0.0;
-        for (int x = w; x < n; x += NW)
-            for (int y = lane; y < n; y += 64) {
-                double* a = H + 2 * ((long)x * ld + y);
-                if (x < y) {
-                    double* b = H + 2 * ((long)y * ld + x);
-                    const double r = 0.5 * (a[0] + b[0]), im = 0.5 * (a[1] - b[1]);
-                    a[0] = r;
-                    a[1] = im;
-                    b[0] = r;
-                    b[1] = -im;
-                } else if (x == y) {
-                    a[1] = 0.0;
-                    tr += a[0];
-                }
-            }
-        block_sum2(tr, unused, red);
-        if (tid == 0) trace[0] = tr;
+    const int m = n - j - 1;
+    // x = column j below the diagonal
+    double x2 = 0.0, unused = 0.0;
+    for (int i = tid; i < m; i += RW) {
+        const double* h = H + 2 * ((long)(j + 1 + i) * ld + j);
+        v[2 * i] = h[0];
+        v[2 * i + 1] = h[1];
+        if (i > 0) x2 += h[0] * h[0] + h[1] * h[1];
     }
-
-    for (int j = 0; j < n - 1; ++j) {
-        const int m = n - j - 1;
-        // x = column j below the diagonal
-        double x2 = 0.0, unused = 0.0;
-        for (int i = tid; i < m; i += TB) {
-            const double* h = H + 2 * ((long)(j + 1 + i) * ld + j);
-            v[2 * i] = h[0];
-            v[2 * i + 1] = h[1];
-            if (i > 0) x2 += h[0] * h[0] + h[1] * h[1];
+    block_sum2<RWV>(x2, unused, red);
+    if (tid == 0) {
+        const double ar = v[0], ai = v[1];
+        double beta, tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
+        if (x2 == 0.0 && ai == 0.0) {
+            beta = ar;   // already reduced: H_j = I
+        } else {
+            beta = -copysign(sqrt(ar * ar + ai * ai + x2), ar);
+            tr_ = (beta - ar) / beta;
+            ti_ = -ai / beta;
+            const double dr = ar - beta, di = ai, den = dr * dr + di * di;   // 1/(alpha - beta)
+            sr = dr / den;
+            si = -di / den;
         }
-        block_sum2(x2, unused, red);
-        if (tid == 0) {
-            const double ar = v[0], ai = v[1];
-            double beta, tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
-            if (x2 == 0.0 && ai == 0.0) {
-                beta = ar;   // already reduced: H_j = I
-            } else {
-                beta = -copysign(sqrt(ar * ar + ai * ai + x2), ar);
-                tr_ = (beta - ar) / beta;
-                ti_ = -ai / beta;
-                const double dr = ar - beta, di = ai, den = dr * dr + di * di;   // 1/(alpha - beta)
-                sr = dr / den;
-                si = -di / den;
-            }
-            sc[0] = tr_;
-            sc[1] = ti_;
-            sc[2] = sr;
-            sc[3] = si;
+        sc[0] = tr_;
+        sc[1] = ti_;
+        sc[2] = sr;
+        sc[3] = si;
+        if (blockIdx.x == 0) {
             off[j] = beta;
             tau[2 * j] = tr_;
             tau[2 * j + 1] = ti_;
             dg[j] = H[2 * ((long)j * ld + j)];
         }
-        __syncthreads();
-        const double tr_ = sc[0], ti_ = sc[1], sr = sc[2], si = sc[3];
-        for (int i = tid; i < m; i += TB) {
-            double vr = 1.0, vi = 0.0;
-            if (i > 0) {
-                const double xr = v[2 * i], xi = v[2 * i + 1];
-                vr = xr * sr - xi * si;
-                vi = xr * si + xi * sr;
-            }
-            v[2 * i] = vr;
-            v[2 * i + 1] = vi;
+    }
+    __syncthreads();
+    const double tr_ = sc[0], ti_ = sc[1], sr = sc[2], si = sc[3];
+    for (int i = tid; i < m; i += RW) {
+        double vr = 1.0, vi = 0.0;
+        if (i > 0) {
+            const double xr = v[2 * i], xi = v[2 * i + 1];
+            vr = xr * sr - xi * si;
+            vi = xr * si + xi * sr;
+        }
+        v[2 * i] = vr;
+        v[2 * i + 1] = vi;
+        if (blockIdx.x == 0) {
             refl[2 * ((long)j * n + i)] = vr;
             refl[2 * ((long)j * n + i) + 1] = vi;
+            vbuf[2 * i] = vr;
+            vbuf[2 * i + 1] = vi;
         }
-        __syncthreads();
-        if (tr_ == 0.0 && ti_ == 0.0) continue;
-        const long base = (long)(j + 1) * ld + (j + 1);
-        // p = tau A22 v: each wave takes four rows at a time (four loads in flight per lane)
-        for (int r0 = 4 * w; r0 < m; r0 += 4 * NW) {
-            double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int c = lane; c < m; c += 64) {
-                const double vr = v[2 * c], vi = v[2 * c + 1];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (r0 + q < m) {
-                        const double* h = H + 2 * (base + (long)(r0 + q) * ld + c);
-                        const double hr = h[0], hi = h[1];
-                        ar[q] += hr * vr - hi * vi;
-                        ai[q] += hr * vi + hi * vr;
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double qr = wave_sum(ar[q]), qi = wave_sum(ai[q]);
-                if (lane == 0 && r0 + q < m) {
-                    p[2 * (r0 + q)] = tr_ * qr - ti_ * qi;
-                    p[2 * (r0 + q) + 1] = tr_ * qi + ti_ * qr;
-                }
-            }
-        }
-        __syncthreads();
-        // w = p - (tau/2) (p^H v) v
-        double hr = 0.0, hi = 0.0;
-        for (int i = tid; i < m; i += TB) {
-            const double pr = p[2 * i], pi = p[2 * i + 1], vr = v[2 * i], vi = v[2 * i + 1];
-            hr += pr * vr + pi * vi;
-            hi += pr * vi - pi * vr;
-        }
-        block_sum2(hr, hi, red);
-        const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
-        for (int i = tid; i < m; i += TB) {
-            const double vr = v[2 * i], vi = v[2 * i + 1];
-            p[2 * i] += a2r * vr - a2i * vi;
-            p[2 * i + 1] += a2r * vi + a2i * vr;
-        }
-        __syncthreads();
-        // A22 -= v w^H + w v^H, four rows per wave at a time
-        for (int r0 = 4 * w; r0 < m; r0 += 4 * NW) {
-            for (int c = lane; c < m; c += 64) {
-                const double vcr = v[2 * c], vci = v[2 * c + 1], wcr = p[2 * c], wci = p[2 * c + 1];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = r0 + q;
-                    if (r < m) {
-                        const double vr = v[2 * r], vi = v[2 * r + 1], wr = p[2 * r], wi = p[2 * r + 1];
-                        double* h = H + 2 * (base + (long)r * ld + c);
-                        h[0] -= vr * wcr + vi * wci + wr * vcr + wi * vci;
-                        h[1] -= vi * wcr - vr * wci + wi * vcr - wr * vci;
-                    }
-                }
-            }
-        }
-        __syncthreads();
     }
-    if (tid == 0) dg[n - 1] = H[2 * ((long)(n - 1) * ld + (n - 1))];
+    __syncthreads();
+    // p = tau A22 v over this workgroup's rows
+    const long base = (long)(j + 1) * ld + (j + 1);
+    const int nw = gridDim.x * RWV;
+    for (int r0 = ROWS_PER_WAVE * (blockIdx.x * RWV + w); r0 < m; r0 += ROWS_PER_WAVE * nw) {
+        double ar[ROWS_PER_WAVE], ai[ROWS_PER_WAVE];
+#pragma unroll
+        for (int q = 0; q < ROWS_PER_WAVE; ++q) ar[q] = ai[q] = 0.0;
+        for (int c = lane; c < m; c += 64) {
+            const double vr = v[2 * c], vi = v[2 * c + 1];
+#pragma unroll
+            for (int q = 0; q < ROWS_PER_WAVE; ++q) {
+                if (r0 + q < m) {
+                    const double* h = H + 2 * (base + (long)(r0 + q) * ld + c);
+                    const double hr = h[0], hi = h[1];
+                    ar[q] += hr * vr - hi * vi;
+                    ai[q] += hr * vi + hi * vr;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ROWS_PER_WAVE; ++q) {
+            const double qr = wave_sum(ar[q]), qi = wave_sum(ai[q]);
+            if (lane == 0 && r0 + q < m) {
+                pbuf[2 * (r0 + q)] = tr_ * qr - ti_ * qi;
+                pbuf[2 * (r0 + q) + 1] = tr_ * qi + ti_ * qr;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(RW) void tri_rank2_kernel(double* __restrict__ H, int ld, int n, int j,
+                                                       const double* __restrict__ tau,
+                                                       const double* __restrict__ vbuf,
+                                                       const double* __restrict__ pbuf) {
+    __shared__ double v[2 * TRI_MAX];
+    __shared__ double p[2 * TRI_MAX];
+    __shared__ double red[2 * RWV];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m = n - j - 1;
+    const double tr_ = tau[2 * j], ti_ = tau[2 * j + 1];
+    if (tr_ == 0.0 && ti_ == 0.0) return;   // H_j = I: the same for every workgroup
+    double hr = 0.0, hi = 0.0;
+    for (int i = tid; i < 2 * m; i += RW) {
+        v[i] = vbuf[i];
+        p[i] = pbuf[i];
+    }
+    __syncthreads();
+    // w = p - (tau/2) (p^H v) v
+    for (int i = tid; i < m; i += RW) {
+        const double pr = p[2 * i], pi = p[2 * i + 1], vr = v[2 * i], vi = v[2 * i + 1];
+        hr += pr * vr + pi * vi;
+        hi += pr * vi - pi * vr;
+    }
+    block_sum2<RWV>(hr, hi, red);
+    const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
+    for (int i = tid; i < m; i += RW) {
+        const double vr = v[2 * i], vi = v[2 * i + 1];
+        p[2 * i] += a2r * vr - a2i * vi;
+        p[2 * i + 1] += a2r * vi + a2i * vr;
+    }
+    __syncthreads();
+    // A22 -= v w^H + w v^H over this workgroup's rows
+    const long base = (long)(j + 1) * ld + (j + 1);
+    const int nw = gridDim.x * RWV;
+    for (int r0 = ROWS_PER_WAVE * (blockIdx.x * RWV + w); r0 < m; r0 += ROWS_PER_WAVE * nw) {
+        for (int c = lane; c < m; c += 64) {
+            const double vcr = v[2 * c], vci = v[2 * c + 1], wcr = p[2 * c], wci = p[2 * c + 1];
+#pragma unroll
+            for (int q = 0; q < ROWS_PER_WAVE; ++q) {
+                const int r = r0 + q;
+                if (r < m) {
+                    const double vr = v[2 * r], vi = v[2 * r + 1], wr = p[2 * r], wi = p[2 * r + 1];
+                    double* h = H + 2 * (base + (long)r * ld + c);
+                    h[0] -= vr * wcr + vi * wci + wr * vcr + wi * vci;
+                    h[1] -= vi * wcr - vr * wci + wi * vcr - wr * vci;
+                }
+            }
+        }
+    }
+}
+
+__global__ void tri_last_kernel(const double* __restrict__ H, int ld, int n, double* __restrict__ dg) {
+    if (threadIdx.x == 0) dg[n - 1] = H[2 * ((long)(n - 1) * ld + (n - 1))];
 }
 
 // On-chip reduction for orders <= RMAX.  The lower triangle is cut into 8 x 8 tiles (diagonal
@@ -907,6 +958,7 @@ size_t tri_work_bytes(int n) {
     b += P_COUNT * sizeof(double);                // par
     b += (size_t)n * n * 2 * sizeof(double);      // reflector rows
     b += (size_t)n * n * sizeof(double);          // Z
+    b += (size_t)n * 4 * sizeof(double);          // v and p of the multi-workgroup reduction
     return b + 1024;
 }
 
@@ -923,12 +975,24 @@ hipError_t eigh_top(hipStream_t s, int n, double* H, int ldh, int level, double 
     double* par = trace + 64;
     double* refl = par + P_COUNT;
     double* Z = refl + (size_t)n * n * 2;
+    double* vbuf = Z + (size_t)n * n;
+    double* pbuf = vbuf + 2 * (size_t)n;
     const double nn = (double)n;
     if (prof) prof->begin(s, PF_TRI_REDUCE);
     if (n <= RMAX)
         hipLaunchKernelGGL(tri_reduce_reg_kernel, dim3(1), dim3(RB), 0, s, H, ldh, n, dg, off, tv, refl, trace);
     else
-        hipLaunchKernelGGL(tri_reduce_kernel, dim3(1), dim3(TB), 0, s, H, ldh, n, dg, off, tv, refl, trace);
+    {
+        hipLaunchKernelGGL(tri_herm_kernel, dim3(reduce_groups(n)), dim3(RW), 0, s, H, ldh, n);
+        hipLaunchKernelGGL(tri_trace_kernel, dim3(1), dim3(RW), 0, s, H, ldh, n, trace);
+        for (int j = 0; j < n - 1; ++j) {
+            const int g = reduce_groups(n - j - 1);
+            hipLaunchKernelGGL(tri_hh_symv_kernel, dim3(g), dim3(RW), 0, s, H, ldh, n, j, dg, off, tv, refl, vbuf,
+                               pbuf);
+            hipLaunchKernelGGL(tri_rank2_kernel, dim3(g), dim3(RW), 0, s, H, ldh, n, j, tv, vbuf, pbuf);
+        }
+        hipLaunchKernelGGL(tri_last_kernel, dim3(1), dim3(64), 0, s, H, ldh, n, dg);
+    }
     // Hermitian tridiagonal reduction: 16/3 n^3 real flop; the matrix is read and rewritten
     // once per column
     if (prof) prof->end(s, PF_TRI_REDUCE, 16.0 / 3.0 * nn * nn * nn, 16.0 * nn * nn * 2.0);
