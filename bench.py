@@ -91,6 +91,86 @@ def _batch(count: int, workers: int) -> dict:
             "max_bond": max(max(r["bonds"]) for r in res)}
 
 
+def _saturated(max_warm: int, precisions) -> dict:
+    """The saturated steady state at chi = 512: the benchmark circuit's gate set (seed-0 angles,
+    rates 1e-3) on a 20-atom chain, layers run untimed until the three centre bonds are at 512
+    (at most `max_warm` layers; six in FP64, seven in FP32), then one more layer in which only
+    the two-site updates whose three bonds are all 512 (theta of 8192 x 8192 at rank <= 4608)
+    are timed, each bracketed by synchronisations.  The FP32 run uses a cutoff of 1e-12
+    sigma_1 instead of its default 1e-6 so that its bonds grow to the same size; its energy
+    is compared with the FP64 run's after the same number of layers where both ran as many.
+    FP32 products resolve Schmidt values only down to their rounding floor, so the FP32 run
+    may not saturate at all; its record then shows no timed updates and its largest bond."""
+    import numpy as np
+    import torch
+    from paper_2309_08572_amd import circuits, mpdo
+    from workloads import config_m3
+    n, chi = 20, 512
+    spec = config_m3(0, n=n, p=10, chi=chi)          # one fixed angle set for up to 10 layers
+    max_warm = min(max_warm, spec.p - 1)
+    modes = {"fp64": mpdo.MPDO_FP64, "fp32": mpdo.MPDO_FP32}
+    res = {}
+
+    def layer(m, k, timed):
+        kr = circuits.block_kraus(spec.gamma[k], spec.p_leak, spec.d)
+        times, prof = [], None
+        for i in circuits.bond_order(n):
+            b = m.bond_dims()
+            sat = 0 < i < n - 2 and b[i - 1] >= chi and b[i] >= chi and b[i + 1] >= chi
+            if timed and sat:
+                m.profile(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            m.apply_gate_kraus(i, kr)
+            if timed and sat:
+                m.synchronize()
+                times.append(time.perf_counter() - t0)
+                p = m.profile_read()
+                m.profile(False)
+                prof = p if prof is None else {f: {q: prof[f][q] + p[f][q] for q in p[f]} for f in p}
+        for j in range(n):
+            m.apply_channel(j, [circuits.x_rotation(spec.beta[k], spec.d)])
+            m.apply_channel(j, circuits.dephasing_kraus(spec.p_deph, spec.d))
+            m.apply_channel(j, circuits.decay_kraus(spec.p_decay, spec.d))
+        return times, prof
+
+    for name in precisions:
+        m = mpdo.MPDO(n, spec.d, chi, precision=modes[name], cutoff_rel=1e-14 if name == "fp64" else 1e-12)
+        m.init_product_state([circuits.plus_rho(spec.d)] * n)
+        warm = 0
+        while warm < max_warm and min(m.bond_dims()[n // 2 - 2:n // 2 + 1]) < chi:
+            layer(m, warm, False)
+            warm += 1
+        times, prof = layer(m, warm, True)
+        obs = circuits.observables(m)
+        g = prof["gemm"] if prof else {"flops": 0.0, "ms": 0.0, "launches": 0}
+        t = float(np.sum(times)) if times else 0.0
+        res[name] = {
+            "untimed_layers": warm,
+            "saturated_updates": len(times),
+            "updates_per_s": len(times) / t if t else 0.0,
+            "ms_per_update": 1e3 * t / len(times) if times else 0.0,
+            "gemm_tflops_per_update_time": g["flops"] / t / 1e12 if t else 0.0,
+            "gemm": {"launches": g["launches"], "ms": g["ms"], "flop": g["flops"],
+                     "achieved_tflops": g["flops"] / (1e-3 * g["ms"]) / 1e12 if g["ms"] else 0.0,
+                     "peak_tflops": PEAK["fp64_mfma"] if name == "fp64" else PEAK["fp32_mfma"]},
+            "kernel_ms": {f: v["ms"] for f, v in (prof or {}).items() if v["launches"]},
+            "energy_per_site": obs["energy_per_site"],
+            "max_bond": max(m.bond_dims()),
+        }
+        m.close()
+    out = {"workload": f"noisy QAOA gate set, N={n} atoms, d=4, chi_max={chi}, seed 0, rates 1e-3: untimed "
+                       f"layers until the centre bonds reach {chi}, then the updates of the next layer with "
+                       f"chi_l = chi_m = chi_r = {chi}",
+           **res}
+    if "fp64" in res and "fp32" in res and res["fp32"]["updates_per_s"] and res["fp64"]["updates_per_s"]:
+        out["fp32_speedup_vs_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
+        if res["fp32"]["untimed_layers"] == res["fp64"]["untimed_layers"]:
+            out["fp32_abs_err_energy_per_site_vs_fp64"] = abs(res["fp32"]["energy_per_site"] -
+                                                              res["fp64"]["energy_per_site"])
+    return out
+
+
 def _pulse_gate(n_steps: int) -> dict:
     """The pulse-level gate builder on the paper's Gaussian CZ pulse (d=4, dissipation 0.001/T,
     branching 1/16, 1/16, 7/8): wall time of one call, host in and host out."""
@@ -184,6 +264,9 @@ def main() -> int:
                     help="also time this many circuits of the 256-circuit batch workload "
                          "(one per worker stream vs one at a time)")
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--saturated-layers", type=int, default=8,
+                    help="at most this many untimed layers before the saturated chi=512 updates are timed "
+                         "(0: skip that leg)")
     ap.add_argument("--pulse-steps", type=int, default=20000,
                     help="also time the pulse-level CZ gate builder with this many steps (0: skip)")
     args = ap.parse_args()
@@ -266,6 +349,8 @@ def main() -> int:
         out["batch"] = _batch(args.batch_circuits, args.workers)
     if args.pulse_steps > 0:
         out["pulse_gate"] = _pulse_gate(args.pulse_steps)
+    if args.saturated_layers > 0:
+        out["saturated"] = _saturated(args.saturated_layers, run)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(spec, args.cpu_baseline_seconds)
     print(json.dumps(out))

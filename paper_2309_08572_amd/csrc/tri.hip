@@ -144,12 +144,13 @@ __global__ __launch_bounds__(RW) void tri_hh_symv_kernel(const double* __restric
     __shared__ double sc[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m = n - j - 1;
-    // x = column j below the diagonal
+    // x = column j below the diagonal, read as the conjugate of row j right of the diagonal
+    // (contiguous; the trailing updates keep the matrix Hermitian to rounding)
     double x2 = 0.0, unused = 0.0;
     for (int i = tid; i < m; i += RW) {
-        const double* h = H + 2 * ((long)(j + 1 + i) * ld + j);
+        const double* h = H + 2 * ((long)j * ld + (j + 1 + i));
         v[2 * i] = h[0];
-        v[2 * i + 1] = h[1];
+        v[2 * i + 1] = -h[1];
         if (i > 0) x2 += h[0] * h[0] + h[1] * h[1];
     }
     block_sum2<RWV>(x2, unused, red);
