@@ -150,7 +150,9 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
         }
         __syncthreads();
         if (k0 + BK < kend) fetch(k0 + BK);
-#pragma unroll
+        // unrolled by two: a full unroll hoists all eight k-steps' operands into registers and
+        // leaves one wave per SIMD (308 registers); by two the FP64 kernel fits two waves
+#pragma unroll 2
         for (int kk = 0; kk < BK; kk += 4) {
             T ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
