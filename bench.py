@@ -154,6 +154,13 @@ def _saturated(max_warm: int, precisions) -> dict:
             "gemm": {"launches": g["launches"], "ms": g["ms"], "flop": g["flops"],
                      "achieved_tflops": g["flops"] / (1e-3 * g["ms"]) / 1e12 if g["ms"] else 0.0,
                      "peak_tflops": PEAK["fp64_mfma"] if name == "fp64" else PEAK["fp32_mfma"]},
+            "roofline": {"bound": "mfma", "kernel_family": "gemm",
+                         "achieved": g["flops"] / (1e-3 * g["ms"]) / 1e12 if g["ms"] else 0.0,
+                         "peak": PEAK["fp64_mfma"] if name == "fp64" else PEAK["fp32_mfma"], "unit": "TFLOP/s",
+                         "frac": (g["flops"] / (1e-3 * g["ms"]) / 1e12 if g["ms"] else 0.0) /
+                                 (PEAK["fp64_mfma"] if name == "fp64" else PEAK["fp32_mfma"]),
+                         "traffic": None, "launches": g["launches"],
+                         "avg_launch_us": 1e3 * g["ms"] / g["launches"] if g["launches"] else 0.0},
             "kernel_ms": {f: v["ms"] for f, v in (prof or {}).items() if v["launches"]},
             "energy_per_site": obs["energy_per_site"],
             "max_bond": max(m.bond_dims()),

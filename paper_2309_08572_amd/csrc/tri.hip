@@ -301,11 +301,34 @@ static_assert((RMAX / RT) * (RMAX / RT + 1) / 2 <= RG * RS, "tiles of the larges
 struct RedLds {
     double tr[RS_LDS][RT][RB];   // LDS tiles, [slot][column][lane]
     double ti[RS_LDS][RT][RB];
-    double vabs[2 * RMAX];
+    double vabs[2 * RMAX];       // column j below the diagonal (absolute rows)
+    double v[2 * RMAX];          // Householder vector (absolute rows, zero outside the block)
     double pabs[2 * RMAX];
-    double red[2 * RNW];
-    double sc[4];
+    double red[2 * RNW];         // the two per-column reductions alternate between red and
+    double red2[2 * RNW];        // red2, so each needs only the barrier after its writes
 };
+
+// Workgroup sums of a and b with one barrier: `red` must not be written again before every
+// thread has passed another barrier (callers alternate two buffers).
+template <int NWV>
+__device__ __forceinline__ void block_sum2_once(double& a, double& b, double* red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int q = 0; q < NWV; ++q) {
+        sa += red[2 * q];
+        sb += red[2 * q + 1];
+    }
+    a = sa;
+    b = sb;
+}
 
 // sum over the 8 lanes of an aligned group, returned to all 8 (DPP: quad xor 1, quad xor 2,
 // then the mirror inside each half-row brings in the other quad; no LDS traffic)
@@ -484,6 +507,7 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
     }
     for (int i = tid; i < 2 * RMAX; i += RB) {
         L.vabs[i] = 0.0;
+        L.v[i] = 0.0;
         L.pabs[i] = 0.0;
     }
     {
@@ -507,10 +531,12 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
 #pragma unroll
         for (int s = 0; s < RS_LDS; ++s)
             tile_extract(LdsRow{L.tr[s], L.ti[s], tid}, tI[RS_REG + s], tJ[RS_REG + s], j, k, n, L.vabs, dg, x2);
-        block_sum2<RNW>(x2, unused, L.red);
-        if (tid == 0) {
+        block_sum2_once<RNW>(x2, unused, L.red);
+        // every thread forms the reflector scalars itself (same inputs, same result)
+        double tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
+        {
             const double arr = L.vabs[2 * (j + 1)], aii = L.vabs[2 * (j + 1) + 1];
-            double beta, tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
+            double beta;
             if (x2 == 0.0 && aii == 0.0) {
                 beta = arr;
             } else {
@@ -521,16 +547,12 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
                 sr = dr / den;
                 si = -di / den;
             }
-            L.sc[0] = tr_;
-            L.sc[1] = ti_;
-            L.sc[2] = sr;
-            L.sc[3] = si;
-            off[j] = beta;
-            tau[2 * j] = tr_;
-            tau[2 * j + 1] = ti_;
+            if (tid == 0) {
+                off[j] = beta;
+                tau[2 * j] = tr_;
+                tau[2 * j + 1] = ti_;
+            }
         }
-        __syncthreads();
-        const double tr_ = L.sc[0], ti_ = L.sc[1], sr = L.sc[2], si = L.sc[3];
         // v (absolute index, zero at rows <= j), reflector row j; clear the accumulator
         for (int i = tid; i < n; i += RB) {
             double vr = 0.0, vi = 0.0;
@@ -541,8 +563,8 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
                 vr = xr * sr - xi * si;
                 vi = xr * si + xi * sr;
             }
-            L.vabs[2 * i] = vr;
-            L.vabs[2 * i + 1] = vi;
+            L.v[2 * i] = vr;
+            L.v[2 * i + 1] = vi;
             if (i > j) {
                 refl[2 * ((long)j * n + (i - j - 1))] = vr;
                 refl[2 * ((long)j * n + (i - j - 1)) + 1] = vi;
@@ -557,13 +579,13 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
         for (int s = 0; s < RS_REG; ++s)
             if (tile_live(tI[s], tJ[s], j)) {
                 RegRow x{ar[s], ai[s]};
-                tile_matvec(x, tI[s], tJ[s], k, L.vabs, L.pabs);
+                tile_matvec(x, tI[s], tJ[s], k, L.v, L.pabs);
             }
 #pragma unroll
         for (int s = 0; s < RS_LDS; ++s)
             if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
                 LdsRow x{L.tr[s], L.ti[s], tid};
-                tile_matvec(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.vabs, L.pabs);
+                tile_matvec(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.pabs);
             }
         __syncthreads();
         // p <- tau p; w = p - (tau/2)(p^H v) v
@@ -573,16 +595,16 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
             const double pr = tr_ * pr0 - ti_ * pi0, pi = tr_ * pi0 + ti_ * pr0;
             L.pabs[2 * i] = pr;
             L.pabs[2 * i + 1] = pi;
-            const double vr = L.vabs[2 * i], vi = L.vabs[2 * i + 1];
+            const double vr = L.v[2 * i], vi = L.v[2 * i + 1];
             hr += pr * vr + pi * vi;
             hi += pr * vi - pi * vr;
         }
-        block_sum2<RNW>(hr, hi, L.red);
+        block_sum2_once<RNW>(hr, hi, L.red2);
         const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
         for (int i = tid; i < RMAX; i += RB) {
             double wr = 0.0, wi = 0.0;
             if (i > j && i < n) {
-                const double vr = L.vabs[2 * i], vi = L.vabs[2 * i + 1];
+                const double vr = L.v[2 * i], vi = L.v[2 * i + 1];
                 wr = L.pabs[2 * i] + a2r * vr - a2i * vi;
                 wi = L.pabs[2 * i + 1] + a2r * vi + a2i * vr;
             }
@@ -595,13 +617,13 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
         for (int s = 0; s < RS_REG; ++s)
             if (tile_live(tI[s], tJ[s], j)) {
                 RegRow x{ar[s], ai[s]};
-                tile_update(x, tI[s], tJ[s], k, L.vabs, L.pabs);
+                tile_update(x, tI[s], tJ[s], k, L.v, L.pabs);
             }
 #pragma unroll
         for (int s = 0; s < RS_LDS; ++s)
             if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
                 LdsRow x{L.tr[s], L.ti[s], tid};
-                tile_update(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.vabs, L.pabs);
+                tile_update(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.pabs);
             }
         __syncthreads();
     }
