@@ -14,6 +14,12 @@
 // each view so loads coalesce whichever way the view is laid out.  Large-k products with a
 // small output (Gram matrices of tall factors) split k over blockIdx.z and accumulate with
 // FP64/FP32 atomics into a zeroed output.
+#include <stdlib.h>
+
+#include <mutex>
+#include <type_traits>
+#include <unordered_map>
+
 #include "common.h"
 #include "gemm.h"
 
@@ -230,12 +236,23 @@ __global__ void cscale_kernel(CView<T> C, int M, int N, double br, double bi) {
     C.p[off + 1] = (T)(C.conj ? -vi : vi);
 }
 
-}  // namespace
+// Split of the k range over workgroups for an output of `tiles` 64 x 64 tiles: the output alone
+// cannot fill the 256 compute units below 192 tiles, and one 64 x 64 x 32 complex k-step keeps
+// a CU's FP64 matrix cores busy for ~3.4 us, so small outputs are spread over the chip in
+// k-chunks of at least 64.
+int heuristic_ksplit(int tiles, int K) {
+    if (tiles >= 192 || K < 128) return 1;
+    int ks = (768 + tiles - 1) / tiles;
+    const int maxks = K / 64;
+    if (ks > maxks) ks = maxks;
+    if (ks > 64) ks = 64;
+    return ks < 1 ? 1 : ks;
+}
 
+// One product with the k range split `ks` ways (ks = 1: no split).
 template <typename T>
-hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
-                 CView<T> C, int batch, long sA, long sB, long sC, ProfSink* prof) {
-    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
+                        int batch, long sA, long sB, long sC, int ks, ProfSink* prof) {
     GemmArgs<T> g;
     g.M = M;
     g.N = N;
@@ -255,33 +272,23 @@ hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView
     g.ksplit = 1;
     g.kchunk = ((g.K + BK - 1) / BK) * BK;
     if (g.kchunk == 0) g.kchunk = BK;
-    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
-    // split long reductions when the output alone cannot fill the 256 compute units
-    // (one 64 x 64 x 32 complex k-step keeps a CU's FP64 matrix cores busy for ~3.4 us, so
-    // small outputs are spread over the chip in k-chunks of at least 64)
-    if (tiles < 192 && g.K >= 128) {
-        int ks = (768 + tiles - 1) / tiles;
-        const int maxks = g.K / 64;
-        if (ks > maxks) ks = maxks;
-        if (ks > 64) ks = 64;
+    if (ks >= 2) {
+        const int chunk = (((g.K + ks - 1) / ks + BK - 1) / BK) * BK;
+        ks = (g.K + chunk - 1) / chunk;
         if (ks >= 2) {
-            const int chunk = (((g.K + ks - 1) / ks + BK - 1) / BK) * BK;
-            ks = (g.K + chunk - 1) / chunk;
-            if (ks >= 2) {
-                // C <- beta*C first, then accumulate alpha*AB atomically
-                const long tot = (long)M * N;
-                if (prof) prof->begin(s, PF_OTHER);
-                for (int bb = 0; bb < batch; ++bb) {
-                    CView<T> Cb = C;
-                    Cb.p = C.p + 2 * (long)bb * sC;
-                    hipLaunchKernelGGL(cscale_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                                       Cb, M, N, beta.re, beta.im);
-                }
-                if (prof) prof->end(s, PF_OTHER, 0.0, 2.0 * sizeof(T) * (double)tot * batch);
-                g.ksplit = ks;
-                g.kchunk = chunk;
-                g.atomic = 1;
+            // C <- beta*C first, then accumulate alpha*AB atomically
+            const long tot = (long)M * N;
+            if (prof) prof->begin(s, PF_OTHER);
+            for (int bb = 0; bb < batch; ++bb) {
+                CView<T> Cb = C;
+                Cb.p = C.p + 2 * (long)bb * sC;
+                hipLaunchKernelGGL(cscale_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Cb, M, N,
+                                   beta.re, beta.im);
             }
+            if (prof) prof->end(s, PF_OTHER, 0.0, 2.0 * sizeof(T) * (double)tot * batch);
+            g.ksplit = ks;
+            g.kchunk = chunk;
+            g.atomic = 1;
         }
     }
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * g.ksplit);
@@ -296,6 +303,104 @@ hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView
         prof->end(s, PF_GEMM, flop, bytes);
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- autotuner of the k split
+// Shapes are bucketed by the powers of two of M, N, K, the batch and the precision.  With
+// tuning on (environment MPDO_GEMM_AUTOTUNE=1), the first product of a bucket with beta = 0
+// (the output then does not depend on its old contents) is run with each candidate split on
+// its stream between HIP events, the fastest is cached for the bucket, and the product is run
+// once more with it; later products of the bucket use the cached split.  With tuning off, or
+// with beta != 0, the heuristic above decides.  The cache is shared by all threads.
+struct TuneKey {
+    int m, n, k, batch, fp64;
+    bool operator==(const TuneKey& o) const {
+        return m == o.m && n == o.n && k == o.k && batch == o.batch && fp64 == o.fp64;
+    }
+};
+struct TuneHash {
+    size_t operator()(const TuneKey& t) const {
+        return (((size_t)t.m * 131 + t.n) * 131 + t.k) * 131 + (size_t)t.batch * 2 + t.fp64;
+    }
+};
+std::mutex g_tune_mutex;
+std::unordered_map<TuneKey, int, TuneHash> g_tune;
+
+int log2_bucket(long x) {
+    int b = 0;
+    while ((1L << b) < x) ++b;
+    return b;
+}
+
+bool autotune_on() {
+    const char* e = getenv("MPDO_GEMM_AUTOTUNE");
+    return e && atoi(e) != 0;
+}
+
+template <typename T>
+int tune_ksplit(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
+                int batch, long sA, long sB, long sC, int tiles) {
+    const TuneKey key{log2_bucket(M), log2_bucket(N), log2_bucket(K), log2_bucket(batch),
+                      std::is_same<T, double>::value ? 1 : 0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
+    const int h = heuristic_ksplit(tiles, K);
+    int cands[8], nc = 0;
+    cands[nc++] = 1;
+    for (int ks = 2; ks <= 64 && ks <= K / 64; ks *= 2) cands[nc++] = ks;
+    if (h > 1) {
+        bool have = false;
+        for (int i = 0; i < nc; ++i) have = have || cands[i] == h;
+        if (!have && nc < 8) cands[nc++] = h;
+    }
+    int best = h;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return h;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return h;
+    }
+    for (int i = 0; i < nc; ++i) {
+        // one untimed run, then one timed
+        if (cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, cands[i], nullptr) != hipSuccess)
+            continue;
+        (void)hipEventRecord(e0, s);
+        (void)cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, cands[i], nullptr);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    g_tune[key] = best;
+    return best;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
+                 CView<T> C, int batch, long sA, long sB, long sC, ProfSink* prof) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+    int ks = heuristic_ksplit(tiles, K < 0 ? 0 : K);
+    if (autotune_on() && beta.re == 0.0 && beta.im == 0.0 && K >= 128)
+        ks = tune_ksplit<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, tiles);
+    return cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, ks, prof);
+}
+
+int gemm_tuned_buckets() {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    return (int)g_tune.size();
 }
 
 template hipError_t cgemm<double>(hipStream_t, int, int, int, cd, CView<double>, CView<double>, cd,

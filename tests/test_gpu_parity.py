@@ -185,3 +185,21 @@ def test_bad_arguments_raise():
     # the context is still usable
     m.apply_gate_kraus(0, circuits.block_kraus(0.3, 0.01, 4))
     assert abs(m.trace() - 1.0) < 1e-13
+
+
+def test_gemm_autotuner_gives_the_same_circuit(monkeypatch):
+    """With the k-split autotuner on (MPDO_GEMM_AUTOTUNE=1) every product is still computed by
+    the same kernel, only split differently over k: the N=16 circuit must agree with the
+    untuned run to the FP64 bar (rounding of the split sums only)."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08572_amd import circuits
+    from workloads.qaoa import config_m1
+    spec = config_m1(0, n=16)
+    print("[gpu] M1-shaped N=16, GEMM autotuner off / on", flush=True)
+    ref = circuits.observables(circuits.run_circuit(spec))
+    monkeypatch.setenv("MPDO_GEMM_AUTOTUNE", "1")
+    got = circuits.observables(circuits.run_circuit(spec))
+    assert abs(got["energy_per_site"] - ref["energy_per_site"]) <= 1e-10 * max(1.0, abs(ref["energy_per_site"]))
+    np.testing.assert_allclose(got["populations"], ref["populations"], rtol=0, atol=1e-10)
