@@ -21,6 +21,25 @@
  *    and later calls return MPDO_E_STATE.  An infeasible PPT cut is not an error: it falls
  *    back to theta = 0 (end of Sec. III.D) and is reported in mpdo_trunc_info.
  *  - A context is not re-entrant; use one context per stream.
+ *
+ * Numerical safeguards of the two-site update (apply_gate, apply_gate_kraus, truncate)
+ *  - Every orthonormal basis built by the split (range bases, Schmidt vectors) is checked
+ *    before the new sites are written: ||Q||_F^2 must equal its column count to 1e-9 (FP64)
+ *    or 1e-3 (FP32) with no non-finite entry, otherwise the update returns MPDO_E_NUMERIC
+ *    ("orthonormal basis lost accuracy") instead of committing a wrong state.
+ *  - Splits whose exact range basis would need a Hermitian eigenproblem above order 1024
+ *    (the saturated chi = 512 regime) build the basis of the dominant left singular subspace
+ *    by block subspace iteration (chi + 256 directions, stopped when the captured weight
+ *    changes by less than 1e-10 of itself) and split its core exactly; the weight it misses
+ *    lies below the chi cut.
+ *
+ * Environment (read at each use)
+ *   MPDO_DEBUG_CHECKS=1         print every orthonormality check and block-Jacobi sweep count
+ *                               to stderr
+ *   MPDO_SUBSPACE_MIN_ORDER=n   use the subspace iteration above order n (< 1024) instead of
+ *                               1024, for testing it where the exact split also runs
+ *   MPDO_GEMM_AUTOTUNE=1        time the k split of each GEMM shape bucket on first use and
+ *                               keep the fastest (default: a fixed heuristic)
  */
 #ifndef MPDO_H
 #define MPDO_H

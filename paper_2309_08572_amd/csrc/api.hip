@@ -45,9 +45,9 @@ constexpr int EIG_MAX_SWEEPS = 40;
 // Range bases whose exact construction would need an eigenproblem above TRI_MAX are found by
 // block subspace iteration on theta theta^H: SUB_OVER extra directions beyond chi, at most
 // SUB_ITERS passes, stopping once the captured weight ||Q^H theta||_F^2 grows by less than the
-// tolerance (relative; FP64 1e-12, FP32 1e-6).
+// tolerance (relative; FP64 1e-10, FP32 1e-6), far below the weight a chi-cut discards there.
 constexpr int SUB_OVER = 256;
-constexpr int SUB_ITERS = 12;
+constexpr int SUB_ITERS = 8;
 
 // Order above which a split uses the subspace iteration: TRI_MAX, or MPDO_SUBSPACE_MIN_ORDER
 // from the environment (lower values let tests run the subspace path where the exact path
@@ -403,7 +403,7 @@ struct Engine {
         ++nchk;
     }
     void orth_verify() {
-        static const int dbg = getenv("MPDO_DEBUG_CHECKS") != nullptr;
+        const bool dbg = getenv("MPDO_DEBUG_CHECKS") != nullptr;
         if (nchk == 0) return;
         const int m = nchk;
         nchk = 0;
@@ -496,7 +496,7 @@ struct Engine {
                        long ldq, T* Kout, long ldk) {
         const int rank_bound = Fb ? std::min(k, std::min(na, nb)) : std::min(na, nb);
         const int m = std::min(chi + SUB_OVER, rank_bound);
-        const double tol = std::is_same<T, double>::value ? 1e-12 : 1e-6;
+        const double tol = std::is_same<T, double>::value ? 1e-10 : 1e-6;
         T* X = s.bR;     // nb x cols: random start block, then orth(theta^H Q)
         T* T1 = s.bU;    // k x cols, Fb X
         T* Y = s.bC;     // na x cols
