@@ -23,7 +23,6 @@
 #include <complex>
 #include <memory>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/mpdo.h"
@@ -73,14 +72,23 @@ inline cd C1() { return cd{1.0, 0.0}; }
 inline cd C0() { return cd{0.0, 0.0}; }
 inline cd Cr(double x) { return cd{x, 0.0}; }
 
-uint64_t fnv1a(const void* p, size_t n) {
+// 64-bit lookup key of a byte range: four independent multiply-xorshift lanes over 8-byte
+// words, the tail byte by byte.  Only a key: every cache hit is confirmed by comparing the data.
+uint64_t hash_bytes(const void* p, size_t n, uint64_t seed) {
     const unsigned char* b = (const unsigned char*)p;
-    uint64_t h = 1469598103934665603ull;
-    for (size_t i = 0; i < n; ++i) {
-        h ^= b[i];
-        h *= 1099511628211ull;
-    }
-    return h;
+    uint64_t h[4] = {seed, seed ^ 0x9E3779B97F4A7C15ull, seed ^ 0xC2B2AE3D27D4EB4Full, seed ^ 0x165667B19E3779F9ull};
+    size_t i = 0;
+    for (; i + 32 <= n; i += 32)
+        for (int l = 0; l < 4; ++l) {
+            uint64_t w;
+            memcpy(&w, b + i + 8 * l, 8);
+            h[l] = (h[l] ^ w) * 0x9E3779B97F4A7C15ull;
+            h[l] ^= h[l] >> 29;
+        }
+    uint64_t r = h[0] ^ (h[1] * 3) ^ (h[2] * 5) ^ (h[3] * 7) ^ n;
+    for (; i < n; ++i) r = (r ^ b[i]) * 0x100000001B3ull;
+    r ^= r >> 31;
+    return r * 0xBF58476D1CE4E5B9ull;
 }
 
 // ---------------------------------------------------------------------- device arena
@@ -221,6 +229,21 @@ struct GateFactor {
     double* Y = nullptr;
 };
 
+// A two-site map as an update applies it: the caller's input folded with the single-atom maps
+// queued on the two atoms, with its operator-Schmidt factors.  Keyed by exactly what determines
+// it (input bytes and queued maps), so repeated gates skip the host-side build, fold and
+// factorisation.
+struct FoldEntry {
+    uint64_t id = 0, h = 0, used = 0;
+    int kind = 0;                  // 0: superoperator given, 1: Kraus set given
+    std::vector<double> in;        // the caller's input as given
+    bool ida = true, idb = true;   // nothing queued on atom i / atom i+1
+    std::vector<zc> pa, pb;        // the queued maps otherwise
+    GateFactor gf;                 // X, Y null: the update takes the explicit path
+    std::vector<zc> S;             // the folded superoperator (read by the explicit path)
+};
+constexpr int FOLD_CACHE_MAX = 64;
+
 }  // namespace
 
 // ====================================================================== context
@@ -260,9 +283,12 @@ struct mpdo_ctx_s {
     Scratch<double> sd;           // FP64 scratch (all work in FP64 mode; eigen/PPT always)
     Scratch<float> sf;            // FP32 scratch (FP32 mode)
     Scratch<double> sg;           // small FP64 scratch for gate factorisation (D2^2)
-    std::unordered_map<uint64_t, GateFactor> gcache;
-    std::vector<uint64_t> gorder;
-    std::vector<double*> gslots;  // free device slots for operator-Schmidt factors
+    std::vector<FoldEntry> fcache;    // folded two-site maps (at most FOLD_CACHE_MAX)
+    uint64_t fclock = 0, fnext = 1;
+    uint64_t sdev_id = 0;            // entry whose superoperator is in Sdev / SdevT (0: none)
+    const std::vector<zc>* Scur = nullptr;   // host copy of the current update's superoperator
+    uint64_t Scur_id = 0;
+    std::vector<double*> gslots;     // free device slots for operator-Schmidt factors
     std::unique_ptr<EventProf> prof;   // non-null while measurement is on
     double prof_acc[4 * PF_COUNT] = {0};
     double* obuf = nullptr;       // operator vectors of one expectation term (N x D2)
@@ -296,6 +322,19 @@ struct Engine {
     double eps() const { return std::is_same<T, double>::value ? EPS64 : EPS32; }
 
     void sync() { HIPCHK(hipStreamSynchronize(st)); }
+
+    // the superoperator of the current update into Sdev / SdevT, unless it is there already
+    void load_superop() {
+        if (!c.Scur) throw Fail{MPDO_E_STATE, "no superoperator for the explicit update"};
+        if (c.sdev_id == c.Scur_id) return;
+        const int m2 = c.D2 * c.D2;
+        HIPCHK(hipMemcpyAsync(c.Sdev, c.Scur->data(), c.Scur->size() * sizeof(zc), hipMemcpyHostToDevice, st));
+        if (c.fp32)
+            HIPCHK((geam<double, float>(st, m2, m2, C1(), V<double>(c.Sdev, m2, 1), C0(),
+                                        V<float>((float*)c.SdevT, m2, 1))));
+        sync();
+        c.sdev_id = c.Scur_id;
+    }
 
     int read_int(const int* dp) {
         HIPCHK(hipMemcpyAsync(c.hint, dp, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -760,6 +799,7 @@ struct Engine {
         } else {
             // explicit theta: merge then gate
             const int m2 = D2 * D2;
+            load_superop();
             gemm(nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(), V<T>(s.bT1, nR, 1));
             gemm(m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(), V<T>(s.bA, cr, 1), cl, 0,
                  (long)m2 * cr, (long)m2 * cr);
@@ -959,8 +999,9 @@ void alloc_state(mpdo_ctx c) {
     if (c->fp32) c->sf.carve(c->arena, nmax);
     c->sg.carve(c->arena, m2);
     c->gslots.clear();
-    c->gcache.clear();
-    c->gorder.clear();
+    c->fcache.clear();
+    c->sdev_id = 0;
+    c->Scur = nullptr;
     for (int q = 0; q < 128; ++q) c->gslots.push_back(c->arena.take<double>((size_t)MAX_FACTOR_RANK * m2 * 2));
     c->obuf = c->arena.take<double>((size_t)c->N * c->D2 * 2);
     c->o2buf = c->arena.take<double>((size_t)c->N * c->D2 * c->D2 * 2);
@@ -991,12 +1032,29 @@ void set_ovec(mpdo_ctx c, int j) {
     upload(c, c->ovec + 2 * (size_t)j * D2, o.data(), D2 * sizeof(zc));
 }
 
+void release_entry(mpdo_ctx c, size_t k) {
+    FoldEntry& e = c->fcache[k];
+    if (e.gf.X) {
+        c->gslots.push_back(e.gf.X);
+        c->gslots.push_back(e.gf.Y);
+    }
+    if (e.id == c->sdev_id) c->sdev_id = 0;
+    c->fcache.erase(c->fcache.begin() + (long)k);
+}
+
+// index of the least recently used entry (only among those holding factor slots if asked)
+long lru_entry(mpdo_ctx c, bool with_slots) {
+    long k = -1;
+    for (size_t q = 0; q < c->fcache.size(); ++q) {
+        if (with_slots && !c->fcache[q].gf.X) continue;
+        if (k < 0 || c->fcache[q].used < c->fcache[(size_t)k].used) k = (long)q;
+    }
+    return k;
+}
+
 // operator-Schmidt factors of the (D2^2 x D2^2) superoperator S: S = sum_k X_k (x) Y_k
 GateFactor factorize(mpdo_ctx c, const std::vector<zc>& S) {
     const int D2 = c->D2, m2 = D2 * D2;
-    const uint64_t h = fnv1a(S.data(), S.size() * sizeof(zc));
-    auto it = c->gcache.find(h);
-    if (it != c->gcache.end()) return it->second;
     // reshuffle R[(a,c),(b,e)] = S[(a,b),(c,e)]
     std::vector<zc> R((size_t)m2 * m2);
     for (int a = 0; a < D2; ++a)
@@ -1014,18 +1072,12 @@ GateFactor factorize(mpdo_ctx c, const std::vector<zc>& S) {
     if (r > MAX_FACTOR_RANK || r <= 0) {
         gf.X = gf.Y = nullptr;
     } else {
-        // free the oldest cached factors until a slot pair is available
-        while (c->gslots.size() < 2 && !c->gorder.empty()) {
-            const uint64_t old = c->gorder.front();
-            c->gorder.erase(c->gorder.begin());
-            GateFactor o = c->gcache[old];
-            c->gcache.erase(old);
-            if (o.X) {
-                c->gslots.push_back(o.X);
-                c->gslots.push_back(o.Y);
-            }
+        // free the least recently used factors until a slot pair is available
+        while (c->gslots.size() < 2) {
+            const long k = lru_entry(c, true);
+            if (k < 0) throw Fail{MPDO_E_NOMEM, "no slot for gate factors"};
+            release_entry(c, (size_t)k);
         }
-        if (c->gslots.size() < 2) throw Fail{MPDO_E_NOMEM, "no slot for gate factors"};
         gf.X = c->gslots.back();
         c->gslots.pop_back();
         gf.Y = c->gslots.back();
@@ -1035,46 +1087,89 @@ GateFactor factorize(mpdo_ctx c, const std::vector<zc>& S) {
                                      V<double>(gf.X, m2, 1))));
         HIPCHK((geam<double, double>(c->st, r, m2, C1(), V<double>(g.bK, m2, 1), C0(), V<double>(gf.Y, m2, 1))));
     }
-    c->gcache[h] = gf;
-    c->gorder.push_back(h);
     return gf;
 }
 
-template <typename T>
-void do_update(mpdo_ctx c, int i, const std::vector<zc>& S_in, int chi, mpdo_trunc_info* info) {
+// S <- S (P_i (x) P_{i+1}) for the single-atom maps queued on atoms i and i+1
+void fold_pending(mpdo_ctx c, int i, std::vector<zc>& S) {
     const int D2 = c->D2, m2 = D2 * D2;
-    // fold queued single-atom maps: S' = S (P_i (x) P_{i+1})
-    std::vector<zc> S = S_in;
-    if (!c->pend_id[i] || !c->pend_id[i + 1]) {
-        std::vector<zc> P((size_t)m2 * m2, zc(0, 0));
-        for (int a = 0; a < D2; ++a)
-            for (int b = 0; b < D2; ++b)
-                for (int cc = 0; cc < D2; ++cc)
-                    for (int e = 0; e < D2; ++e) {
-                        const zc pa = c->pend_id[i] ? zc(a == cc ? 1 : 0, 0) : c->pending[i][(size_t)a * D2 + cc];
-                        const zc pb =
-                            c->pend_id[i + 1] ? zc(b == e ? 1 : 0, 0) : c->pending[i + 1][(size_t)b * D2 + e];
-                        P[(size_t)(a * D2 + b) * m2 + (cc * D2 + e)] = pa * pb;
-                    }
-        std::vector<zc> out((size_t)m2 * m2, zc(0, 0));
-        for (int r = 0; r < m2; ++r)
-            for (int k = 0; k < m2; ++k) {
-                const zc sv = S[(size_t)r * m2 + k];
-                if (sv == zc(0, 0)) continue;
-                for (int col = 0; col < m2; ++col) out[(size_t)r * m2 + col] += sv * P[(size_t)k * m2 + col];
-            }
-        S.swap(out);
+    std::vector<zc> P((size_t)m2 * m2, zc(0, 0));
+    for (int a = 0; a < D2; ++a)
+        for (int b = 0; b < D2; ++b)
+            for (int cc = 0; cc < D2; ++cc)
+                for (int e = 0; e < D2; ++e) {
+                    const zc pa = c->pend_id[i] ? zc(a == cc ? 1 : 0, 0) : c->pending[i][(size_t)a * D2 + cc];
+                    const zc pb = c->pend_id[i + 1] ? zc(b == e ? 1 : 0, 0) : c->pending[i + 1][(size_t)b * D2 + e];
+                    P[(size_t)(a * D2 + b) * m2 + (cc * D2 + e)] = pa * pb;
+                }
+    std::vector<zc> out((size_t)m2 * m2, zc(0, 0));
+    for (int r = 0; r < m2; ++r)
+        for (int k = 0; k < m2; ++k) {
+            const zc sv = S[(size_t)r * m2 + k];
+            if (sv == zc(0, 0)) continue;
+            for (int col = 0; col < m2; ++col) out[(size_t)r * m2 + col] += sv * P[(size_t)k * m2 + col];
+        }
+    S.swap(out);
+}
+
+// The folded map of an update on atoms (i, i+1): from the cache when the same input meets the
+// same queued maps again, otherwise built (from the Kraus set if kind == 1), folded, factorised
+// and cached.  Returns the entry's index in the cache.
+size_t folded_map(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n_kraus) {
+    const int D2 = c->D2;
+    const size_t pbytes = (size_t)D2 * D2 * sizeof(zc);
+    const bool ida = c->pend_id[i] != 0, idb = c->pend_id[i + 1] != 0;
+    uint64_t h = hash_bytes(in, n_in * sizeof(double), 0x51ull + (uint64_t)kind);
+    h = hash_bytes(ida ? nullptr : c->pending[i].data(), ida ? 0 : pbytes, h ^ 0xA1ull);
+    h = hash_bytes(idb ? nullptr : c->pending[i + 1].data(), idb ? 0 : pbytes, h ^ 0xB2ull);
+    for (size_t k = 0; k < c->fcache.size(); ++k) {
+        FoldEntry& e = c->fcache[k];
+        if (e.h != h || e.kind != kind || e.in.size() != n_in || e.ida != ida || e.idb != idb) continue;
+        if (memcmp(e.in.data(), in, n_in * sizeof(double)) != 0) continue;
+        if (!ida && memcmp(e.pa.data(), c->pending[i].data(), pbytes) != 0) continue;
+        if (!idb && memcmp(e.pb.data(), c->pending[i + 1].data(), pbytes) != 0) continue;
+        e.used = ++c->fclock;
+        return k;
+    }
+    std::vector<zc> S;
+    if (kind == 1) {
+        S = superop_from_kraus_2(in, n_kraus, c->d);
+    } else {
+        S.resize(n_in / 2);
+        memcpy(S.data(), in, n_in * sizeof(double));
+    }
+    if (!ida || !idb) fold_pending(c, i, S);
+    while ((int)c->fcache.size() >= FOLD_CACHE_MAX) release_entry(c, (size_t)lru_entry(c, false));
+    FoldEntry e;
+    e.gf = factorize(c, S);   // may release entries to free factor slots
+    e.id = c->fnext++;
+    e.h = h;
+    e.used = ++c->fclock;
+    e.kind = kind;
+    e.in.assign(in, in + n_in);
+    e.ida = ida;
+    e.idb = idb;
+    if (!ida) e.pa = c->pending[i];
+    if (!idb) e.pb = c->pending[i + 1];
+    e.S.swap(S);
+    c->fcache.push_back(std::move(e));
+    return c->fcache.size() - 1;
+}
+
+template <typename T>
+void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n_kraus, int chi,
+               mpdo_trunc_info* info) {
+    const FoldEntry& e = c->fcache[folded_map(c, i, kind, in, n_in, n_kraus)];
+    const GateFactor gf = e.gf;
+    if (!c->pend_id[i] || !c->pend_id[i + 1]) {   // the queued maps are now part of the update
         c->pend_id[i] = c->pend_id[i + 1] = 1;
         set_ovec(c, i);
         set_ovec(c, i + 1);
         c->lvalid = std::min(c->lvalid, i);
         c->rvalid = std::max(c->rvalid, i + 2);
     }
-    GateFactor gf = factorize(c, S);
-    upload(c, c->Sdev, S.data(), S.size() * sizeof(zc));
-    if (c->fp32)
-        HIPCHK((geam<double, float>(c->st, m2, m2, C1(), V<double>(c->Sdev, m2, 1), C0(),
-                                    V<float>((float*)c->SdevT, m2, 1))));
+    c->Scur = &e.S;   // loaded to the device only if the update takes the explicit path
+    c->Scur_id = e.id;
     if (c->fp32) {
         Engine<float> E(*c, c->sf);
         E.update(i, gf.X ? &gf : nullptr, chi, info);
@@ -1378,12 +1473,13 @@ mpdo_status mpdo_init_product_state(mpdo_ctx c, const double* rho_sites) {
     return MPDO_OK;
 }
 
-static mpdo_status gate_common(mpdo_ctx c, int site, const std::vector<zc>& S, int chi, mpdo_trunc_info* info) {
+static mpdo_status gate_common(mpdo_ctx c, int site, int kind, const double* in, size_t n_in, int n_kraus, int chi,
+                               mpdo_trunc_info* info) {
     try {
         if (c->fp32)
-            do_update<float>(c, site, S, chi, info);
+            do_update<float>(c, site, kind, in, n_in, n_kraus, chi, info);
         else
-            do_update<double>(c, site, S, chi, info);
+            do_update<double>(c, site, kind, in, n_in, n_kraus, chi, info);
     } catch (const Fail& f) {
         set_err(c, f);
         return f.st;
@@ -1407,9 +1503,7 @@ mpdo_status mpdo_apply_gate(mpdo_ctx c, int site, const double* superop, mpdo_tr
         c->err = "non-finite superoperator entry";
         return MPDO_E_ARG;
     }
-    std::vector<zc> S((size_t)m2 * m2);
-    memcpy(S.data(), superop, S.size() * sizeof(zc));
-    return gate_common(c, site, S, c->chi, info);
+    return gate_common(c, site, 0, superop, (size_t)m2 * m2 * 2, 0, c->chi, info);
 }
 
 mpdo_status mpdo_apply_gate_kraus(mpdo_ctx c, int site, int n_kraus, const double* kraus, mpdo_trunc_info* info) {
@@ -1432,7 +1526,7 @@ mpdo_status mpdo_apply_gate_kraus(mpdo_ctx c, int site, int n_kraus, const doubl
         c->err = "Kraus set is not trace preserving";
         return MPDO_E_ARG;
     }
-    return gate_common(c, site, superop_from_kraus_2(kraus, n_kraus, c->d), c->chi, info);
+    return gate_common(c, site, 1, kraus, (size_t)n_kraus * dim * dim * 2, n_kraus, c->chi, info);
 }
 
 mpdo_status mpdo_apply_channel(mpdo_ctx c, int site, int n_kraus, const double* kraus) {
@@ -1490,9 +1584,9 @@ mpdo_status mpdo_truncate(mpdo_ctx c, int bond, int chi, mpdo_trunc_info* info) 
         return MPDO_E_ARG;
     }
     const int m2 = c->D2 * c->D2;
-    std::vector<zc> S((size_t)m2 * m2, zc(0, 0));
-    for (int a = 0; a < m2; ++a) S[(size_t)a * m2 + a] = zc(1, 0);
-    return gate_common(c, bond, S, chi, info);
+    std::vector<double> S((size_t)m2 * m2 * 2, 0.0);
+    for (int a = 0; a < m2; ++a) S[((size_t)a * m2 + a) * 2] = 1.0;
+    return gate_common(c, bond, 0, S.data(), S.size(), 0, chi, info);
 }
 
 mpdo_status mpdo_expect(mpdo_ctx c, int n_terms, const int* first_site, const int* n_sites_in_term, const double* ops,
