@@ -38,8 +38,9 @@
  *                               to stderr
  *   MPDO_SUBSPACE_MIN_ORDER=n   use the subspace iteration above order n (< 1024) instead of
  *                               1024, for testing it where the exact split also runs
- *   MPDO_GEMM_AUTOTUNE=1        time the k split of each GEMM shape bucket on first use and
- *                               keep the fastest (default: a fixed heuristic)
+ *   MPDO_GEMM_AUTOTUNE=1        time the launch plan (tile size and k split) of each GEMM
+ *                               shape bucket on first use and keep the fastest (default: a
+ *                               cost model of matrix-core time per compute unit)
  */
 #ifndef MPDO_H
 #define MPDO_H

@@ -14,6 +14,6 @@ template <typename T>
 hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
                  CView<T> C, int batch = 1, long sA = 0, long sB = 0, long sC = 0, ProfSink* prof = nullptr);
 
-// Number of shape buckets the k-split autotuner has settled (MPDO_GEMM_AUTOTUNE=1).
+// Number of shape buckets the launch-plan autotuner has settled (MPDO_GEMM_AUTOTUNE=1).
 int gemm_tuned_buckets();
 }  // namespace mpdo

@@ -8,14 +8,21 @@
 //
 // Complex products use four real MFMA products per k-step (re*re - im*im, re*im + im*re);
 // counted as 8 real flop per complex multiply-add, the same as the algorithm.
-// Block tile 64 x 64, k-step 32, 256 threads = 4 waves of 64 lanes, each wave owns a
-// 32 x 32 quadrant = 2 x 2 MFMA 16x16 tiles.  Tiles of A and B are staged through LDS as
+// Block tile 64 x 64 or 32 x 32, k-step 32, 256 threads = 4 waves of 64 lanes; each wave owns
+// a quadrant of 2 x 2 or 1 x 1 MFMA 16x16 tiles.  Tiles of A and B are staged through LDS as
 // separate real and imaginary planes; the global loader walks the contiguous dimension of
 // each view so loads coalesce whichever way the view is laid out.  Large-k products with a
 // small output (Gram matrices of tall factors) split k over blockIdx.z and accumulate with
 // FP64/FP32 atomics into a zeroed output.
+//
+// One FP64 16x16x4 MFMA occupies a SIMD for 64 cycles (78.6 TFLOP/s over 1024 SIMDs), so a
+// workgroup needs 64 WM^2 cycles per unit of k on its compute unit: the small products of an
+// update (outputs of a few 64 x 64 tiles) are bound by how many compute units they reach.
+// The launcher picks the tile size and the k split from that cost (plan_of).
 #include <stdlib.h>
 
+#include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <type_traits>
 #include <unordered_map>
@@ -27,8 +34,6 @@ namespace mpdo {
 
 namespace {
 
-constexpr int BM = 64;
-constexpr int BN = 64;
 constexpr int BK = 32;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -76,8 +81,10 @@ __device__ __forceinline__ void load_cplx(const T* p, long off, int conj, T& re,
     if (conj) im = -im;
 }
 
-template <typename T>
+// WM: MFMA tiles per wave along each output dimension; block tile (32 WM) x (32 WM)
+template <typename T, int WM>
 __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
+    constexpr int BM = 32 * WM, BN = 32 * WM, WQ = 16 * WM;
     __shared__ T sAr[BM][BK + 1];
     __shared__ T sAi[BM][BK + 1];
     __shared__ T sBr[BK][BN + 1];
@@ -100,11 +107,11 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
     const T* Bp = g.B.p + 2 * (long)b * g.sB;
     T* Cp = g.C.p + 2 * (long)b * g.sC;
 
-    typename Acc<T>::v cr[2][2], ci[2][2];
+    typename Acc<T>::v cr[WM][WM], ci[WM][WM];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < WM; ++j) {
             cr[i][j] = (typename Acc<T>::v){0, 0, 0, 0};
             ci[i][j] = (typename Acc<T>::v){0, 0, 0, 0};
         }
@@ -160,22 +167,22 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
         // leaves one wave per SIMD (308 registers); by two the FP64 kernel fits two waves
 #pragma unroll 2
         for (int kk = 0; kk < BK; kk += 4) {
-            T ar[2], ai[2], nai[2], br[2], bi[2];
+            T ar[WM], ai[WM], nai[WM], br[WM], bi[WM];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                ar[i] = sAr[wr * 32 + i * 16 + li][kk + lk];
-                ai[i] = sAi[wr * 32 + i * 16 + li][kk + lk];
+            for (int i = 0; i < WM; ++i) {
+                ar[i] = sAr[wr * WQ + i * 16 + li][kk + lk];
+                ai[i] = sAi[wr * WQ + i * 16 + li][kk + lk];
                 nai[i] = -ai[i];
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                br[j] = sBr[kk + lk][wc * 32 + j * 16 + li];
-                bi[j] = sBi[kk + lk][wc * 32 + j * 16 + li];
+            for (int j = 0; j < WM; ++j) {
+                br[j] = sBr[kk + lk][wc * WQ + j * 16 + li];
+                bi[j] = sBi[kk + lk][wc * WQ + j * 16 + li];
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < WM; ++j) {
                     cr[i][j] = mfma16(ar[i], br[j], cr[i][j]);
                     cr[i][j] = mfma16(nai[i], bi[j], cr[i][j]);
                     ci[i][j] = mfma16(ar[i], bi[j], ci[i][j]);
@@ -187,13 +194,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
 
     // ---- epilogue: lane holds column lane%16 and rows acc_row(lane/16, r) of each tile
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WM; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wr * 32 + i * 16 + acc_row(T(0), lk, r);
-                const int gn = n0 + wc * 32 + j * 16 + li;
+                const int gm = m0 + wr * WQ + i * 16 + acc_row(T(0), lk, r);
+                const int gn = n0 + wc * WQ + j * 16 + li;
                 if (gm >= g.M || gn >= g.N) continue;
                 const double xr = (double)cr[i][j][r], xi = (double)ci[i][j][r];
                 const double vr = g.ar * xr - g.ai * xi;
@@ -236,23 +243,59 @@ __global__ void cscale_kernel(CView<T> C, int M, int N, double br, double bi) {
     C.p[off + 1] = (T)(C.conj ? -vi : vi);
 }
 
-// Split of the k range over workgroups for an output of `tiles` 64 x 64 tiles: the output alone
-// cannot fill the 256 compute units below 192 tiles, and one 64 x 64 x 32 complex k-step keeps
-// a CU's FP64 matrix cores busy for ~3.4 us, so small outputs are spread over the chip in
-// k-chunks of at least 64.
-int heuristic_ksplit(int tiles, int K) {
-    if (tiles >= 192 || K < 128) return 1;
-    int ks = (768 + tiles - 1) / tiles;
-    const int maxks = K / 64;
-    if (ks > maxks) ks = maxks;
-    if (ks > 64) ks = 64;
-    return ks < 1 ? 1 : ks;
+// Launch plan: block tile (32 wm)^2 with wm = 2 or 1, and the k range split ks ways.
+struct Plan {
+    int wm, ks;
+};
+
+int tiles_of(int M, int N, int batch, int wm) {
+    const int bt = 32 * wm;
+    return ((M + bt - 1) / bt) * ((N + bt - 1) / bt) * batch;
 }
 
-// One product with the k range split `ks` ways (ks = 1: no split).
+// k extent of one chunk when the k range is split about ks ways (a multiple of BK)
+int chunk_of(int K, int ks) { return (((K + ks - 1) / ks + BK - 1) / BK) * BK; }
+
+// Estimated time (us) of a plan.  Matrix-core time: a workgroup spends 64 wm^2 cycles (FP64;
+// 32 for FP32) per unit of k on its compute unit, and the workgroups run in rounds of 256, one
+// per compute unit (a unit that holds two shares its matrix cores between them).  Operand
+// traffic: every workgroup reads a (32 wm) x chunk tile of A and of B, at ~16 TB/s from L2
+// and the memory-side cache, counted at a quarter weight (it mostly overlaps the matrix work;
+// it decides between plans of equal matrix time).  A split adds its atomic updates of the
+// output (~2 TB/s), the pre-scaling launch and ~5 us of fixed cost; every launch ~2 us.
+double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p) {
+    const double tsz = fp64 ? 8.0 : 4.0;
+    const double W = (double)tiles_of(M, N, batch, p.wm) * p.ks;
+    const int chunk = p.ks > 1 ? chunk_of(K, p.ks) : K;
+    const double cyc = (fp64 ? 64.0 : 32.0) * p.wm * p.wm * chunk;
+    const double mfma_us = std::ceil(W / 256.0) * cyc / 2400.0;
+    const double bytes = W * chunk * 64.0 * p.wm * 2.0 * tsz;
+    const double atomic_us = p.ks > 1 ? W * 1024.0 * p.wm * p.wm * 2.0 * tsz / 2e6 : 0.0;
+    return mfma_us + 0.25 * bytes / 16e6 + atomic_us + 2.0 + (p.ks > 1 ? 5.0 : 0.0);
+}
+
+Plan plan_of(int M, int N, int K, int batch, bool fp64) {
+    Plan best{2, 1};
+    double best_t = plan_cost(M, N, K, batch, fp64, best);
+    for (int wm = 2; wm >= 1; --wm)
+        for (int ks = 1; ks <= 64; ks *= 2) {
+            if (ks > 1 && K < 2 * BK) break;
+            const int k_eff = ks > 1 ? (K + chunk_of(K, ks) - 1) / chunk_of(K, ks) : 1;
+            if (ks > 1 && k_eff < 2) continue;
+            const Plan p{wm, k_eff};
+            const double t = plan_cost(M, N, K, batch, fp64, p);
+            if (t < 0.97 * best_t) {
+                best = p;
+                best_t = t;
+            }
+        }
+    return best;
+}
+
+// One product with the plan's tile size and k split (ks = 1: no split).
 template <typename T>
 hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
-                        int batch, long sA, long sB, long sC, int ks, ProfSink* prof) {
+                        int batch, long sA, long sB, long sC, Plan plan, ProfSink* prof) {
     GemmArgs<T> g;
     g.M = M;
     g.N = N;
@@ -272,8 +315,9 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
     g.ksplit = 1;
     g.kchunk = ((g.K + BK - 1) / BK) * BK;
     if (g.kchunk == 0) g.kchunk = BK;
+    int ks = plan.ks;
     if (ks >= 2) {
-        const int chunk = (((g.K + ks - 1) / ks + BK - 1) / BK) * BK;
+        const int chunk = chunk_of(g.K, ks);
         ks = (g.K + chunk - 1) / chunk;
         if (ks >= 2) {
             // C <- beta*C first, then accumulate alpha*AB atomically
@@ -291,9 +335,13 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
             g.atomic = 1;
         }
     }
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * g.ksplit);
+    const int bt = 32 * plan.wm;
+    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, batch * g.ksplit);
     if (prof) prof->begin(s, PF_GEMM);
-    hipLaunchKernelGGL(cgemm_kernel<T>, grid, dim3(256), 0, s, g);
+    if (plan.wm == 2)
+        hipLaunchKernelGGL((cgemm_kernel<T, 2>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((cgemm_kernel<T, 1>), grid, dim3(256), 0, s, g);
     if (prof) {
         // algorithmic: 8 flop per complex multiply-add; A, B read and C written once (and read
         // when beta != 0)
@@ -305,13 +353,13 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- autotuner of the k split
+// ---------------------------------------------------------------- autotuner of the plan
 // Shapes are bucketed by the powers of two of M, N, K, the batch and the precision.  With
 // tuning on (environment MPDO_GEMM_AUTOTUNE=1), the first product of a bucket with beta = 0
-// (the output then does not depend on its old contents) is run with each candidate split on
+// (the output then does not depend on its old contents) is run with each candidate plan on
 // its stream between HIP events, the fastest is cached for the bucket, and the product is run
-// once more with it; later products of the bucket use the cached split.  With tuning off, or
-// with beta != 0, the heuristic above decides.  The cache is shared by all threads.
+// once more with it; later products of the bucket use the cached plan.  With tuning off, or
+// with beta != 0, the cost model above decides.  The cache is shared by all threads.
 struct TuneKey {
     int m, n, k, batch, fp64;
     bool operator==(const TuneKey& o) const {
@@ -324,7 +372,7 @@ struct TuneHash {
     }
 };
 std::mutex g_tune_mutex;
-std::unordered_map<TuneKey, int, TuneHash> g_tune;
+std::unordered_map<TuneKey, Plan, TuneHash> g_tune;
 
 int log2_bucket(long x) {
     int b = 0;
@@ -338,25 +386,25 @@ bool autotune_on() {
 }
 
 template <typename T>
-int tune_ksplit(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
-                int batch, long sA, long sB, long sC, int tiles) {
-    const TuneKey key{log2_bucket(M), log2_bucket(N), log2_bucket(K), log2_bucket(batch),
-                      std::is_same<T, double>::value ? 1 : 0};
+Plan tune_plan(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
+               int batch, long sA, long sB, long sC) {
+    const bool fp64 = std::is_same<T, double>::value;
+    const TuneKey key{log2_bucket(M), log2_bucket(N), log2_bucket(K), log2_bucket(batch), fp64 ? 1 : 0};
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) return it->second;
     }
-    const int h = heuristic_ksplit(tiles, K);
-    int cands[8], nc = 0;
-    cands[nc++] = 1;
-    for (int ks = 2; ks <= 64 && ks <= K / 64; ks *= 2) cands[nc++] = ks;
-    if (h > 1) {
-        bool have = false;
-        for (int i = 0; i < nc; ++i) have = have || cands[i] == h;
-        if (!have && nc < 8) cands[nc++] = h;
-    }
-    int best = h;
+    const Plan h = plan_of(M, N, K, batch, fp64);
+    Plan cands[16];
+    int nc = 0;
+    cands[nc++] = h;
+    for (int wm = 2; wm >= 1; --wm)
+        for (int ks = 1; ks <= 64 && nc < 16; ks *= 2) {
+            if (ks > 1 && ks > K / 64) break;
+            if (!(wm == h.wm && ks == h.ks)) cands[nc++] = Plan{wm, ks};
+        }
+    Plan best = h;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return h;
@@ -391,11 +439,11 @@ template <typename T>
 hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
                  CView<T> C, int batch, long sA, long sB, long sC, ProfSink* prof) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
-    int ks = heuristic_ksplit(tiles, K < 0 ? 0 : K);
+    const int k = K < 0 ? 0 : K;
+    Plan plan = plan_of(M, N, k, batch, std::is_same<T, double>::value);
     if (autotune_on() && beta.re == 0.0 && beta.im == 0.0 && K >= 128)
-        ks = tune_ksplit<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, tiles);
-    return cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, ks, prof);
+        plan = tune_plan<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC);
+    return cgemm_launch<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, plan, prof);
 }
 
 int gemm_tuned_buckets() {
