@@ -109,7 +109,7 @@ struct Arena {
 template <typename T>
 struct Scratch {
     int nmax = 0;        // largest matrix side handled
-    T *bA, *bB, *bT1, *bQ, *bK, *bC, *bR, *bU, *bB2, *bG, *bZ, *bW, *bVT, *bQ2, *bK2, *bU2;
+    T *bA, *bB, *bT1, *bQ, *bK, *bC, *bR, *bU, *bB2, *bG, *bW, *bVT, *bQ2, *bK2, *bU2;
     double *Gd, *Vd, *evals, *sig, *inv, *st, *sums, *lvec, *rvec, *tl, *tr, *fac, *pout, *sc, *vtmp, *vtmp2;
     double* odev;   // ||Q||_F^2 and non-finite count of recent orthonormal bases (64 pairs)
     int* cnt;
@@ -118,7 +118,7 @@ struct Scratch {
     static size_t bytes(int nmax) {
         const size_t n2 = (size_t)nmax * nmax * 2;
         size_t b = 0;
-        b += 16 * (n2 * sizeof(T) + 256);
+        b += 15 * (n2 * sizeof(T) + 256);
         b += 2 * (n2 * sizeof(double) + 256);
         b += 14 * ((size_t)nmax * 2 * sizeof(double) + 256) + 4096 + 2048;
         b += eigh_work_bytes(nmax) + 256;
@@ -137,7 +137,6 @@ struct Scratch {
         bU = a.take<T>(n2);
         bB2 = a.take<T>(n2);
         bG = a.take<T>(n2);
-        bZ = a.take<T>(n2);
         bW = a.take<T>(n2);
         bQ2 = a.take<T>(n2);
         bK2 = a.take<T>(n2);
@@ -459,14 +458,21 @@ struct Engine {
         }
     }
 
-    // Newton-Schulz: make the n x q columns of Q (view, dense storage in buffer with ld) orthonormal
+    // Newton-Schulz: make the n x q columns of Q (view, dense storage in buffer with ld) orthonormal,
+    // X <- X (3/2 I - 1/2 X^H X), alternating between Q and the scratch bW (ld q)
     void ns_orth(T* Q, long ldq, int n, int q, int iters) {
+        T* cur = Q;
+        long ldc = ldq;
         for (int it = 0; it < iters; ++it) {
-            gemm(q, q, n, C1(), adj(V<T>(Q, ldq, 1)), V<T>(Q, ldq, 1), C0(), V<T>(s.bG, q, 1));
-            HIPCHK(ns_prep<T>(st, s.bG, q, s.bZ));
-            gemm(n, q, q, C1(), V<T>(Q, ldq, 1), V<T>(s.bZ, q, 1), C0(), V<T>(s.bW, q, 1));
-            HIPCHK((geam<T, T>(st, n, q, C1(), V<T>(s.bW, q, 1), C0(), V<T>(Q, ldq, 1))));
+            gemm(q, q, n, C1(), adj(V<T>(cur, ldc, 1)), V<T>(cur, ldc, 1), C0(), V<T>(s.bG, q, 1));
+            T* nxt = cur == Q ? s.bW : Q;
+            const long ldn = cur == Q ? (long)q : ldq;
+            HIPCHK(cgemm_shift_b<T>(st, n, q, q, C1(), V<T>(cur, ldc, 1), V<T>(s.bG, q, 1), -0.5, 1.5,
+                                    V<T>(nxt, ldn, 1), ps()));
+            cur = nxt;
+            ldc = ldn;
         }
+        if (cur != Q) HIPCHK((geam<T, T>(st, n, q, C1(), V<T>(cur, ldc, 1), C0(), V<T>(Q, ldq, 1))));
     }
 
     // Orthonormal basis of range(F) for the n x cc view F, up to three Gram levels: level 0
@@ -502,9 +508,14 @@ struct Engine {
             gemm(acc, cc, n, C1(), adj(V<T>(Qn, cc, 1)), F, C0(), V<T>(Kb + 2 * (long)q * cc, cc, 1));
             q += acc;
             if (q >= qmax || lev == 2) break;
-            // residual F - Q K; stop once nothing above the cutoff is left
+            // residual F - Q K, projected out of range(Q) a second time (its rounding inside
+            // range(Q), ~eps sqrt(q) ||F||, would otherwise return as deep-level directions that
+            // the projection of the new columns leaves short and nearly dependent); stop once
+            // nothing above the cutoff is left
             HIPCHK((geam<T, T>(st, n, cc, C1(), F, C0(), V<T>(s.bT1, cc, 1))));
             gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(Kb, cc, 1), C1(), V<T>(s.bT1, cc, 1));
+            gemm(q, cc, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(s.bT1, cc, 1), C0(), V<T>(s.bW, cc, 1));
+            gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bW, cc, 1), C1(), V<T>(s.bT1, cc, 1));
             HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums));
             double sums[2], st5[5];
             read_doubles2(s.sums, 2, sums, s.st, 5, st5);
@@ -622,9 +633,11 @@ struct Engine {
             orth_check("split", Vn, ldu, a, acc, lev, a);
             kacc += acc;
             if (kacc >= chi || kacc >= a || lev == 2) break;
-            // residual R = F - U (U^H F)
+            // residual R = F - U (U^H F), projected twice (as in orth2); Bb is rebuilt at the end
             gemm(kacc, b, a, C1(), adj(V<T>(Ub, ldu, 1)), F, C0(), V<T>(Bb, b, 1));
             HIPCHK((geam<T, T>(st, a, b, C1(), F, C0(), V<T>(s.bR, b, 1))));
+            gemm(a, b, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(Bb, b, 1), C1(), V<T>(s.bR, b, 1));
+            gemm(kacc, b, a, C1(), adj(V<T>(Ub, ldu, 1)), V<T>(s.bR, b, 1), C0(), V<T>(Bb, b, 1));
             gemm(a, b, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(Bb, b, 1), C1(), V<T>(s.bR, b, 1));
             HIPCHK(sumsq<T>(st, V<T>(s.bR, b, 1), a, b, s.sums));
             double sums[2], st5[5];

@@ -72,6 +72,8 @@ struct GemmArgs {
     long sA, sB, sC;   // batch strides in complex elements
     double ar, ai, br, bi;
     int atomic;        // 1: accumulate alpha*AB into C with atomics (beta ignored)
+    int bshift;        // 1: op(B) is replaced by bsc op(B) + bdg I as it is loaded
+    double bsc, bdg;
 };
 
 template <typename T>
@@ -141,7 +143,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
             const int gn = n0 + n, gk = k0 + k;
             pbr[j] = 0;
             pbi[j] = 0;
-            if (gn < g.N && gk < kend) load_cplx(Bp, (long)gk * g.B.rs + (long)gn * g.B.cs, g.B.conj, pbr[j], pbi[j]);
+            if (gn < g.N && gk < kend) {
+                load_cplx(Bp, (long)gk * g.B.rs + (long)gn * g.B.cs, g.B.conj, pbr[j], pbi[j]);
+                if (g.bshift) {
+                    pbr[j] = (T)((gk == gn ? g.bdg : 0.0) + g.bsc * (double)pbr[j]);
+                    pbi[j] = (T)(g.bsc * (double)pbi[j]);
+                }
+            }
         }
     };
     if (kbeg < kend) fetch(kbeg);
@@ -295,7 +303,8 @@ Plan plan_of(int M, int N, int K, int batch, bool fp64) {
 // One product with the plan's tile size and k split (ks = 1: no split).
 template <typename T>
 hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
-                        int batch, long sA, long sB, long sC, Plan plan, ProfSink* prof) {
+                        int batch, long sA, long sB, long sC, Plan plan, ProfSink* prof, double bsc = 1.0,
+                        double bdg = 0.0) {
     GemmArgs<T> g;
     g.M = M;
     g.N = N;
@@ -312,6 +321,9 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
     g.br = beta.re;
     g.bi = beta.im;
     g.atomic = 0;
+    g.bshift = (bsc != 1.0 || bdg != 0.0) ? 1 : 0;
+    g.bsc = bsc;
+    g.bdg = bdg;
     g.ksplit = 1;
     g.kchunk = ((g.K + BK - 1) / BK) * BK;
     if (g.kchunk == 0) g.kchunk = BK;
@@ -446,6 +458,15 @@ hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView
     return cgemm_launch<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, plan, prof);
 }
 
+template <typename T>
+hipError_t cgemm_shift_b(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, double b_scale,
+                         double b_diag, CView<T> C, ProfSink* prof) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int k = K < 0 ? 0 : K;
+    const Plan plan = plan_of(M, N, k, 1, std::is_same<T, double>::value);
+    return cgemm_launch<T>(s, M, N, k, alpha, A, B, cd{0.0, 0.0}, C, 1, 0, 0, 0, plan, prof, b_scale, b_diag);
+}
+
 int gemm_tuned_buckets() {
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     return (int)g_tune.size();
@@ -455,5 +476,9 @@ template hipError_t cgemm<double>(hipStream_t, int, int, int, cd, CView<double>,
                                   CView<double>, int, long, long, long, ProfSink*);
 template hipError_t cgemm<float>(hipStream_t, int, int, int, cd, CView<float>, CView<float>, cd,
                                  CView<float>, int, long, long, long, ProfSink*);
+template hipError_t cgemm_shift_b<double>(hipStream_t, int, int, int, cd, CView<double>, CView<double>, double,
+                                          double, CView<double>, ProfSink*);
+template hipError_t cgemm_shift_b<float>(hipStream_t, int, int, int, cd, CView<float>, CView<float>, double, double,
+                                         CView<float>, ProfSink*);
 
 }  // namespace mpdo

@@ -55,10 +55,6 @@ hipError_t scale_cols(hipStream_t s, CView<T> X, int M, int N, const double* f);
 template <typename T>
 hipError_t fill_random(hipStream_t s, CView<T> X, int M, int N, uint64_t seed);
 
-// Z = 1.5 I - 0.5 G  (q x q, dense row-major): one Newton-Schulz step for orthonormal columns.
-template <typename T>
-hipError_t ns_prep(hipStream_t s, const T* G, int q, T* Z);
-
 // Purity-Preserving Truncation on the kept spectrum (fac[j] = Lambda~_j / Lambda'_j).
 // out: [0] tr before, [1] xi before, [2] theta, [3] feasible, [4] degenerate sigma, [5] x,
 //      [6] max |Im T'L'|, [7] |Lambda'|^2, [8] T'.Lambda', [9] sum Im, [10] tr after,

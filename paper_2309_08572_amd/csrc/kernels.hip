@@ -299,15 +299,6 @@ __global__ void scale_cols_kernel(CView<T> X, int M, int N, const double* __rest
     X.p[off + 1] = (T)((double)X.p[off + 1] * f[n]);
 }
 
-template <typename T>
-__global__ void ns_prep_kernel(const T* __restrict__ G, int q, T* __restrict__ Z) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= q * q) return;
-    const int a = idx / q, b = idx % q;
-    Z[2 * idx] = (T)((a == b ? 1.5 : 0.0) - 0.5 * (double)G[2 * idx]);
-    Z[2 * idx + 1] = (T)(-0.5 * (double)G[2 * idx + 1]);
-}
-
 // PPT on the kept spectrum.  Inputs (device, FP64):
 //   sig[k]   kept Schmidt values Lambda'
 //   tl[k]    left trace factors  (l . U_j), complex
@@ -650,12 +641,6 @@ hipError_t scale_cols(hipStream_t s, CView<T> X, int M, int N, const double* f) 
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t ns_prep(hipStream_t s, const T* G, int q, T* Z) {
-    hipLaunchKernelGGL(ns_prep_kernel<T>, dim3(blocks_for((long)q * q)), dim3(256), 0, s, G, q, Z);
-    return hipGetLastError();
-}
-
 hipError_t ppt(hipStream_t s, const double* sig, const double* tl, const double* tr, const double* sc, int k,
                int use_ppt, int renorm, double* fac, double* out) {
     hipLaunchKernelGGL(ppt_kernel, dim3(1), dim3(256), 0, s, sig, tl, tr, sc, k, use_ppt, renorm, fac, out);
@@ -719,7 +704,6 @@ hipError_t bilinear(hipStream_t s, const T* L, int n, const double* y, double* o
     template hipError_t bilinear<T>(hipStream_t, const T*, int, const double*, double*);                         \
     template hipError_t scale_cols<T>(hipStream_t, CView<T>, int, int, const double*);                          \
     template hipError_t fill_random<T>(hipStream_t, CView<T>, int, int, uint64_t);                               \
-    template hipError_t ns_prep<T>(hipStream_t, const T*, int, T*);                                              \
     template hipError_t scale_rows<T>(hipStream_t, T*, int, int, long, const double*);                          \
     template hipError_t gemv_left<T>(hipStream_t, CView<T>, int, int, const double*, double*);                  \
     template hipError_t row_norms<T>(hipStream_t, CView<T>, int, int, double*);

@@ -26,17 +26,49 @@ namespace {
 
 constexpr int TB = 1024;      // threads of the one-workgroup kernels
 constexpr int NW = TB / 64;   // waves
-constexpr int BK_COLS = 4;    // columns per back-transform workgroup (LDS: (BK_COLS + 3) x 16 TRI_MAX bytes)
+constexpr int BK_COLS = 4;    // columns per back-transform workgroup (LDS: (BK_COLS + 1) x 16 TRI_MAX + 64 KB)
 constexpr int BK_THREADS = 256;
 constexpr int BK_LANES = BK_THREADS / BK_COLS;   // lanes per column (one wave)
 static_assert(BK_LANES == 64, "one wave per back-transform column");
 constexpr double EPS = 2.220446049250313e-16;
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+// x from another lane of the same row of 16 (DPP; every source lane is in the row, so with all
+// lanes active no lane keeps the placeholder 0)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Reductions over the 64 lanes of a wave (all lanes active), returned to every lane.  Inside
+// each row of 16 lanes: quad swaps (xor 1, xor 2), then the half-row mirror (lane i with 7 - i)
+// and the row mirror (i with 15 - i), register moves with no LDS round trip; then two
+// cross-row shuffles.  Each step combines the same two values in either order, so every lane
+// ends with the same bits.
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double x, Op op) {
+    x = op(x, dpp_mov<0xB1>(x));    // quad_perm [1,0,3,2]
+    x = op(x, dpp_mov<0x4E>(x));    // quad_perm [2,3,0,1]
+    x = op(x, dpp_mov<0x141>(x));   // row_half_mirror
+    x = op(x, dpp_mov<0x140>(x));   // row_mirror
+    x = op(x, __shfl_xor(x, 16, 64));
+    x = op(x, __shfl_xor(x, 32, 64));
     return x;
 }
+struct SumOp {
+    __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct MaxOp {
+    __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+struct MinOp {
+    __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+__device__ __forceinline__ double wave_sum(double x) { return wave_reduce(x, SumOp()); }
+__device__ __forceinline__ double wave_max(double x) { return wave_reduce(x, MaxOp()); }
+__device__ __forceinline__ double wave_min(double x) { return wave_reduce(x, MinOp()); }
 
 // sums of a and b over a workgroup of NWV waves, returned to every thread (red: 2 * NWV doubles)
 template <int NWV = NW>
@@ -61,11 +93,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 
 // max of a and min of b over the workgroup
 __device__ __forceinline__ void block_maxmin(double& a, double& b, double* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a = fmax(a, __shfl_xor(a, o, 64));
-        b = fmin(b, __shfl_xor(b, o, 64));
-    }
+    a = wave_max(a);
+    b = wave_min(b);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
         red[2 * w] = a;
@@ -332,13 +361,6 @@ __device__ __forceinline__ void block_sum2_once(double& a, double& b, double* re
 
 // sum over the 8 lanes of an aligned group, returned to all 8 (DPP: quad xor 1, quad xor 2,
 // then the mirror inside each half-row brings in the other quad; no LDS traffic)
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double x) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 __device__ __forceinline__ double group8_sum(double x) {
     x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
     x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
@@ -676,13 +698,8 @@ __device__ void wave_multisect(const double* d, const double* e2, int n, int idx
         const double x = lo + (double)(lane + 1) * h;
         const int c = sturm_count(d, e2, n, x, pivmin);
         double nlo = c <= idx ? x : lo, nhi = c <= idx ? hi : x;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
-            nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
-        }
-        lo = nlo;
-        hi = nhi;
+        lo = wave_max(nlo);
+        hi = wave_min(nhi);
     }
 }
 
@@ -718,13 +735,10 @@ __global__ __launch_bounds__(64) void tri_top_kernel(const double* __restrict__ 
         e2max = fmax(e2max, e2[i]);
         dmax = fmax(dmax, di);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
-        gmin = fmin(gmin, __shfl_xor(gmin, o, 64));
-        e2max = fmax(e2max, __shfl_xor(e2max, o, 64));
-        dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
-    }
+    gmax = wave_max(gmax);
+    gmin = wave_min(gmin);
+    e2max = wave_max(e2max);
+    dmax = wave_max(dmax);
     __syncthreads();
     const double tnorm = fmax(fabs(gmin), fabs(gmax));
     const double pivmin = DBL_MIN * fmax(1.0, e2max);
@@ -779,15 +793,17 @@ __global__ __launch_bounds__(64) void tri_eval_kernel(const double* __restrict__
     }
 }
 
-// Wave k < m: eigenvector k of T by three steps of inverse iteration (LU with partial pivoting
-// of T - lambda_k I fused with the forward solve, factors in the wave's LDS).  Z row k (length
-// n) receives the unit vector.
+// Wave k < m: eigenvector k of T by three steps of inverse iteration.  The first pass factors
+// T - lambda_k I (LU with partial pivoting between neighbouring rows) fused with its forward
+// solve and keeps the multipliers, the row swaps and the reciprocal pivots in the wave's LDS;
+// the later passes only substitute.  Z row k (length n) receives the unit vector.
 __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ dg, const double* __restrict__ off,
                                                      int n, const int* __restrict__ cnt,
                                                      const double* __restrict__ par,
                                                      const double* __restrict__ evals, double* __restrict__ Z) {
-    __shared__ double d[TRI_MAX], e[TRI_MAX], u0[TRI_MAX], u1[TRI_MAX], u2[TRI_MAX], yv[TRI_MAX], z[TRI_MAX];
-    __shared__ double ssum;
+    __shared__ double d[TRI_MAX], e[TRI_MAX], u0[TRI_MAX], u1[TRI_MAX], u2[TRI_MAX], yv[TRI_MAX], z[TRI_MAX],
+        fm[TRI_MAX];
+    __shared__ unsigned char sw[TRI_MAX];
     const int k = blockIdx.x, lane = threadIdx.x;
     if (k >= cnt[0]) return;
     for (int i = lane; i < n; i += 64) {
@@ -801,37 +817,56 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ 
     const double tiny = EPS * tnorm > 0.0 ? EPS * tnorm : DBL_MIN;
     for (int iter = 0; iter < 3; ++iter) {
         if (lane == 0) {
-            double p0 = d[0] - lk, p1 = n > 1 ? e[0] : 0.0, y = z[0];
-            for (int i = 0; i < n - 1; ++i) {
-                const double sub = e[i], nd = d[i + 1] - lk, ns = (i + 1 < n - 1) ? e[i + 1] : 0.0;
-                const double xn = z[i + 1];
-                if (fabs(p0) >= fabs(sub)) {
-                    if (p0 == 0.0) p0 = tiny;
-                    const double mlt = sub / p0;
-                    u0[i] = p0;
-                    u1[i] = p1;
-                    u2[i] = 0.0;
-                    yv[i] = y;
-                    p0 = nd - mlt * p1;
-                    p1 = ns;
-                    y = xn - mlt * y;
-                } else {
-                    const double mlt = p0 / sub;
-                    u0[i] = sub;
-                    u1[i] = nd;
-                    u2[i] = ns;
-                    yv[i] = xn;
-                    const double np0 = p1 - mlt * nd;
-                    p1 = -mlt * ns;
-                    p0 = np0;
-                    y = y - mlt * xn;
+            double y = z[0];
+            if (iter == 0) {
+                double p0 = d[0] - lk, p1 = n > 1 ? e[0] : 0.0;
+                for (int i = 0; i < n - 1; ++i) {
+                    const double sub = e[i], nd = d[i + 1] - lk, ns = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+                    const double xn = z[i + 1];
+                    if (fabs(p0) >= fabs(sub)) {
+                        if (p0 == 0.0) p0 = tiny;
+                        const double mlt = sub / p0;
+                        fm[i] = mlt;
+                        sw[i] = 0;
+                        u0[i] = 1.0 / p0;
+                        u1[i] = p1;
+                        u2[i] = 0.0;
+                        yv[i] = y;
+                        p0 = nd - mlt * p1;
+                        p1 = ns;
+                        y = xn - mlt * y;
+                    } else {
+                        const double mlt = p0 / sub;
+                        fm[i] = mlt;
+                        sw[i] = 1;
+                        u0[i] = 1.0 / sub;
+                        u1[i] = nd;
+                        u2[i] = ns;
+                        yv[i] = xn;
+                        const double np0 = p1 - mlt * nd;
+                        p1 = -mlt * ns;
+                        p0 = np0;
+                        y = y - mlt * xn;
+                    }
+                }
+                if (p0 == 0.0) p0 = tiny;
+                u0[n - 1] = 1.0 / p0;
+            } else {
+                for (int i = 0; i < n - 1; ++i) {
+                    const double xn = z[i + 1];
+                    if (sw[i] == 0) {
+                        yv[i] = y;
+                        y = xn - fm[i] * y;
+                    } else {
+                        yv[i] = xn;
+                        y = y - fm[i] * xn;
+                    }
                 }
             }
-            if (p0 == 0.0) p0 = tiny;
-            double z1 = y / p0, z2 = 0.0;
+            double z1 = y * u0[n - 1], z2 = 0.0;
             z[n - 1] = z1;
             for (int i = n - 2; i >= 0; --i) {
-                const double z0 = (yv[i] - u1[i] * z1 - u2[i] * z2) / u0[i];
+                const double z0 = (yv[i] - u1[i] * z1 - u2[i] * z2) * u0[i];
                 z[i] = z0;
                 z2 = z1;
                 z1 = z0;
@@ -892,16 +927,20 @@ __global__ __launch_bounds__(TB) void tri_mgs_kernel(int n, const int* __restric
 }
 
 // ------------------------------------------------------------------ back-transform
-// V[:, k] = H_0 ... H_{n-2} z_k for k < cnt[0]; workgroup b owns columns [BK_COLS b, BK_COLS (b+1)).  The
-// reflector of the next step is loaded into registers while the current one is applied.
+// V[:, k] = H_0 ... H_{n-2} z_k for k < cnt[0]; workgroup b owns columns [BK_COLS b, BK_COLS (b+1)),
+// one wave per column.  Reflectors are staged through LDS in chunks of R = BK_CH / (2 (n-1))
+// (slot stride 2 (n-1) doubles): the next chunk is loaded into registers while the current one
+// is applied, so the latency of a global load is paid once per chunk, and the waves apply a
+// chunk with no barrier between its reflectors (each touches only its own column).
+constexpr int BK_CH = 4096;   // doubles per chunk buffer
 __global__ __launch_bounds__(BK_THREADS) void tri_back_kernel(const double* __restrict__ refl,
                                                               const double* __restrict__ tau, int n,
                                                               const double* __restrict__ Z,
                                                               const int* __restrict__ cnt, double* __restrict__ V,
                                                               int ldv) {
-    constexpr int PF = (2 * TRI_MAX + BK_THREADS - 1) / BK_THREADS;   // doubles per thread per reflector
+    constexpr int PF = BK_CH / BK_THREADS;   // doubles per thread per chunk
     __shared__ double zb[BK_COLS][2 * TRI_MAX];
-    __shared__ double vb[2][2 * TRI_MAX];
+    __shared__ double vb[2][BK_CH];
     __shared__ double tl[2 * TRI_MAX];
     const int m = cnt[0];
     const int k0 = blockIdx.x * BK_COLS;
@@ -915,43 +954,40 @@ __global__ __launch_bounds__(BK_THREADS) void tri_back_kernel(const double* __re
         zb[c][2 * i + 1] = 0.0;
     }
     const int c = tid / BK_LANES, part = tid % BK_LANES;
-    // reflector j occupies refl[2 j n .. 2 j n + 2 (n-1-j))
+    const int S = 2 * (n - 1);
+    const int R = S > 0 ? BK_CH / S : 1;   // >= 2 since n <= TRI_MAX
+    // reflector j occupies refl[2 j n .. 2 j n + 2 (n-1-j)); chunk of jhi holds jhi, jhi-1, ...
     double pf[PF];
-    auto fetch = [&](int j) {
-        const int L2 = 2 * (n - 1 - j);
+    auto fetch = [&](int jhi) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int i = tid + q * BK_THREADS;
-            pf[q] = (j >= 0 && i < L2) ? refl[2L * j * n + i] : 0.0;
+            const int idx = tid + q * BK_THREADS;
+            const int r = S > 0 ? idx / S : 0, o = idx - r * S, j = jhi - r;
+            pf[q] = (S > 0 && r < R && j >= 0 && o < 2 * (n - 1 - j)) ? refl[2L * j * n + o] : 0.0;
         }
     };
     int buf = 0;
     fetch(n - 2);
-    for (int j = n - 2; j >= 0; --j) {
-        const int L = n - 1 - j;
+    for (int jhi = n - 2; jhi >= 0; jhi -= R) {
 #pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int i = tid + q * BK_THREADS;
-            if (i < 2 * L) vb[buf][i] = pf[q];
-        }
-        fetch(j - 1);
+        for (int q = 0; q < PF; ++q) vb[buf][tid + q * BK_THREADS] = pf[q];
+        fetch(jhi - R);
         __syncthreads();
-        const double tr = tl[2 * j], ti = tl[2 * j + 1];
-        if (tr != 0.0 || ti != 0.0) {
+        for (int r = 0; r < R && jhi - r >= 0; ++r) {
+            const int j = jhi - r, L = n - 1 - j;
+            const double tr = tl[2 * j], ti = tl[2 * j + 1];
+            if (tr == 0.0 && ti == 0.0) continue;
             // s = v^H z[j+1..]
             double sr = 0.0, si = 0.0;
             const double* zc = &zb[c][2 * (j + 1)];
-            const double* vv = vb[buf];
+            const double* vv = &vb[buf][r * S];
             for (int i = part; i < L; i += BK_LANES) {
                 const double vr = vv[2 * i], vi = vv[2 * i + 1], zr = zc[2 * i], zi = zc[2 * i + 1];
                 sr += vr * zr + vi * zi;
                 si += vr * zi - vi * zr;
             }
-#pragma unroll
-            for (int o = BK_LANES / 2; o > 0; o >>= 1) {
-                sr += __shfl_xor(sr, o, 64);
-                si += __shfl_xor(si, o, 64);
-            }
+            sr = wave_sum(sr);
+            si = wave_sum(si);
             // z -= tau s v
             const double fr = tr * sr - ti * si, fi = tr * si + ti * sr;
             double* zw = &zb[c][2 * (j + 1)];
