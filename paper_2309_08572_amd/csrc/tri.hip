@@ -332,31 +332,25 @@ struct RedLds {
     double ti[RS_LDS][RT][RB];
     double vabs[2 * RMAX];       // column j below the diagonal (absolute rows)
     double v[2 * RMAX];          // Householder vector (absolute rows, zero outside the block)
-    double pabs[2 * RMAX];
-    double red[2 * RNW];         // the two per-column reductions alternate between red and
-    double red2[2 * RNW];        // red2, so each needs only the barrier after its writes
+    double pabs[2 * RMAX];       // A22 v, accumulated by the tiles' atomics (cleared after use)
+    double wv[2 * RMAX];         // w of the rank-2 update
+    double red[2 * RNW];         // per-wave partials of v^H A22 v (written before the matvec barrier)
+    double red2[2 * RNW];        // per-wave partials of the next column's norm (before the update barrier)
 };
 
-// Workgroup sums of a and b with one barrier: `red` must not be written again before every
-// thread has passed another barrier (callers alternate two buffers).
-template <int NWV>
-__device__ __forceinline__ void block_sum2_once(double& a, double& b, double* red) {
+// Per-wave partial of a workgroup sum into red[w]; after the next barrier collect() returns the
+// sum to every thread.  red must not be written again before every thread has passed a later
+// barrier.
+__device__ __forceinline__ void publish(double a, double* red) {
     a = wave_sum(a);
-    b = wave_sum(b);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[2 * w] = a;
-        red[2 * w + 1] = b;
-    }
-    __syncthreads();
-    double sa = 0.0, sb = 0.0;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+}
+template <int NWV>
+__device__ __forceinline__ double collect(const double* red) {
+    double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < NWV; ++q) {
-        sa += red[2 * q];
-        sb += red[2 * q + 1];
-    }
-    a = sa;
-    b = sb;
+    for (int q = 0; q < NWV; ++q) s += red[q];
+    return s;
 }
 
 // sum over the 8 lanes of an aligned group, returned to all 8 (DPP: quad xor 1, quad xor 2,
@@ -393,20 +387,38 @@ __device__ __forceinline__ void tile_extract(const TileRow& x, int I, int J, int
     }
 }
 
-// Row sums of the tile row stay in the lane; the column contributions of an off-diagonal tile
-// (its mirror image above the diagonal) are summed over the 8 lanes of the group by DPP moves,
-// so that lane k adds column 8J + k: two atomics per lane per tile, none of them to the same
-// address within a group.
+// Householder vector entry c of column j: 1 at j + 1, (sr + i si) x_c below it (x = column j in
+// vabs), 0 above and past n
+__device__ __forceinline__ void hh_entry(const double* vabs, int c, int j, int n, double sr, double si,
+                                         double& vr, double& vi) {
+    vr = 0.0;
+    vi = 0.0;
+    if (c == j + 1) {
+        vr = 1.0;
+    } else if (c > j + 1 && c < n) {
+        const double xr = vabs[2 * c], xi = vabs[2 * c + 1];
+        vr = xr * sr - xi * si;
+        vi = xr * si + xi * sr;
+    }
+}
+
+// p += A22 v over one tile.  Row sums of the tile row stay in the lane; the column
+// contributions of an off-diagonal tile (its mirror image above the diagonal) are summed over
+// the 8 lanes of the group by DPP moves, so that lane k adds column 8J + k: two atomics per
+// lane per tile, none of them to the same address within a group.  This lane's share of
+// v^H A22 v (real: A22 is Hermitian) goes to vav: conj(v_r) times the row sum, and for an
+// off-diagonal tile conj(v_c) times the mirrored column sum the lane receives.
 template <class TileRow>
-__device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, const double* vabs, double* pabs) {
+__device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, const double* v, double* pabs,
+                                            double& vav) {
     __builtin_amdgcn_sched_barrier(0);   // keep one tile's operands live at a time
     const int r = RT * I + k;
-    const double vrr = vabs[2 * r], vri = vabs[2 * r + 1];
+    const double vrr = v[2 * r], vri = v[2 * r + 1];
     double rr = 0.0, ri = 0.0, cr = 0.0, ci = 0.0;
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         const int c = RT * J + q;
-        const double vcr = vabs[2 * c], vci = vabs[2 * c + 1];
+        const double vcr = v[2 * c], vci = v[2 * c + 1];
         const double hr = x.re(q), hi = x.im(q);
         rr += hr * vcr - hi * vci;
         ri += hr * vci + hi * vcr;
@@ -420,15 +432,18 @@ __device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, con
         }
     }
     if (I != J) {
-        atomicAdd(&pabs[2 * (RT * J + k)], cr);
-        atomicAdd(&pabs[2 * (RT * J + k) + 1], ci);
+        const int c = RT * J + k;
+        atomicAdd(&pabs[2 * c], cr);
+        atomicAdd(&pabs[2 * c + 1], ci);
+        vav += v[2 * c] * cr + v[2 * c + 1] * ci;
     }
     atomicAdd(&pabs[2 * r], rr);
     atomicAdd(&pabs[2 * r + 1], ri);
+    vav += vrr * rr + vri * ri;
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// A -= v w^H + w v^H on this lane's tile row (w in pabs)
+// A -= v w^H + w v^H on this lane's tile row
 template <class TileRow>
 __device__ __forceinline__ void tile_update(TileRow& x, int I, int J, int k, const double* vabs, const double* wabs) {
     __builtin_amdgcn_sched_barrier(0);
@@ -531,13 +546,29 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
         L.vabs[i] = 0.0;
         L.v[i] = 0.0;
         L.pabs[i] = 0.0;
+        L.wv[i] = 0.0;
     }
     {
         double unused = 0.0;
         block_sum2<RNW>(tr, unused, L.red);
         if (tid == 0) trace[0] = tr;
     }
+    // column 0 below the diagonal -> vabs, dg[0]; the squared norm below the subdiagonal -> red2
+    {
+        double x2 = 0.0;
+#pragma unroll
+        for (int s = 0; s < RS_REG; ++s) tile_extract(RegRow{ar[s], ai[s]}, tI[s], tJ[s], 0, k, n, L.vabs, dg, x2);
+#pragma unroll
+        for (int s = 0; s < RS_LDS; ++s)
+            tile_extract(LdsRow{L.tr[s], L.ti[s], tid}, tI[RS_REG + s], tJ[RS_REG + s], 0, k, n, L.vabs, dg, x2);
+        publish(x2, L.red2);
+        __syncthreads();
+    }
 
+    // Four barriers per column: after v (in LDS), after the matvec (p = A22 v and v^H A22 v
+    // complete), after w, after the update (which also extracts column j + 1 and its norm).
+    // p^H v = conj(tau) v^H A22 v, so w = tau p - (|tau|^2 / 2)(v^H A22 v) v needs no
+    // reduction of its own.
     for (int j = 0; j < n - 1; ++j) {
         // Tile coordinates are laundered each column so that the compiler recomputes the
         // LDS column addresses instead of keeping 40 of them live across the loop.
@@ -546,14 +577,7 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
             asm volatile("" : "+v"(tI[s]));
             asm volatile("" : "+v"(tJ[s]));
         }
-        // column j below the diagonal -> vabs (absolute rows); diagonal entry -> dg[j]
-        double x2 = 0.0, unused = 0.0;
-#pragma unroll
-        for (int s = 0; s < RS_REG; ++s) tile_extract(RegRow{ar[s], ai[s]}, tI[s], tJ[s], j, k, n, L.vabs, dg, x2);
-#pragma unroll
-        for (int s = 0; s < RS_LDS; ++s)
-            tile_extract(LdsRow{L.tr[s], L.ti[s], tid}, tI[RS_REG + s], tJ[RS_REG + s], j, k, n, L.vabs, dg, x2);
-        block_sum2_once<RNW>(x2, unused, L.red);
+        const double x2 = collect<RNW>(L.red2);
         // every thread forms the reflector scalars itself (same inputs, same result)
         double tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
         {
@@ -575,88 +599,73 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
                 tau[2 * j + 1] = ti_;
             }
         }
-        // v (absolute index, zero at rows <= j), reflector row j; clear the accumulator
-        for (int i = tid; i < n; i += RB) {
-            double vr = 0.0, vi = 0.0;
-            if (i == j + 1) {
-                vr = 1.0;
-            } else if (i > j + 1) {
-                const double xr = L.vabs[2 * i], xi = L.vabs[2 * i + 1];
-                vr = xr * sr - xi * si;
-                vi = xr * si + xi * sr;
-            }
+        const bool reflect = tr_ != 0.0 || ti_ != 0.0;   // the same in every thread
+        // v (absolute rows: 1 at j + 1, (sr + i si) x below, 0 elsewhere) and reflector row j
+        for (int i = tid; i < RMAX; i += RB) {
+            double vr, vi;
+            hh_entry(L.vabs, i, j, n, sr, si, vr, vi);
             L.v[2 * i] = vr;
             L.v[2 * i + 1] = vi;
-            if (i > j) {
+            if (i > j && i < n) {
                 refl[2 * ((long)j * n + (i - j - 1))] = vr;
                 refl[2 * ((long)j * n + (i - j - 1)) + 1] = vi;
             }
-            L.pabs[2 * i] = 0.0;
-            L.pabs[2 * i + 1] = 0.0;
         }
         __syncthreads();
-        if (tr_ == 0.0 && ti_ == 0.0) continue;
-        // p = A22 v (tau applied below)
+        // p = A22 v (tau applied below) and this thread's share of v^H A22 v
+        double vav = 0.0;
+        if (reflect) {
 #pragma unroll
-        for (int s = 0; s < RS_REG; ++s)
-            if (tile_live(tI[s], tJ[s], j)) {
-                RegRow x{ar[s], ai[s]};
-                tile_matvec(x, tI[s], tJ[s], k, L.v, L.pabs);
-            }
+            for (int s = 0; s < RS_REG; ++s)
+                if (tile_live(tI[s], tJ[s], j)) {
+                    RegRow x{ar[s], ai[s]};
+                    tile_matvec(x, tI[s], tJ[s], k, L.v, L.pabs, vav);
+                }
 #pragma unroll
-        for (int s = 0; s < RS_LDS; ++s)
-            if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
-                LdsRow x{L.tr[s], L.ti[s], tid};
-                tile_matvec(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.pabs);
-            }
-        __syncthreads();
-        // p <- tau p; w = p - (tau/2)(p^H v) v
-        double hr = 0.0, hi = 0.0;
-        for (int i = j + 1 + tid; i < n; i += RB) {
-            const double pr0 = L.pabs[2 * i], pi0 = L.pabs[2 * i + 1];
-            const double pr = tr_ * pr0 - ti_ * pi0, pi = tr_ * pi0 + ti_ * pr0;
-            L.pabs[2 * i] = pr;
-            L.pabs[2 * i + 1] = pi;
-            const double vr = L.v[2 * i], vi = L.v[2 * i + 1];
-            hr += pr * vr + pi * vi;
-            hi += pr * vi - pi * vr;
+            for (int s = 0; s < RS_LDS; ++s)
+                if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
+                    LdsRow x{L.tr[s], L.ti[s], tid};
+                    tile_matvec(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.pabs, vav);
+                }
         }
-        block_sum2_once<RNW>(hr, hi, L.red2);
-        const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
-        for (int i = tid; i < RMAX; i += RB) {
-            double wr = 0.0, wi = 0.0;
-            if (i > j && i < n) {
-                const double vr = L.v[2 * i], vi = L.v[2 * i + 1];
-                wr = L.pabs[2 * i] + a2r * vr - a2i * vi;
-                wi = L.pabs[2 * i + 1] + a2r * vi + a2i * vr;
+        publish(vav, L.red);
+        __syncthreads();
+        // w = tau p - (|tau|^2 / 2)(v^H A22 v) v; clear p
+        {
+            const double h = 0.5 * (tr_ * tr_ + ti_ * ti_) * collect<RNW>(L.red);
+            for (int i = tid; i < RMAX; i += RB) {
+                double wr = 0.0, wi = 0.0;
+                if (reflect && i > j && i < n) {
+                    const double pr0 = L.pabs[2 * i], pi0 = L.pabs[2 * i + 1];
+                    wr = tr_ * pr0 - ti_ * pi0 - h * L.v[2 * i];
+                    wi = tr_ * pi0 + ti_ * pr0 - h * L.v[2 * i + 1];
+                }
+                L.wv[2 * i] = wr;
+                L.wv[2 * i + 1] = wi;
+                L.pabs[2 * i] = 0.0;
+                L.pabs[2 * i + 1] = 0.0;
             }
-            L.pabs[2 * i] = wr;
-            L.pabs[2 * i + 1] = wi;
         }
         __syncthreads();
-        // A22 -= v w^H + w v^H (entries outside the trailing block see v = w = 0)
+        // A22 -= v w^H + w v^H (entries outside the trailing block see v = w = 0); then column
+        // j + 1 below the diagonal -> vabs, dg[j + 1], and its norm below the subdiagonal
+        double x2n = 0.0;
 #pragma unroll
-        for (int s = 0; s < RS_REG; ++s)
-            if (tile_live(tI[s], tJ[s], j)) {
-                RegRow x{ar[s], ai[s]};
-                tile_update(x, tI[s], tJ[s], k, L.v, L.pabs);
-            }
+        for (int s = 0; s < RS_REG; ++s) {
+            RegRow x{ar[s], ai[s]};
+            if (reflect && tile_live(tI[s], tJ[s], j)) tile_update(x, tI[s], tJ[s], k, L.v, L.wv);
+            tile_extract(x, tI[s], tJ[s], j + 1, k, n, L.vabs, dg, x2n);
+        }
 #pragma unroll
-        for (int s = 0; s < RS_LDS; ++s)
-            if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
-                LdsRow x{L.tr[s], L.ti[s], tid};
-                tile_update(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.pabs);
-            }
+        for (int s = 0; s < RS_LDS; ++s) {
+            LdsRow x{L.tr[s], L.ti[s], tid};
+            if (reflect && tile_live(tI[RS_REG + s], tJ[RS_REG + s], j))
+                tile_update(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.wv);
+            tile_extract(x, tI[RS_REG + s], tJ[RS_REG + s], j + 1, k, n, L.vabs, dg, x2n);
+        }
+        publish(x2n, L.red2);
         __syncthreads();
     }
-    // last diagonal entry
-    double unused = 0.0;
-#pragma unroll
-    for (int s = 0; s < RS_REG; ++s)
-        tile_extract(RegRow{ar[s], ai[s]}, tI[s], tJ[s], n - 1, k, n, L.vabs, dg, unused);
-#pragma unroll
-    for (int s = 0; s < RS_LDS; ++s)
-        tile_extract(LdsRow{L.tr[s], L.ti[s], tid}, tI[RS_REG + s], tJ[RS_REG + s], n - 1, k, n, L.vabs, dg, unused);
 }
 
 // ------------------------------------------------------------------ eigenvalues / vectors
