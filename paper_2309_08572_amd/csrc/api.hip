@@ -112,6 +112,8 @@ struct Scratch {
     T *bA, *bB, *bT1, *bQ, *bK, *bC, *bR, *bU, *bB2, *bG, *bW, *bVT, *bQ2, *bK2, *bU2;
     double *Gd, *Vd, *evals, *sig, *inv, *st, *sums, *lvec, *rvec, *tl, *tr, *fac, *pout, *sc, *vtmp, *vtmp2;
     double* odev;   // ||Q||_F^2 and non-finite count of recent orthonormal bases (64 pairs)
+    double* sqp;    // partial sums of sumsq (2 SUMSQ_MAX_BLOCKS)
+    unsigned* sqc;  // arrival counter of sumsq (0 between calls)
     int* cnt;
     void* eigwork;
 
@@ -121,6 +123,7 @@ struct Scratch {
         b += 15 * (n2 * sizeof(T) + 256);
         b += 2 * (n2 * sizeof(double) + 256);
         b += 14 * ((size_t)nmax * 2 * sizeof(double) + 256) + 4096 + 2048;
+        b += 2 * SUMSQ_MAX_BLOCKS * sizeof(double) + 256 + 256;   // sumsq partials and counter
         b += eigh_work_bytes(nmax) + 256;
         return b;
     }
@@ -159,6 +162,8 @@ struct Scratch {
         pout = a.take<double>(64);
         sc = a.take<double>(64);
         odev = a.take<double>(128);
+        sqp = a.take<double>(2 * SUMSQ_MAX_BLOCKS);
+        sqc = a.take<unsigned>(64);
         cnt = a.take<int>(64);
         eigwork = (void*)a.take<char>(eigh_work_bytes(n));
     }
@@ -345,8 +350,18 @@ struct Engine {
         sync();
         memcpy(out, c.hbuf, n * sizeof(double));
     }
-    // two device arrays (na + nb <= 64 doubles) with one synchronisation
+    // two device arrays (na + nb <= 64 doubles) with one synchronisation; one copy when they lie
+    // within 1024 doubles of each other (the small result slots of a scratch do)
     void read_doubles2(const double* da, int na, double* oa, const double* db, int nb, double* ob) {
+        const double* lo = std::min(da, db);
+        const double* hi = std::max(da + na, db + nb);
+        if (hi - lo <= 1024) {
+            HIPCHK(hipMemcpyAsync(c.hbuf, lo, (size_t)(hi - lo) * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            memcpy(oa, c.hbuf + (da - lo), na * sizeof(double));
+            memcpy(ob, c.hbuf + (db - lo), nb * sizeof(double));
+            return;
+        }
         HIPCHK(hipMemcpyAsync(c.hbuf, da, na * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(c.hbuf + na, db, nb * sizeof(double), hipMemcpyDeviceToHost, st));
         sync();
@@ -359,6 +374,12 @@ struct Engine {
     void gemm(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_, int batch = 1, long sA = 0,
               long sB = 0, long sC = 0) {
         HIPCHK(cgemm<T>(st, M, N, K, a, A, B, b, C_, batch, sA, sB, sC, ps()));
+    }
+    // C = A (B diag(f)) for a device array f of N real factors
+    void gemm_cols(int M, int N, int K, CView<T> A, CView<T> B, const double* f, CView<T> C_) {
+        GemmOpts o;
+        o.b_col = f;
+        HIPCHK(cgemm_ex<T>(st, M, N, K, C1(), A, B, C0(), C_, o, ps()));
     }
 
     // Gram G = F^H F (c x c) of the n x c view F, into the FP64 eigen buffer (dense, ld c)
@@ -433,7 +454,7 @@ struct Engine {
     void orth_check(const char* stage, T* Q, long ldq, int n, int q, int level, int order) {
         if (q <= 0) return;
         if (nchk == NCHK) orth_verify();
-        HIPCHK(sumsq<T>(st, V<T>(Q, ldq, 1), n, q, s.odev + 2 * nchk));
+        HIPCHK(sumsq<T>(st, V<T>(Q, ldq, 1), n, q, s.odev + 2 * nchk, s.sqp, s.sqc));
         chk_q[nchk] = q;
         chk_order[nchk] = order;
         chk_level[nchk] = level;
@@ -467,8 +488,11 @@ struct Engine {
             gemm(q, q, n, C1(), adj(V<T>(cur, ldc, 1)), V<T>(cur, ldc, 1), C0(), V<T>(s.bG, q, 1));
             T* nxt = cur == Q ? s.bW : Q;
             const long ldn = cur == Q ? (long)q : ldq;
-            HIPCHK(cgemm_shift_b<T>(st, n, q, q, C1(), V<T>(cur, ldc, 1), V<T>(s.bG, q, 1), -0.5, 1.5,
-                                    V<T>(nxt, ldn, 1), ps()));
+            GemmOpts o;
+            o.b_scale = -0.5;
+            o.b_diag = 1.5;
+            HIPCHK(cgemm_ex<T>(st, n, q, q, C1(), V<T>(cur, ldc, 1), V<T>(s.bG, q, 1), C0(), V<T>(nxt, ldn, 1), o,
+                               ps()));
             cur = nxt;
             ldc = ldn;
         }
@@ -497,8 +521,7 @@ struct Engine {
             if (acc <= 0) break;
             // new columns R W diag(lambda^-1/2), made orthogonal to the earlier ones
             T* Qn = Qb + 2 * q;
-            gemm(n, acc, cc, C1(), R, V<T>(s.bVT, cc, 1), C0(), V<T>(Qn, cc, 1));
-            HIPCHK(scale_cols<T>(st, V<T>(Qn, cc, 1), n, acc, s.inv));
+            gemm_cols(n, acc, cc, R, V<T>(s.bVT, cc, 1), s.inv, V<T>(Qn, cc, 1));
             if (q > 0) {
                 gemm(q, acc, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(Qn, cc, 1), C0(), V<T>(s.bG, acc, 1));
                 gemm(n, acc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Qn, cc, 1));
@@ -516,7 +539,7 @@ struct Engine {
             gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(Kb, cc, 1), C1(), V<T>(s.bT1, cc, 1));
             gemm(q, cc, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(s.bT1, cc, 1), C0(), V<T>(s.bW, cc, 1));
             gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bW, cc, 1), C1(), V<T>(s.bT1, cc, 1));
-            HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums));
+            HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums, s.sqp, s.sqc));
             double sums[2], st5[5];
             read_doubles2(s.sums, 2, sums, s.st, 5, st5);
             if (lev == 0) {
@@ -577,7 +600,7 @@ struct Engine {
             }
             ++sub_iters;
             if (m >= rank_bound) break;
-            HIPCHK(sumsq<T>(st, V<T>(Cq, nb, 1), q, nb, s.sums));
+            HIPCHK(sumsq<T>(st, V<T>(Cq, nb, 1), q, nb, s.sums, s.sqp, s.sqc));
             double w[2];
             read_doubles(s.sums, 2, w);
             if (w[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the subspace iteration"};
@@ -621,10 +644,8 @@ struct Engine {
             // next residual would carry that lean as directions of size eps sigma_max^2 / sigma_j
             // and the cut would keep them as spurious Schmidt values.  One pass
             // V <- R (R^H V) diag(1/lambda) puts the columns back into range(R) to rounding.
-            gemm(b, acc, a, C1(), adj(R), V<T>(s.bVT, a, 1), C0(), V<T>(s.bT1, acc, 1));
-            HIPCHK(scale_cols<T>(st, V<T>(s.bT1, acc, 1), b, acc, s.inv));
-            gemm(a, acc, b, C1(), R, V<T>(s.bT1, acc, 1), C0(), V<T>(Vn, ldu, 1));
-            HIPCHK(scale_cols<T>(st, V<T>(Vn, ldu, 1), a, acc, s.inv));
+            gemm_cols(b, acc, a, adj(R), V<T>(s.bVT, a, 1), s.inv, V<T>(s.bT1, acc, 1));
+            gemm_cols(a, acc, b, R, V<T>(s.bT1, acc, 1), s.inv, V<T>(Vn, ldu, 1));
             if (kacc > 0) {
                 gemm(kacc, acc, a, C1(), adj(V<T>(Ub, ldu, 1)), V<T>(Vn, ldu, 1), C0(), V<T>(s.bG, acc, 1));
                 gemm(a, acc, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Vn, ldu, 1));
@@ -639,7 +660,7 @@ struct Engine {
             gemm(a, b, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(Bb, b, 1), C1(), V<T>(s.bR, b, 1));
             gemm(kacc, b, a, C1(), adj(V<T>(Ub, ldu, 1)), V<T>(s.bR, b, 1), C0(), V<T>(Bb, b, 1));
             gemm(a, b, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(Bb, b, 1), C1(), V<T>(s.bR, b, 1));
-            HIPCHK(sumsq<T>(st, V<T>(s.bR, b, 1), a, b, s.sums));
+            HIPCHK(sumsq<T>(st, V<T>(s.bR, b, 1), a, b, s.sums, s.sqp, s.sqc));
             double sums[2], st5[5];
             read_doubles2(s.sums, 2, sums, s.st, 5, st5);
             // the residual R = F - U U^H F carries rounding of about eps ||F||_F: values below
@@ -794,7 +815,7 @@ struct Engine {
             // core C = K Fb (q x nb)
             gemm(q, nb, k, C1(), V<T>(s.bK, k, 1), Fb, C0(), V<T>(s.bC, nb, 1));
             // ||theta||^2 (= ||C||^2) and its non-finite count stay in sc[4..5] for PPT
-            HIPCHK(sumsq<T>(st, V<T>(s.bC, nb, 1), q, nb, s.sc + 4));
+            HIPCHK(sumsq<T>(st, V<T>(s.bC, nb, 1), q, nb, s.sc + 4, s.sqp, s.sqc));
             double sums[2];
             read_doubles(s.sc + 4, 2, sums);
             if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
@@ -819,7 +840,7 @@ struct Engine {
             CView<T> Th = V<T>(s.bA, nR, 1);
             HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
             HIPCHK(dot(st, s.lvec, s.vtmp, nL, s.sc));
-            HIPCHK(sumsq<T>(st, Th, nL, nR, s.sc + 4));
+            HIPCHK(sumsq<T>(st, Th, nL, nR, s.sc + 4, s.sqp, s.sqc));
             double sums[2];
             read_doubles(s.sc + 4, 2, sums);
             if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
@@ -1011,6 +1032,10 @@ void alloc_state(mpdo_ctx c) {
     c->sd.carve(c->arena, c->fp32 ? 64 : nmax);
     if (c->fp32) c->sf.carve(c->arena, nmax);
     c->sg.carve(c->arena, m2);
+    // sumsq arrival counters start at 0 (every call leaves them 0)
+    HIPCHK(hipMemsetAsync(c->sd.sqc, 0, 64 * sizeof(unsigned), c->st));
+    if (c->fp32) HIPCHK(hipMemsetAsync(c->sf.sqc, 0, 64 * sizeof(unsigned), c->st));
+    HIPCHK(hipMemsetAsync(c->sg.sqc, 0, 64 * sizeof(unsigned), c->st));
     c->gslots.clear();
     c->fcache.clear();
     c->sdev_id = 0;

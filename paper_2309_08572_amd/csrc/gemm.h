@@ -14,12 +14,21 @@ template <typename T>
 hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
                  CView<T> C, int batch = 1, long sA = 0, long sB = 0, long sC = 0, ProfSink* prof = nullptr);
 
-// C = alpha * A * (b_scale * B + b_diag * I) (B square in its leading K x N block): the shifted
-// operand is formed as B's tiles are loaded, so an iteration such as Newton-Schulz,
-// X (3/2 I - 1/2 X^H X), needs no separate kernel for it.  C must not alias A or B.
+// Operand transforms applied as B's tiles are loaded, so that no separate kernel forms them:
+// op(B) -> (b_scale op(B) + b_diag I) diag(b_col)  (b_diag needs B square in its leading
+// K x N block; b_col, if non-null, is a device array of N real factors).  Newton-Schulz,
+// X (3/2 I - 1/2 X^H X), and products followed by a column scaling, R (V diag(s)), use them.
+struct GemmOpts {
+    double b_scale = 1.0;
+    double b_diag = 0.0;
+    const double* b_col = nullptr;
+};
+
+// cgemm with operand transforms.  C must not alias A or B.
 template <typename T>
-hipError_t cgemm_shift_b(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, double b_scale,
-                         double b_diag, CView<T> C, ProfSink* prof = nullptr);
+hipError_t cgemm_ex(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
+                    const GemmOpts& opt, ProfSink* prof = nullptr, int batch = 1, long sA = 0, long sB = 0,
+                    long sC = 0);
 
 // Number of shape buckets the launch-plan autotuner has settled (MPDO_GEMM_AUTOTUNE=1).
 int gemm_tuned_buckets();

@@ -74,6 +74,7 @@ struct GemmArgs {
     int atomic;        // 1: accumulate alpha*AB into C with atomics (beta ignored)
     int bshift;        // 1: op(B) is replaced by bsc op(B) + bdg I as it is loaded
     double bsc, bdg;
+    const double* bcol;   // non-null: column n of op(B) is scaled by bcol[n] as it is loaded
 };
 
 template <typename T>
@@ -83,14 +84,17 @@ __device__ __forceinline__ void load_cplx(const T* p, long off, int conj, T& re,
     if (conj) im = -im;
 }
 
-// WM: MFMA tiles per wave along each output dimension; block tile (32 WM) x (32 WM)
-template <typename T, int WM>
+// WM: MFMA tiles per wave along each output dimension; block tile (32 WM) x (32 WM).
+// TF: 1 if B's operand transforms (bshift, bcol) may be set; the plain kernel keeps the
+// registers they need free (the FP64 64 x 64 kernel stays within two waves per SIMD).
+template <typename T, int WM, int TF>
 __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
     constexpr int BM = 32 * WM, BN = 32 * WM, WQ = 16 * WM;
     __shared__ T sAr[BM][BK + 1];
     __shared__ T sAi[BM][BK + 1];
     __shared__ T sBr[BK][BN + 1];
     __shared__ T sBi[BK][BN + 1];
+    __shared__ double sbf[BN];   // column factors of B (b_col)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -143,15 +147,16 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
             const int gn = n0 + n, gk = k0 + k;
             pbr[j] = 0;
             pbi[j] = 0;
-            if (gn < g.N && gk < kend) {
-                load_cplx(Bp, (long)gk * g.B.rs + (long)gn * g.B.cs, g.B.conj, pbr[j], pbi[j]);
-                if (g.bshift) {
-                    pbr[j] = (T)((gk == gn ? g.bdg : 0.0) + g.bsc * (double)pbr[j]);
-                    pbi[j] = (T)(g.bsc * (double)pbi[j]);
-                }
-            }
+            if (gn < g.N && gk < kend) load_cplx(Bp, (long)gk * g.B.rs + (long)gn * g.B.cs, g.B.conj, pbr[j], pbi[j]);
         }
     };
+    // operand transforms of B are applied when a tile is staged (the loaded values are waited
+    // for there anyway); the column factors do not depend on k and are read once into LDS
+    const bool btf = TF && (g.bshift || g.bcol);
+    if (TF && g.bcol) {
+        for (int i = tid; i < BN; i += 256) sbf[i] = n0 + i < g.N ? g.bcol[n0 + i] : 1.0;
+        __syncthreads();
+    }
     if (kbeg < kend) fetch(kbeg);
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
         // ---- stage the fetched A tile (BM x BK) and B tile (BK x BN) in LDS
@@ -166,8 +171,17 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
         for (int j = 0; j < PB; ++j) {
             const int e = tid + 256 * j;
             const int n = b_nfast ? e % BN : e / BK, k = b_nfast ? e / BN : e % BK;
-            sBr[k][n] = pbr[j];
-            sBi[k][n] = pbi[j];
+            T br = pbr[j], bi = pbi[j];
+            if (btf) {
+                // (bsc B + bdg I) diag(bcol); entries outside the product stay zero
+                const int gn = n0 + n, gk = k0 + k;
+                const double dg = (g.bshift && gk == gn && gn < g.N && gk < kend) ? g.bdg : 0.0;
+                const double f = g.bcol ? sbf[n] : 1.0;
+                br = (T)((dg + g.bsc * (double)br) * f);
+                bi = (T)(g.bsc * (double)bi * f);
+            }
+            sBr[k][n] = br;
+            sBi[k][n] = bi;
         }
         __syncthreads();
         if (k0 + BK < kend) fetch(k0 + BK);
@@ -282,10 +296,12 @@ double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p) {
     return mfma_us + 0.25 * bytes / 16e6 + atomic_us + 2.0 + (p.ks > 1 ? 5.0 : 0.0);
 }
 
-Plan plan_of(int M, int N, int K, int batch, bool fp64) {
-    Plan best{2, 1};
+// wm_max = 1 restricts the plan to 32 x 32 tiles (the kernel with operand transforms needs
+// more registers than two waves per SIMD allow at 64 x 64)
+Plan plan_of(int M, int N, int K, int batch, bool fp64, int wm_max = 2) {
+    Plan best{wm_max, 1};
     double best_t = plan_cost(M, N, K, batch, fp64, best);
-    for (int wm = 2; wm >= 1; --wm)
+    for (int wm = wm_max; wm >= 1; --wm)
         for (int ks = 1; ks <= 64; ks *= 2) {
             if (ks > 1 && K < 2 * BK) break;
             const int k_eff = ks > 1 ? (K + chunk_of(K, ks) - 1) / chunk_of(K, ks) : 1;
@@ -303,8 +319,8 @@ Plan plan_of(int M, int N, int K, int batch, bool fp64) {
 // One product with the plan's tile size and k split (ks = 1: no split).
 template <typename T>
 hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
-                        int batch, long sA, long sB, long sC, Plan plan, ProfSink* prof, double bsc = 1.0,
-                        double bdg = 0.0) {
+                        int batch, long sA, long sB, long sC, Plan plan, ProfSink* prof,
+                        const GemmOpts& opt = GemmOpts()) {
     GemmArgs<T> g;
     g.M = M;
     g.N = N;
@@ -321,9 +337,10 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
     g.br = beta.re;
     g.bi = beta.im;
     g.atomic = 0;
-    g.bshift = (bsc != 1.0 || bdg != 0.0) ? 1 : 0;
-    g.bsc = bsc;
-    g.bdg = bdg;
+    g.bshift = (opt.b_scale != 1.0 || opt.b_diag != 0.0) ? 1 : 0;
+    g.bsc = opt.b_scale;
+    g.bdg = opt.b_diag;
+    g.bcol = opt.b_col;
     g.ksplit = 1;
     g.kchunk = ((g.K + BK - 1) / BK) * BK;
     if (g.kchunk == 0) g.kchunk = BK;
@@ -350,10 +367,18 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
     const int bt = 32 * plan.wm;
     dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, batch * g.ksplit);
     if (prof) prof->begin(s, PF_GEMM);
-    if (plan.wm == 2)
-        hipLaunchKernelGGL((cgemm_kernel<T, 2>), grid, dim3(256), 0, s, g);
-    else
-        hipLaunchKernelGGL((cgemm_kernel<T, 1>), grid, dim3(256), 0, s, g);
+    const bool tf = g.bshift || g.bcol;
+    if (plan.wm == 2) {
+        if (tf)
+            hipLaunchKernelGGL((cgemm_kernel<T, 2, 1>), grid, dim3(256), 0, s, g);
+        else
+            hipLaunchKernelGGL((cgemm_kernel<T, 2, 0>), grid, dim3(256), 0, s, g);
+    } else {
+        if (tf)
+            hipLaunchKernelGGL((cgemm_kernel<T, 1, 1>), grid, dim3(256), 0, s, g);
+        else
+            hipLaunchKernelGGL((cgemm_kernel<T, 1, 0>), grid, dim3(256), 0, s, g);
+    }
     if (prof) {
         // algorithmic: 8 flop per complex multiply-add; A, B read and C written once (and read
         // when beta != 0)
@@ -448,23 +473,21 @@ Plan tune_plan(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T
 }  // namespace
 
 template <typename T>
-hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
-                 CView<T> C, int batch, long sA, long sB, long sC, ProfSink* prof) {
+hipError_t cgemm_ex(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
+                    const GemmOpts& opt, ProfSink* prof, int batch, long sA, long sB, long sC) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     const int k = K < 0 ? 0 : K;
-    Plan plan = plan_of(M, N, k, batch, std::is_same<T, double>::value);
-    if (autotune_on() && beta.re == 0.0 && beta.im == 0.0 && K >= 128)
+    const bool plain = opt.b_scale == 1.0 && opt.b_diag == 0.0 && !opt.b_col;
+    Plan plan = plan_of(M, N, k, batch, std::is_same<T, double>::value, plain ? 2 : 1);
+    if (plain && autotune_on() && beta.re == 0.0 && beta.im == 0.0 && K >= 128)
         plan = tune_plan<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC);
-    return cgemm_launch<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, plan, prof);
+    return cgemm_launch<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, plan, prof, opt);
 }
 
 template <typename T>
-hipError_t cgemm_shift_b(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, double b_scale,
-                         double b_diag, CView<T> C, ProfSink* prof) {
-    if (M <= 0 || N <= 0) return hipSuccess;
-    const int k = K < 0 ? 0 : K;
-    const Plan plan = plan_of(M, N, k, 1, std::is_same<T, double>::value);
-    return cgemm_launch<T>(s, M, N, k, alpha, A, B, cd{0.0, 0.0}, C, 1, 0, 0, 0, plan, prof, b_scale, b_diag);
+hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
+                 CView<T> C, int batch, long sA, long sB, long sC, ProfSink* prof) {
+    return cgemm_ex<T>(s, M, N, K, alpha, A, B, beta, C, GemmOpts(), prof, batch, sA, sB, sC);
 }
 
 int gemm_tuned_buckets() {
@@ -476,9 +499,9 @@ template hipError_t cgemm<double>(hipStream_t, int, int, int, cd, CView<double>,
                                   CView<double>, int, long, long, long, ProfSink*);
 template hipError_t cgemm<float>(hipStream_t, int, int, int, cd, CView<float>, CView<float>, cd,
                                  CView<float>, int, long, long, long, ProfSink*);
-template hipError_t cgemm_shift_b<double>(hipStream_t, int, int, int, cd, CView<double>, CView<double>, double,
-                                          double, CView<double>, ProfSink*);
-template hipError_t cgemm_shift_b<float>(hipStream_t, int, int, int, cd, CView<float>, CView<float>, double, double,
-                                         CView<float>, ProfSink*);
+template hipError_t cgemm_ex<double>(hipStream_t, int, int, int, cd, CView<double>, CView<double>, cd,
+                                     CView<double>, const GemmOpts&, ProfSink*, int, long, long, long);
+template hipError_t cgemm_ex<float>(hipStream_t, int, int, int, cd, CView<float>, CView<float>, cd, CView<float>,
+                                    const GemmOpts&, ProfSink*, int, long, long, long);
 
 }  // namespace mpdo

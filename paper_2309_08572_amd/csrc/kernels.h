@@ -31,9 +31,14 @@ hipError_t transfer_right(hipStream_t s, const T* A, int cl, int D2, int cr, con
 // v = x (x) z  (complex FP64 vectors of lengths na, nb).
 hipError_t kron_vec(hipStream_t s, const double* x, int na, const double* z, int nb, double* v);
 
-// out2[0] = ||X||_F^2, out2[1] = number of non-finite blocks (FP64).
+// out2[0] = ||X||_F^2, out2[1] = number of blocks with non-finite entries (FP64), in one
+// launch of at most SUMSQ_MAX_BLOCKS blocks.  part: device scratch of 2 SUMSQ_MAX_BLOCKS
+// doubles; cnt: a device counter that is 0 before the call (zero it once when it is
+// allocated; every call leaves it 0 again).  Calls that share part and cnt must be ordered
+// on one stream.
+constexpr int SUMSQ_MAX_BLOCKS = 1024;
 template <typename T>
-hipError_t sumsq(hipStream_t s, CView<T> X, int M, int N, double* out2);
+hipError_t sumsq(hipStream_t s, CView<T> X, int M, int N, double* out2, double* part, unsigned* cnt);
 
 // L[a][b] = x[a] x[b] for the complex FP64 vector x of length n (n x n, row-major, in T).
 template <typename T>

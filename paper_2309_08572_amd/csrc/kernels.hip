@@ -200,30 +200,63 @@ __global__ void kron_kernel(const double* __restrict__ x, int na, const double* 
     v[2 * idx + 1] = xr * zi + xi * zr;
 }
 
+// ||X||_F^2 and the count of non-finite entries in one launch: each block stores its partial
+// sums in part[2 b], part[2 b + 1] and counts itself in *cnt; the last block to arrive adds the
+// partials in block order (the result does not depend on which block finishes when), writes
+// out[0..1] and resets *cnt to 0 for the next call.
 template <typename T>
-__global__ void sumsq_kernel(CView<T> X, int M, int N, double* __restrict__ out) {
+__global__ void sumsq_kernel(CView<T> X, int M, int N, double* __restrict__ out, double* __restrict__ part_g,
+                             unsigned* __restrict__ cnt) {
     __shared__ double part[256];
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    double acc = 0.0;
+    __shared__ double pbad[256];
+    __shared__ bool last;
+    double acc = 0.0, bad = 0.0;
     const long tot = (long)M * N;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += (long)gridDim.x * blockDim.x) {
         const int m = (int)(idx / N), n = (int)(idx - (idx / N) * N);
         const long off = 2 * ((long)m * X.rs + (long)n * X.cs);
         const double r = (double)X.p[off], i = (double)X.p[off + 1];
-        if (!isfinite(r) || !isfinite(i)) bad = 1;
+        if (!isfinite(r) || !isfinite(i)) bad = 1.0;
         acc += r * r + i * i;
     }
     part[threadIdx.x] = acc;
+    pbad[threadIdx.x] = bad;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        if (threadIdx.x < s) {
+            part[threadIdx.x] += part[threadIdx.x + s];
+            pbad[threadIdx.x] += pbad[threadIdx.x + s];
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicAdd(&out[0], part[0]);
-        if (bad) atomicAdd(&out[1], 1.0);
+        part_g[2 * blockIdx.x] = part[0];
+        part_g[2 * blockIdx.x + 1] = pbad[0];
+        __threadfence();
+        last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+        a += part_g[2 * i];
+        b += part_g[2 * i + 1];
+    }
+    part[threadIdx.x] = a;
+    pbad[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            part[threadIdx.x] += part[threadIdx.x + s];
+            pbad[threadIdx.x] += pbad[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = part[0];
+        out[1] = pbad[0];
+        *cnt = 0u;
     }
 }
 
@@ -612,11 +645,11 @@ hipError_t kron_vec(hipStream_t s, const double* x, int na, const double* z, int
 }
 
 template <typename T>
-hipError_t sumsq(hipStream_t s, CView<T> X, int M, int N, double* out2) {
-    hipLaunchKernelGGL(zero_doubles_kernel, dim3(1), dim3(64), 0, s, out2, 2);
+hipError_t sumsq(hipStream_t s, CView<T> X, int M, int N, double* out2, double* part, unsigned* cnt) {
     unsigned nb = blocks_for((long)M * N);
-    if (nb > 1024) nb = 1024;
-    hipLaunchKernelGGL(sumsq_kernel<T>, dim3(nb), dim3(256), 0, s, X, M, N, out2);
+    if (nb > SUMSQ_MAX_BLOCKS) nb = SUMSQ_MAX_BLOCKS;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(sumsq_kernel<T>, dim3(nb), dim3(256), 0, s, X, M, N, out2, part, cnt);
     return hipGetLastError();
 }
 
@@ -699,7 +732,7 @@ hipError_t bilinear(hipStream_t s, const T* L, int n, const double* y, double* o
                                          double*);                                                              \
     template hipError_t transfer_right<T>(hipStream_t, const T*, int, int, int, const double*, const double*,   \
                                           double*);                                                             \
-    template hipError_t sumsq<T>(hipStream_t, CView<T>, int, int, double*);                                      \
+    template hipError_t sumsq<T>(hipStream_t, CView<T>, int, int, double*, double*, unsigned*);                \
     template hipError_t outer<T>(hipStream_t, const double*, int, T*);                                          \
     template hipError_t bilinear<T>(hipStream_t, const T*, int, const double*, double*);                         \
     template hipError_t scale_cols<T>(hipStream_t, CView<T>, int, int, const double*);                          \
