@@ -136,6 +136,25 @@ mpdo_status mpdo_apply_gate(mpdo_ctx ctx, int site, const double* superop,
 mpdo_status mpdo_apply_gate_kraus(mpdo_ctx ctx, int site, int n_kraus, const double* kraus,
                                   mpdo_trunc_info* info);
 
+/* Pulse-level gate of atoms (site, site+1) with nearest-neighbour Rydberg crosstalk (Sec. II,
+ * "MPO form of the noisy CZ gate with crosstalk"; noise-free, as the paper simulates it):
+ * rho -> U rho U^+ with U = sum_{a,b in {0,1}} P^a_{site-1} (x) u[a + 2b] (x) P^b_{site+2},
+ * P^1 = |rydberg><rydberg| and P^0 = I - P^1 on the neighbour.  u4: four pair unitaries of
+ * d^2 x d^2 complex (host, index sigma_site*d + sigma_{site+1}), u4[a + 2b] being the pulse
+ * with the detunings of atoms site and site+1 shifted by a*B and b*B.  At an end of the chain
+ * the missing neighbour contributes a = 0 (or b = 0) only.  Channels queued on the four atoms
+ * act first.  The gate is applied exactly: the neighbour bonds are enlarged four-fold by the
+ * neighbours' Rydberg class, the pair's merged tensor receives the gate block by block and is
+ * split without a cut (info describes that split), and canonical sweeps over the four atoms
+ * compress the three bonds to their Schmidt ranks.  Needs 4 chi_l', 4 chi_r' and
+ * D2 * min(4 chi_l', 4 chi_r') within chi_max, chi_l' and chi_r' being the bonds between each
+ * neighbour and the pair (factor 1 instead of 4 at a chain end).  The first call allocates
+ * 16 D2^4 complex FP64 (plus an FP32 copy in FP32 mode) with hipMalloc, freed by
+ * mpdo_destroy.  E_ARG for site outside [0, N-2], rydberg outside [0, d), non-finite or
+ * non-unitary (by more than 1e-10) entries, or a pair that does not fit chi_max. */
+mpdo_status mpdo_apply_gate_crosstalk(mpdo_ctx ctx, int site, int rydberg, const double* u4,
+                                      mpdo_trunc_info* info);
+
 /* Single-atom channel (Sec. II noise; Sec. IV mixer): n_kraus operators of d x d complex
  * (host).  The map is queued on the atom and enters the next two-site update that touches
  * it (maps on different atoms commute), or the next expectation.  E_ARG if not trace

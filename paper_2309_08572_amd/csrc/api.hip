@@ -248,6 +248,16 @@ struct FoldEntry {
 };
 constexpr int FOLD_CACHE_MAX = 64;
 
+// Two-site map that depends on the classes of the enlarged outer bonds (crosstalk gate): the
+// left bond of the pair is na blocks of c1 (class alpha, block-major), the right bond nb blocks
+// of c3; block (alpha, beta) of theta receives the D2^2 x D2^2 superoperator G[4 alpha + beta]
+// (device, working precision).
+template <typename T>
+struct BlockGate {
+    int na = 1, nb = 1, c1 = 0, c3 = 0;
+    const T* G[16] = {nullptr};
+};
+
 }  // namespace
 
 // ====================================================================== context
@@ -281,6 +291,8 @@ struct mpdo_ctx_s {
     int lvalid = 0, rvalid = 0;
     double* Sdev = nullptr;       // D2^2 x D2^2 superoperator (FP64)
     void* SdevT = nullptr;        // same in the working precision
+    double* xg = nullptr;         // crosstalk block superoperators (16 x D2^4 complex FP64), on first use
+    void* xgT = nullptr;          // the same in the working precision (FP32 mode)
     double* hbuf = nullptr;       // pinned host buffer
     int* hint = nullptr;
 
@@ -724,6 +736,21 @@ struct Engine {
     // ------------------------------------------------------------ canonical moves
     void swap_site(int j, int spare_idx) { std::swap(c.site[j], c.spare[spare_idx]); }
 
+    // site j <- P applied on its physical index (P: D2 x D2 device matrix, row = new index)
+    void apply_phys(int j, const T* P) {
+        const int cl = c.dims[j], cr = c.dims[j + 1], D2 = c.D2;
+        gemm(D2, cr, D2, C1(), V<T>((T*)P, D2, 1), V<T>(site(j), cr, 1), C0(), V<T>((T*)c.spare[0], cr, 1), cl, 0,
+             (long)D2 * cr, (long)D2 * cr);
+        swap_site(j, 0);
+        site_changed(j);
+    }
+    // site j enlarged by class_expand (mode, ncls); the caller updates the bond dimension
+    void expand(int j, int mode, int ncls, const EtaClass& cls) {
+        HIPCHK(class_expand<T>(st, site(j), c.dims[j], c.D2, c.dims[j + 1], mode, ncls, cls, (T*)c.spare[0]));
+        swap_site(j, 0);
+        site_changed(j);
+    }
+
     void move_right(int j) {
         const int cl = c.dims[j], cr = c.dims[j + 1], cr2 = c.dims[j + 2];
         const int n = cl * c.D2;
@@ -764,7 +791,7 @@ struct Engine {
     }
 
     // ------------------------------------------------------------ the two-site update
-    void update(int i, const GateFactor* gf, int chi, mpdo_trunc_info* info) {
+    void update(int i, const GateFactor* gf, int chi, mpdo_trunc_info* info, const BlockGate<T>* bg = nullptr) {
         eig_calls = 0;
         sub_iters = 0;
         const int D2 = c.D2;
@@ -785,7 +812,7 @@ struct Engine {
         const int na = dir > 0 ? nL : nR;
         const int nb = dir > 0 ? nR : nL;
         const int r = gf ? gf->r : 0;
-        const bool factored = gf && r <= MAX_FACTOR_RANK && (long)r * cm < (long)na;
+        const bool factored = !bg && gf && r <= MAX_FACTOR_RANK && (long)r * cm < (long)na;
         int kept = 0;
         double n2 = 0.0;
         T* Left = nullptr;   // new site i  (nL x kept), unscaled
@@ -833,10 +860,21 @@ struct Engine {
         } else {
             // explicit theta: merge then gate
             const int m2 = D2 * D2;
-            load_superop();
             gemm(nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(), V<T>(s.bT1, nR, 1));
-            gemm(m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(), V<T>(s.bA, cr, 1), cl, 0,
-                 (long)m2 * cr, (long)m2 * cr);
+            if (bg) {
+                // theta[l][eta eta'][r] as cl blocks of m2 x cr: block (alpha, beta) = rows
+                // l in [alpha c1, (alpha + 1) c1), columns r in [beta c3, (beta + 1) c3)
+                for (int a = 0; a < bg->na; ++a)
+                    for (int b = 0; b < bg->nb; ++b) {
+                        const long off = 2 * ((long)a * bg->c1 * m2 * cr + (long)b * bg->c3);
+                        gemm(m2, bg->c3, m2, C1(), V<T>((T*)bg->G[4 * a + b], m2, 1), V<T>(s.bT1 + off, cr, 1), C0(),
+                             V<T>(s.bA + off, cr, 1), bg->c1, 0, (long)m2 * cr, (long)m2 * cr);
+                    }
+            } else {
+                load_superop();
+                gemm(m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(), V<T>(s.bA, cr, 1), cl, 0,
+                     (long)m2 * cr, (long)m2 * cr);
+            }
             CView<T> Th = V<T>(s.bA, nR, 1);
             HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
             HIPCHK(dot(st, s.lvec, s.vtmp, nL, s.sc));
@@ -938,6 +976,28 @@ std::vector<zc> superop_from_kraus_2(const double* kraus, int nk, int d) {
                                     }
                     }
     }
+    return S;
+}
+
+// Superoperator of rho -> Kk rho Kb^+ on two atoms (Kk, Kb: d^2 x d^2 on sigma_i d + sigma_{i+1}),
+// in the layout of superop_from_kraus_2 (which sums this over Kk = Kb = K)
+std::vector<zc> superop_pair(const zc* Kk, const zc* Kb, int d) {
+    const int D2 = d * d, m = D2 * D2;
+    std::vector<zc> S((size_t)m * m);
+    for (int a = 0; a < d; ++a)
+        for (int ap = 0; ap < d; ++ap)
+            for (int b = 0; b < d; ++b)
+                for (int bp = 0; bp < d; ++bp) {
+                    const int row = (a * d + ap) * D2 + (b * d + bp);
+                    for (int s_ = 0; s_ < d; ++s_)
+                        for (int sp = 0; sp < d; ++sp)
+                            for (int t = 0; t < d; ++t)
+                                for (int tp = 0; tp < d; ++tp) {
+                                    const int col = (s_ * d + sp) * D2 + (t * d + tp);
+                                    S[(size_t)row * m + col] =
+                                        Kk[(a * d + b) * D2 + (s_ * d + t)] * std::conj(Kb[(ap * d + bp) * D2 + (sp * d + tp)]);
+                                }
+                }
     return S;
 }
 
@@ -1217,6 +1277,118 @@ void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n
     }
 }
 
+// Crosstalk gate of the pair (i, i+1) (noise-free, Sec. II "MPO form of the noisy CZ gate with
+// crosstalk"): U = sum_ab P^a_{i-1} (x) u[a + 2b] (x) P^b_{i+2}, P^1 the Rydberg projector.  On
+// the vectorised index eta = sigma d + sigma' of a neighbour the projectors pick the class
+// alpha = [sigma = r] + 2 [sigma' = r]; the superoperator is block diagonal in the two
+// neighbours' classes, with block u[a + 2b] (x) conj(u[a' + 2b']).  Steps:
+//  1. the centre moves to the pair; queued maps of the neighbours are applied to their sites,
+//     those of the pair are folded into the blocks;
+//  2. the neighbour bonds are enlarged by the class (site i-1 and i+2 keep each entry only in
+//     its class block, sites i and i+1 are replicated), which represents the same rho exactly;
+//  3. the pair update applies block (alpha, beta) to its part of theta and splits it; theta's
+//     rank bound fits chi_max, so nothing is cut and PPT is the identity;
+//  4. canonical sweeps over i-1 .. i+2 orthonormalise the enlarged sites, compressing the three
+//     bonds to their Schmidt ranks (range bases; nothing above the rounding floor is cut).
+// The gate is therefore exact; it needs the enlarged bonds (4x) and theta's rank bound
+// min(cl D2, D2 cr) within chi_max.
+template <typename T>
+void do_crosstalk(mpdo_ctx c, Engine<T>& E, int i, int ryd, const double* u4, mpdo_trunc_info* info) {
+    const int d = c->d, D2 = c->D2, m2 = D2 * D2, N = c->N;
+    const bool left = i >= 1, right = i + 2 <= N - 1;
+    const int na = left ? 4 : 1, nb = right ? 4 : 1;
+    // In the enlarged form the pair's middle bond is not rho's Schmidt cut (the class sums over
+    // the neighbour bonds lie outside theta), so theta is split without a cut: its rank bound
+    // min(cl D2, D2 cr) must fit chi_max as well as the enlarged bonds themselves.
+    const long cl_x = (long)na * c->dims[i], cr_x = (long)nb * c->dims[i + 2];
+    if (cl_x > c->chi || cr_x > c->chi || std::min(cl_x, cr_x) * D2 > c->chi)
+        throw Fail{MPDO_E_ARG, "crosstalk gate: the enlarged pair does not fit chi_max"};
+    EtaClass cls;
+    for (int e = 0; e < EtaClass::MAXD2; ++e) cls.c[e] = 0;
+    for (int e = 0; e < D2; ++e) cls.c[e] = ((e / d) == ryd ? 1 : 0) + ((e % d) == ryd ? 2 : 0);
+    // block superoperators with the pair's queued maps folded in
+    const size_t blk = (size_t)m2 * m2;
+    if (!c->xg) {
+        if (hipMalloc((void**)&c->xg, 16 * blk * sizeof(zc)) != hipSuccess) throw Fail{MPDO_E_NOMEM, "crosstalk blocks"};
+        if (c->fp32 && hipMalloc(&c->xgT, 16 * blk * 2 * sizeof(float)) != hipSuccess)
+            throw Fail{MPDO_E_NOMEM, "crosstalk blocks"};
+    }
+    const zc* U = (const zc*)u4;
+    for (int al = 0; al < na; ++al)
+        for (int be = 0; be < nb; ++be) {
+            const int a = al & 1, ap = al >> 1, b = be & 1, bp = be >> 1;
+            std::vector<zc> S = superop_pair(U + (size_t)(a + 2 * b) * m2, U + (size_t)(ap + 2 * bp) * m2, d);
+            if (!c->pend_id[i] || !c->pend_id[i + 1]) fold_pending(c, i, S);
+            HIPCHK(hipMemcpyAsync(c->xg + 2 * (size_t)(4 * al + be) * blk, S.data(), blk * sizeof(zc),
+                                  hipMemcpyHostToDevice, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));   // S is freed at the end of this iteration
+        }
+    BlockGate<T> bg;
+    bg.na = na;
+    bg.nb = nb;
+    for (int q = 0; q < 16; ++q) {
+        if (c->fp32)
+            bg.G[q] = (const T*)((float*)c->xgT + 2 * (size_t)q * blk);
+        else
+            bg.G[q] = (const T*)(c->xg + 2 * (size_t)q * blk);
+    }
+    if (c->fp32)
+        HIPCHK((geam<double, float>(c->st, 16 * m2, m2, C1(), V<double>(c->xg, m2, 1), C0(),
+                                    V<float>((float*)c->xgT, m2, 1))));
+    // 1. centre to the pair; queued maps
+    if (c->centre < i) c->dir = 1;
+    else if (c->centre > i + 1) c->dir = -1;
+    while (c->centre < i) E.move_right(c->centre);
+    while (c->centre > i + 1) E.move_left(c->centre);
+    for (int j : {i - 1, i + 2}) {
+        if (j < 0 || j >= N || c->pend_id[j]) continue;
+        std::vector<zc> P = c->pending[j];
+        upload(c, c->Sdev, P.data(), P.size() * sizeof(zc));   // Sdev as staging; its cache tag is cleared
+        c->sdev_id = 0;
+        if (c->fp32) {
+            HIPCHK((geam<double, float>(c->st, D2, D2, C1(), V<double>(c->Sdev, D2, 1), C0(),
+                                        V<float>((float*)c->SdevT, D2, 1))));
+            E.apply_phys(j, (const T*)c->SdevT);
+        } else {
+            E.apply_phys(j, (const T*)c->Sdev);
+        }
+        c->pend_id[j] = 1;
+        set_ovec(c, j);
+    }
+    if (!c->pend_id[i] || !c->pend_id[i + 1]) {   // folded into the blocks above
+        c->pend_id[i] = c->pend_id[i + 1] = 1;
+        set_ovec(c, i);
+        set_ovec(c, i + 1);
+    }
+    // 2. enlarge the neighbour bonds by class
+    bg.c1 = c->dims[i];
+    bg.c3 = c->dims[i + 2];
+    if (left) {
+        E.expand(i - 1, 0, 4, cls);
+        E.expand(i, 1, 4, cls);
+        c->dims[i] *= 4;
+    }
+    if (right) {
+        E.expand(i + 1, 2, 4, cls);
+        E.expand(i + 2, 3, 4, cls);
+        c->dims[i + 2] *= 4;
+    }
+    c->lvalid = std::min(c->lvalid, std::max(0, i - 1));
+    c->rvalid = std::max(c->rvalid, std::min(N, i + 3));
+    // 3. the pair update with the block superoperators
+    E.update(i, nullptr, c->chi, info, &bg);
+    // 4. canonical form over lo .. hi = i-1 .. i+2.  A bond shrinks to its Schmidt rank when
+    //    the centre crosses it with both sides isometric: sweep to hi, back to lo (every site
+    //    right of lo, the enlarged i+2 included, becomes a right isometry), then to hi again,
+    //    where each move orthonormalises a site whose left side is isometric.
+    const int lo = left ? i - 1 : i, hi = right ? i + 2 : i + 1;
+    while (c->centre < hi) E.move_right(c->centre);
+    while (c->centre > lo) E.move_left(c->centre);
+    while (c->centre < hi) E.move_right(c->centre);
+    c->dir = 1;
+    E.orth_verify();
+}
+
 mpdo_status guard(mpdo_ctx c) {
     if (!c) return MPDO_E_ARG;
     if (c->poisoned) {
@@ -1423,6 +1595,8 @@ mpdo_status mpdo_destroy(mpdo_ctx c) {
     if (!c) return MPDO_E_ARG;
     if (c->st || c->ready) (void)hipStreamSynchronize(c->st);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->xg) (void)hipFree(c->xg);
+    if (c->xgT) (void)hipFree(c->xgT);
     if (c->hbuf) (void)hipHostFree(c->hbuf);
     if (c->hint) (void)hipHostFree(c->hint);
     delete c;
@@ -1565,6 +1739,42 @@ mpdo_status mpdo_apply_gate_kraus(mpdo_ctx c, int site, int n_kraus, const doubl
         return MPDO_E_ARG;
     }
     return gate_common(c, site, 1, kraus, (size_t)n_kraus * dim * dim * 2, n_kraus, c->chi, info);
+}
+
+mpdo_status mpdo_apply_gate_crosstalk(mpdo_ctx c, int site, int rydberg, const double* u4, mpdo_trunc_info* info) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready) {
+        c->err = "state not initialised";
+        return MPDO_E_STATE;
+    }
+    const int dim = c->d * c->d;
+    if (site < 0 || site > c->N - 2 || rydberg < 0 || rydberg >= c->d || !u4) {
+        c->err = "bad site, Rydberg level or null unitaries";
+        return MPDO_E_ARG;
+    }
+    if (!all_finite(u4, (size_t)4 * dim * dim * 2)) {
+        c->err = "non-finite unitary entry";
+        return MPDO_E_ARG;
+    }
+    for (int q = 0; q < 4; ++q)
+        if (cptp_defect(u4 + (size_t)q * dim * dim * 2, 1, dim) > 1e-10) {
+            c->err = "crosstalk pair gate is not unitary";
+            return MPDO_E_ARG;
+        }
+    try {
+        if (c->fp32) {
+            Engine<float> E(*c, c->sf);
+            do_crosstalk<float>(c, E, site, rydberg, u4, info);
+        } else {
+            Engine<double> E(*c, c->sd);
+            do_crosstalk<double>(c, E, site, rydberg, u4, info);
+        }
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
 }
 
 mpdo_status mpdo_apply_channel(mpdo_ctx c, int site, int n_kraus, const double* kraus) {

@@ -60,6 +60,20 @@ hipError_t scale_cols(hipStream_t s, CView<T> X, int M, int N, const double* f);
 template <typename T>
 hipError_t fill_random(hipStream_t s, CView<T> X, int M, int N, uint64_t seed);
 
+// Class of each vectorised physical index eta (D2 <= 16 entries), passed by value.
+struct EtaClass {
+    static constexpr int MAXD2 = 16;
+    int c[MAXD2];
+};
+
+// Bond enlargement of a cl x D2 x cr site tensor X by the class of its physical index (the
+// crosstalk gate's control bonds), into Y (device, (ncls cl or cl) x D2 x (cr or ncls cr)):
+// mode 0 / 3 split the right / left bond into ncls blocks, each keeping the entries of its
+// class; mode 1 / 2 replicate the left / right bond ncls times.  Y must not alias X.
+template <typename T>
+hipError_t class_expand(hipStream_t s, const T* X, int cl, int D2, int cr, int mode, int ncls, const EtaClass& cls,
+                        T* Y);
+
 // Purity-Preserving Truncation on the kept spectrum (fac[j] = Lambda~_j / Lambda'_j).
 // out: [0] tr before, [1] xi before, [2] theta, [3] feasible, [4] degenerate sigma, [5] x,
 //      [6] max |Im T'L'|, [7] |Lambda'|^2, [8] T'.Lambda', [9] sum Im, [10] tr after,

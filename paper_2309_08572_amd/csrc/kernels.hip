@@ -310,6 +310,42 @@ __device__ inline uint64_t splitmix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+// Bond enlargement for the crosstalk gate.  X: cl x D2 x cr site tensor; the vectorised physical
+// index eta has class cls.c[eta] in [0, ncls).  Y (complex, T):
+//   mode 0: cl x D2 x (ncls cr), Y[l][eta][a cr + r] = X[l][eta][r] if a == class(eta), else 0
+//   mode 1: (ncls cl) x D2 x cr, Y[a cl + l][eta][r] = X[l][eta][r]
+//   mode 2: cl x D2 x (ncls cr), Y[l][eta][a cr + r] = X[l][eta][r]
+//   mode 3: (ncls cl) x D2 x cr, Y[a cl + l][eta][r] = X[l][eta][r] if a == class(eta), else 0
+template <typename T>
+__global__ void class_expand_kernel(const T* __restrict__ X, int cl, int D2, int cr, int mode, int ncls, EtaClass cls,
+                                    T* __restrict__ Y) {
+    const long tot = (long)ncls * cl * D2 * cr;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    int l, eta, r, a;
+    if (mode == 0 || mode == 2) {
+        const long wide = (long)ncls * cr;
+        const long q = idx / wide;
+        const int rr = (int)(idx - q * wide);
+        l = (int)(q / D2);
+        eta = (int)(q - (long)l * D2);
+        a = rr / cr;
+        r = rr - a * cr;
+    } else {
+        const long per = (long)D2 * cr;
+        const long ll = idx / per;
+        const int rem = (int)(idx - ll * per);
+        a = (int)(ll / cl);
+        l = (int)(ll - (long)a * cl);
+        eta = rem / cr;
+        r = rem - eta * cr;
+    }
+    const bool keep = (mode == 1 || mode == 2) || cls.c[eta] == a;
+    const long src = 2 * (((long)l * D2 + eta) * cr + r);
+    Y[2 * idx] = keep ? X[src] : (T)0;
+    Y[2 * idx + 1] = keep ? X[src + 1] : (T)0;
+}
+
 template <typename T>
 __global__ void fill_random_kernel(CView<T> X, int M, int N, uint64_t seed) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -661,6 +697,16 @@ hipError_t spectrum_cut(hipStream_t s, const double* lam, int n, int level, doub
 }
 
 template <typename T>
+hipError_t class_expand(hipStream_t s, const T* X, int cl, int D2, int cr, int mode, int ncls, const EtaClass& cls,
+                        T* Y) {
+    if (D2 > EtaClass::MAXD2 || mode < 0 || mode > 3 || ncls < 1) return hipErrorInvalidValue;
+    const long tot = (long)ncls * cl * D2 * cr;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(class_expand_kernel<T>, dim3(blocks_for(tot)), dim3(256), 0, s, X, cl, D2, cr, mode, ncls, cls, Y);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t fill_random(hipStream_t s, CView<T> X, int M, int N, uint64_t seed) {
     if (M <= 0 || N <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_random_kernel<T>, dim3(blocks_for((long)M * N)), dim3(256), 0, s, X, M, N, seed);
@@ -737,6 +783,7 @@ hipError_t bilinear(hipStream_t s, const T* L, int n, const double* y, double* o
     template hipError_t bilinear<T>(hipStream_t, const T*, int, const double*, double*);                         \
     template hipError_t scale_cols<T>(hipStream_t, CView<T>, int, int, const double*);                          \
     template hipError_t fill_random<T>(hipStream_t, CView<T>, int, int, uint64_t);                               \
+    template hipError_t class_expand<T>(hipStream_t, const T*, int, int, int, int, int, const EtaClass&, T*);     \
     template hipError_t scale_rows<T>(hipStream_t, T*, int, int, long, const double*);                          \
     template hipError_t gemv_left<T>(hipStream_t, CView<T>, int, int, const double*, double*);                  \
     template hipError_t row_norms<T>(hipStream_t, CView<T>, int, int, double*);

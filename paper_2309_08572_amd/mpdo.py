@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_
 
 EXPORTS = (
     "mpdo_create", "mpdo_destroy", "mpdo_workspace_bytes", "mpdo_bind_workspace",
-    "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus",
+    "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus", "mpdo_apply_gate_crosstalk",
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_expect2", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
     "mpdo_profile_enable", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
@@ -95,6 +95,7 @@ def load_library() -> C.CDLL:
     lib.mpdo_init_product_state.argtypes = [ctx, dp]
     lib.mpdo_apply_gate.argtypes = [ctx, C.c_int, dp, C.POINTER(TruncInfo)]
     lib.mpdo_apply_gate_kraus.argtypes = [ctx, C.c_int, C.c_int, dp, C.POINTER(TruncInfo)]
+    lib.mpdo_apply_gate_crosstalk.argtypes = [ctx, C.c_int, C.c_int, dp, C.POINTER(TruncInfo)]
     lib.mpdo_apply_channel.argtypes = [ctx, C.c_int, C.c_int, dp]
     lib.mpdo_truncate.argtypes = [ctx, C.c_int, C.c_int, C.POINTER(TruncInfo)]
     lib.mpdo_expect.argtypes = [ctx, C.c_int, ip, ip, dp, C.c_int, dp]
@@ -186,6 +187,18 @@ class MPDO:
         ti = TruncInfo()
         self._check(self.lib.mpdo_apply_gate_kraus(self.ctx, site, K.shape[0], _dptr(K),
                                                    C.byref(ti) if info else None))
+        return ti.as_dict() if info else None
+
+    def apply_gate_crosstalk(self, site: int, rydberg: int, u4, info: bool = False):
+        """Pair gate with nearest-neighbour Rydberg crosstalk: u4[a + 2b] is the pair unitary
+        with the detunings shifted by the blockade when neighbour site-1 (a) / site+2 (b) is
+        in the Rydberg level."""
+        U = _cplx(np.stack([np.asarray(u) for u in u4]))
+        if U.shape[0] != 4:
+            raise ValueError("four pair unitaries expected")
+        ti = TruncInfo()
+        self._check(self.lib.mpdo_apply_gate_crosstalk(self.ctx, site, rydberg, _dptr(U),
+                                                       C.byref(ti) if info else None))
         return ti.as_dict() if info else None
 
     def apply_channel(self, site: int, kraus: Iterable[np.ndarray]):

@@ -1,0 +1,163 @@
+"""GPU parity of the crosstalk gate (mpdo_apply_gate_crosstalk, Sec. II "MPO form of the noisy
+CZ gate with crosstalk") against the dense oracle, through the C ABI.
+
+Seeded random noisy states (two-atom Kraus maps and single-atom channels) on short chains,
+crosstalk gates with four random pair unitaries at both chain ends and in the middle, then the
+density matrix contracted from the GPU site tensors is compared entrywise with the oracle's
+dense density matrix.  The gate is exact (its pair is split without a cut), so the MPO result
+must equal the exact one: FP64 to 1e-10 of max|rho|, FP32 to 1e-5.  The sequences end with gates
+that touch every atom, so no queued channel is left outside the site tensors.
+"""
+import numpy as np
+import pytest
+
+from oracle import crosstalk, dense
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08572_amd import mpdo
+    mpdo.load_library()
+    return mpdo
+
+
+def _unitary(rng, n):
+    z = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _kraus2(rng, d):
+    """a random two-atom channel: a unitary mixed with a dephased copy"""
+    V = _unitary(rng, d * d)
+    p = 0.2
+    Z = np.diag(np.exp(2j * np.pi * np.arange(d) / d))
+    return [np.sqrt(1 - p) * V, np.sqrt(p) * np.kron(Z, np.eye(d)) @ V]
+
+
+def _kraus1(rng, d):
+    V = _unitary(rng, d)
+    g = 0.1
+    K1 = np.zeros((d, d), dtype=np.complex128)
+    K1[0, 1] = np.sqrt(g)
+    K0 = np.eye(d, dtype=np.complex128)
+    K0[1, 1] = np.sqrt(1 - g)
+    return [K0 @ V, K1 @ V]
+
+
+def _rho0(rng, d):
+    z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    r = z @ z.conj().T + 0.5 * np.eye(d)
+    return r / np.trace(r)
+
+
+def _dense_from_sites(m, n, d):
+    v = np.ones((1, 1), dtype=np.complex128)
+    for j in range(n):
+        A = m.get_site(j)                      # cl x D2 x cr
+        cl, D2, cr = A.shape
+        v = (v @ A.reshape(cl, D2 * cr)).reshape(-1, cr)
+    t = v.reshape((d, d) * n)                  # (sigma_0, sigma'_0, sigma_1, sigma'_1, ...)
+    t = np.transpose(t, list(range(0, 2 * n, 2)) + list(range(1, 2 * n, 2)))
+    return t.reshape(d ** n, d ** n)
+
+
+def _run(mpdo, seq, n, d, ryd, chi, precision, seed):
+    rng = np.random.default_rng(seed)
+    rhos = [_rho0(rng, d) for _ in range(n)]
+    dm = dense.DenseRho(rhos)
+    m = mpdo.MPDO(n, d, chi, precision=precision)
+    m.init_product_state(rhos)
+    for op, site in seq:
+        if op == "g":
+            K = _kraus2(rng, d)
+            dm.apply_kraus(K, (site, site + 1))
+            m.apply_gate_kraus(site, K)
+        elif op == "c":
+            K = _kraus1(rng, d)
+            dm.apply_kraus(K, (site,))
+            m.apply_channel(site, K)
+        else:
+            u4 = [_unitary(rng, d * d) for _ in range(4)]
+            crosstalk.apply_crosstalk(dm, site, u4, ryd)
+            m.apply_gate_crosstalk(site, ryd, u4)
+    got = _dense_from_sites(m, n, d)
+    bonds = m.bond_dims()
+    m.close()
+    return got, dm.rho, bonds
+
+
+SEQ5 = [("g", 0), ("g", 2), ("c", 4), ("c", 1), ("g", 1), ("g", 3), ("c", 0), ("c", 2), ("c", 3),
+        ("x", 0), ("x", 2), ("x", 3), ("c", 1), ("c", 4), ("x", 1), ("g", 3)]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_crosstalk_matches_dense_oracle_d2(precision, tol):
+    mpdo = _gpu()
+    prec = mpdo.MPDO_FP64 if precision == "fp64" else mpdo.MPDO_FP32
+    print(f"[gpu] crosstalk N=5 d=2 chi=256 {precision}", flush=True)
+    got, ref, bonds = _run(mpdo, SEQ5, 5, 2, 1, 256, prec, seed=11)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"[gpu] max |rho - rho_oracle| / max|rho| = {err:.2e}, bonds {bonds}", flush=True)
+    assert err <= tol
+    assert max(bonds) <= 16   # the enlarged bonds are compressed back to the exact ranks
+
+
+def test_crosstalk_matches_dense_oracle_d3_middle_pair():
+    mpdo = _gpu()
+    seq = [("g", 0), ("g", 2), ("c", 1), ("c", 3), ("g", 1), ("c", 0), ("c", 2), ("x", 1), ("c", 3),
+           ("x", 1), ("g", 0), ("g", 2)]
+    print("[gpu] crosstalk N=4 d=3 chi=324 fp64", flush=True)
+    got, ref, bonds = _run(mpdo, seq, 4, 3, 2, 324, mpdo.MPDO_FP64, seed=7)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"[gpu] max |rho - rho_oracle| / max|rho| = {err:.2e}, bonds {bonds}", flush=True)
+    assert err <= 1e-10
+
+
+def test_equal_pair_gates_give_the_plain_two_site_gate():
+    mpdo = _gpu()
+    rng = np.random.default_rng(2)
+    d, n = 3, 4
+    rhos = [_rho0(rng, d) for _ in range(n)]
+    V = _unitary(rng, d * d)
+    outs = []
+    for use_x in (False, True):
+        m = mpdo.MPDO(n, d, 324, precision=mpdo.MPDO_FP64)
+        m.init_product_state(rhos)
+        r2 = np.random.default_rng(9)
+        for s_ in (0, 2, 1):
+            m.apply_gate_kraus(s_, _kraus2(r2, d))
+        if use_x:
+            m.apply_gate_crosstalk(1, 2, [V] * 4)
+        else:
+            m.apply_gate_kraus(1, [V])
+        m.apply_gate_kraus(0, [np.eye(d * d)])
+        m.apply_gate_kraus(2, [np.eye(d * d)])
+        outs.append(_dense_from_sites(m, n, d))
+        m.close()
+    err = np.abs(outs[0] - outs[1]).max() / np.abs(outs[0]).max()
+    print(f"[gpu] crosstalk with equal gates vs plain gate: {err:.2e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_pair_that_does_not_fit_chi_max_is_rejected():
+    mpdo = _gpu()
+    rng = np.random.default_rng(4)
+    d, n = 3, 4
+    m = mpdo.MPDO(n, d, 128, precision=mpdo.MPDO_FP64)
+    m.init_product_state([_rho0(rng, d) for _ in range(n)])
+    for s_ in (0, 2, 1):
+        m.apply_gate_kraus(s_, _kraus2(rng, d))
+    print(f"[gpu] bonds {m.bond_dims()}: enlarged pair 36 x 9 x 9 x 36 needs chi_max >= 324", flush=True)
+    assert m.bond_dims() == [9, 81, 9]
+    V = _unitary(rng, d * d)
+    with pytest.raises(mpdo.MpdoError):
+        m.apply_gate_crosstalk(1, 2, [V] * 4)
+    # the context is still usable after the rejected call
+    m.apply_gate_kraus(1, [V])
+    assert abs(m.trace() - 1.0) <= 1e-10
+    m.close()
