@@ -119,3 +119,54 @@ def test_definite_neighbour_classes_select_one_pair_gate():
             crosstalk.apply_crosstalk(dm, 1, us, ryd)
             expect = np.kron(np.kron(nl, us[a + 2 * b] @ rho_pair @ us[a + 2 * b].conj().T), nr)
             assert np.abs(dm.rho - expect).max() <= 1e-13, (a, b)
+
+
+def _rand_state(rng, d, n):
+    out = []
+    for _ in range(n):
+        z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+        r = z @ z.conj().T + 0.5 * np.eye(d)
+        out.append(r / np.trace(r))
+    return out
+
+
+def _unit(rng, k):
+    return np.linalg.qr(rng.normal(size=(k, k)) + 1j * rng.normal(size=(k, k)))[0]
+
+
+def test_mpo_form_equals_dense_when_nothing_is_cut():
+    from oracle import channels, mpo
+    rng = np.random.default_rng(0)
+    d, n = 2, 5
+    rhos = _rand_state(rng, d, n)
+    dm, m = dense.DenseRho(rhos), mpo.MPO(rhos, chi=64)
+    for s_ in (0, 2, 1, 3):
+        V = _unit(rng, d * d)
+        dm.apply_kraus([V], (s_, s_ + 1))
+        m.apply_2site(s_, channels.superop_2site([V], d))
+    for s_ in (0, 1, 2, 3):
+        u = [_unit(rng, d * d) for _ in range(4)]
+        crosstalk.apply_crosstalk(dm, s_, u, 1)
+        crosstalk.apply_crosstalk_mpo(m, s_, u, 1)
+        assert np.abs(m.to_dense() - dm.rho).max() <= 1e-13, s_
+
+
+def test_mpo_form_cut_keeps_xi_with_ppt():
+    """PPT keeps xi = tr(rho^2) / tr(rho)^2 through the cut (Eq. (ppt)); a plain cut does not"""
+    from oracle import channels, mpo
+    rng = np.random.default_rng(1)
+    d, n = 2, 6
+    rhos = _rand_state(rng, d, n)
+    for use_ppt in (True, False):
+        r2 = np.random.default_rng(2)
+        m = mpo.MPO(rhos, chi=64, use_ppt=use_ppt)
+        for s_ in (0, 2, 4, 1, 3):
+            m.apply_2site(s_, channels.superop_2site([_unit(r2, d * d)], d))
+        xi0 = m.purity() / abs(m.trace()) ** 2
+        crosstalk.apply_crosstalk_mpo(m, 2, [_unit(r2, d * d) for _ in range(4)], 1, chi=4)
+        assert m.bond_dims()[2] == 4
+        xi1 = m.purity() / abs(m.trace()) ** 2
+        if use_ppt:
+            assert abs(xi1 - xi0) <= 1e-12 * xi0
+        else:
+            assert abs(xi1 - xi0) > 1e-6 * xi0
