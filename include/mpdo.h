@@ -143,15 +143,16 @@ mpdo_status mpdo_apply_gate_kraus(mpdo_ctx ctx, int site, int n_kraus, const dou
  * d^2 x d^2 complex (host, index sigma_site*d + sigma_{site+1}), u4[a + 2b] being the pulse
  * with the detunings of atoms site and site+1 shifted by a*B and b*B.  At an end of the chain
  * the missing neighbour contributes a = 0 (or b = 0) only.  Channels queued on the four atoms
- * act first.  The gate is applied exactly: the neighbour bonds are enlarged four-fold by the
- * neighbours' Rydberg class, the pair's merged tensor receives the gate block by block and is
- * split without a cut (info describes that split), and canonical sweeps over the four atoms
- * compress the three bonds to their Schmidt ranks.  Needs 4 chi_l', 4 chi_r' and
- * D2 * min(4 chi_l', 4 chi_r') within chi_max, chi_l' and chi_r' being the bonds between each
- * neighbour and the pair (factor 1 instead of 4 at a chain end).  The first call allocates
- * 16 D2^4 complex FP64 (plus an FP32 copy in FP32 mode) with hipMalloc, freed by
- * mpdo_destroy.  E_ARG for site outside [0, N-2], rydberg outside [0, d), non-finite or
- * non-unitary (by more than 1e-10) entries, or a pair that does not fit chi_max. */
+ * act first.  The neighbours are class-split on their bonds (the classes of their
+ * vectorised index under the projectors) and orthonormalised class by class into the pair,
+ * so their bonds keep the class and grow at most four-fold; the pair's merged tensor receives
+ * u[a + 2b] (x) conj(u[a' + 2b']) block by block and is split, cut to chi_max and corrected
+ * by PPT like any two-site update (info describes that update); canonical sweeps over the
+ * four atoms then compress the neighbour bonds to their Schmidt ranks.  Needs four times each
+ * neighbour bond within chi_max (one time at a chain end).  The first call allocates 16 D2^4
+ * complex FP64 (plus an FP32 copy in FP32 mode) with hipMalloc, freed by mpdo_destroy.  E_ARG
+ * for site outside [0, N-2], rydberg outside [0, d), non-finite or non-unitary (by more than
+ * 1e-10) entries, or a neighbour bond whose four-fold exceeds chi_max (nothing is changed). */
 mpdo_status mpdo_apply_gate_crosstalk(mpdo_ctx ctx, int site, int rydberg, const double* u4,
                                       mpdo_trunc_info* info);
 

@@ -248,13 +248,14 @@ struct FoldEntry {
 };
 constexpr int FOLD_CACHE_MAX = 64;
 
-// Two-site map that depends on the classes of the enlarged outer bonds (crosstalk gate): the
-// left bond of the pair is na blocks of c1 (class alpha, block-major), the right bond nb blocks
-// of c3; block (alpha, beta) of theta receives the D2^2 x D2^2 superoperator G[4 alpha + beta]
-// (device, working precision).
+// Two-site map that depends on the classes carried by the pair's outer bonds (crosstalk gate):
+// the left bond is na consecutive blocks, block alpha at offset lo[alpha] with ln[alpha]
+// indices, the right bond nb blocks (ro, rn); block (alpha, beta) of theta receives the
+// D2^2 x D2^2 superoperator G[4 alpha + beta] (device, working precision).
 template <typename T>
 struct BlockGate {
-    int na = 1, nb = 1, c1 = 0, c3 = 0;
+    int na = 1, nb = 1;
+    int lo[4] = {0}, ln[4] = {0}, ro[4] = {0}, rn[4] = {0};
     const T* G[16] = {nullptr};
 };
 
@@ -863,12 +864,13 @@ struct Engine {
             gemm(nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(), V<T>(s.bT1, nR, 1));
             if (bg) {
                 // theta[l][eta eta'][r] as cl blocks of m2 x cr: block (alpha, beta) = rows
-                // l in [alpha c1, (alpha + 1) c1), columns r in [beta c3, (beta + 1) c3)
+                // l in [lo, lo + ln) of alpha, columns r in [ro, ro + rn) of beta
                 for (int a = 0; a < bg->na; ++a)
                     for (int b = 0; b < bg->nb; ++b) {
-                        const long off = 2 * ((long)a * bg->c1 * m2 * cr + (long)b * bg->c3);
-                        gemm(m2, bg->c3, m2, C1(), V<T>((T*)bg->G[4 * a + b], m2, 1), V<T>(s.bT1 + off, cr, 1), C0(),
-                             V<T>(s.bA + off, cr, 1), bg->c1, 0, (long)m2 * cr, (long)m2 * cr);
+                        if (bg->ln[a] <= 0 || bg->rn[b] <= 0) continue;
+                        const long off = 2 * ((long)bg->lo[a] * m2 * cr + (long)bg->ro[b]);
+                        gemm(m2, bg->rn[b], m2, C1(), V<T>((T*)bg->G[4 * a + b], m2, 1), V<T>(s.bT1 + off, cr, 1),
+                             C0(), V<T>(s.bA + off, cr, 1), bg->ln[a], 0, (long)m2 * cr, (long)m2 * cr);
                     }
             } else {
                 load_superop();
@@ -1284,25 +1286,22 @@ void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n
 // neighbours' classes, with block u[a + 2b] (x) conj(u[a' + 2b']).  Steps:
 //  1. the centre moves to the pair; queued maps of the neighbours are applied to their sites,
 //     those of the pair are folded into the blocks;
-//  2. the neighbour bonds are enlarged by the class (site i-1 and i+2 keep each entry only in
-//     its class block, sites i and i+1 are replicated), which represents the same rho exactly;
-//  3. the pair update applies block (alpha, beta) to its part of theta and splits it; theta's
-//     rank bound fits chi_max, so nothing is cut and PPT is the identity;
-//  4. canonical sweeps over i-1 .. i+2 orthonormalise the enlarged sites, compressing the three
-//     bonds to their Schmidt ranks (range bases; nothing above the rounding floor is cut).
-// The gate is therefore exact; it needs the enlarged bonds (4x) and theta's rank bound
-// min(cl D2, D2 cr) within chi_max.
+//  2. each neighbour is split on its bond by the class of its physical index and
+//     orthonormalised class by class; the factors go into the pair, so the pair's outer bonds
+//     carry the class while the neighbours are isometries;
+//  3. the pair update applies block (alpha, beta) to its part of theta; theta is then rho's
+//     coefficient matrix in orthonormal bases, so the cut to chi_max and PPT are those of an
+//     ordinary update;
+//  4. canonical sweeps over i-1 .. i+2 compress the neighbour bonds to their Schmidt ranks
+//     (range bases; nothing above the rounding floor is cut).
+// The class-split neighbour bonds (4x) must fit chi_max.
 template <typename T>
 void do_crosstalk(mpdo_ctx c, Engine<T>& E, int i, int ryd, const double* u4, mpdo_trunc_info* info) {
     const int d = c->d, D2 = c->D2, m2 = D2 * D2, N = c->N;
     const bool left = i >= 1, right = i + 2 <= N - 1;
     const int na = left ? 4 : 1, nb = right ? 4 : 1;
-    // In the enlarged form the pair's middle bond is not rho's Schmidt cut (the class sums over
-    // the neighbour bonds lie outside theta), so theta is split without a cut: its rank bound
-    // min(cl D2, D2 cr) must fit chi_max as well as the enlarged bonds themselves.
-    const long cl_x = (long)na * c->dims[i], cr_x = (long)nb * c->dims[i + 2];
-    if (cl_x > c->chi || cr_x > c->chi || std::min(cl_x, cr_x) * D2 > c->chi)
-        throw Fail{MPDO_E_ARG, "crosstalk gate: the enlarged pair does not fit chi_max"};
+    if ((long)na * c->dims[i] > c->chi || (long)nb * c->dims[i + 2] > c->chi)
+        throw Fail{MPDO_E_ARG, "crosstalk gate: four times a neighbour bond exceeds chi_max"};
     EtaClass cls;
     for (int e = 0; e < EtaClass::MAXD2; ++e) cls.c[e] = 0;
     for (int e = 0; e < D2; ++e) cls.c[e] = ((e / d) == ryd ? 1 : 0) + ((e % d) == ryd ? 2 : 0);
@@ -1360,27 +1359,81 @@ void do_crosstalk(mpdo_ctx c, Engine<T>& E, int i, int ryd, const double* u4, mp
         set_ovec(c, i);
         set_ovec(c, i + 1);
     }
-    // 2. enlarge the neighbour bonds by class
-    bg.c1 = c->dims[i];
-    bg.c3 = c->dims[i + 2];
+    // 2. absorb the neighbours class by class.  Left: the class-split site i-1 (its bond
+    //    (alpha, r)) has column blocks on disjoint physical rows, so orthonormalising each block
+    //    alone, F_alpha = Q_alpha K_alpha, gives a left isometry [Q_0 .. Q_3] whose bond keeps
+    //    the class; K_alpha goes into site i (whose left bond was the replicated (alpha, l)).
+    //    Right: the same with the rows of the class-split site i+2.
+    const int c1 = c->dims[i], c3 = c->dims[i + 2];
     if (left) {
-        E.expand(i - 1, 0, 4, cls);
-        E.expand(i, 1, 4, cls);
-        c->dims[i] *= 4;
+        const int c0 = c->dims[i - 1], cm = c->dims[i + 1];
+        const int n = c0 * D2, w = D2 * cm;
+        HIPCHK(class_expand<T>(c->st, (T*)c->site[i - 1], c0, D2, c1, 0, 4, cls, E.s.bR));
+        T* tq = E.s.bU2;               // the Q blocks side by side, ld 4 c1
+        T* nnext = (T*)c->spare[1];    // new site i: q x w, block alpha at rows [oa, oa + qa)
+        int q = 0;
+        for (int al = 0; al < 4; ++al) {
+            const int qb = E.orth2(V<T>(E.s.bR + 2 * (long)al * c1, 4L * c1, 1), n, c1, E.s.bQ, E.s.bK);
+            bg.lo[al] = q;
+            bg.ln[al] = qb;
+            if (qb > 0) {
+                HIPCHK((geam<T, T>(c->st, n, qb, C1(), V<T>(E.s.bQ, c1, 1), C0(), V<T>(tq + 2 * (long)q, 4L * c1, 1))));
+                E.gemm(qb, w, c1, C1(), V<T>(E.s.bK, c1, 1), V<T>((T*)c->site[i], w, 1), C0(),
+                       V<T>(nnext + 2 * (long)q * w, w, 1));
+            }
+            q += qb;
+        }
+        if (q <= 0) throw Fail{MPDO_E_NUMERIC, "crosstalk: left neighbour vanished"};
+        HIPCHK((geam<T, T>(c->st, n, q, C1(), V<T>(tq, 4L * c1, 1), C0(), V<T>((T*)c->spare[0], q, 1))));
+        E.swap_site(i - 1, 0);
+        E.swap_site(i, 1);
+        c->dims[i] = q;
+        E.site_changed(i - 1);
+        E.site_changed(i);
+    } else {
+        bg.lo[0] = 0;
+        bg.ln[0] = c1;
     }
     if (right) {
-        E.expand(i + 1, 2, 4, cls);
-        E.expand(i + 2, 3, 4, cls);
-        c->dims[i + 2] *= 4;
+        const int c5 = c->dims[i + 3];
+        const int n = D2 * c5;
+        const int h = c->dims[i + 1] * D2;   // site i+1 as an h x c3 matrix
+        // site i+2 class-split on its left bond: rows (beta, l), l < c3, as a (4 c3) x n matrix
+        HIPCHK(class_expand<T>(c->st, (T*)c->site[i + 2], c3, D2, c5, 3, 4, cls, E.s.bR));
+        T* nsite = (T*)c->spare[0];   // new site i+2: p x n, block beta at rows [ob, ob + pb)
+        T* tk = E.s.bU2;              // new site i+1 blocks side by side, ld 4 c3
+        int p = 0;
+        for (int be = 0; be < 4; ++be) {
+            // G_beta^H = Q K (Q: n x pb, K: pb x c3), so G_beta = K^H Q^H
+            const int pbk = E.orth2(adj(V<T>(E.s.bR + 2 * (long)be * c3 * n, n, 1)), n, c3, E.s.bQ, E.s.bK);
+            bg.ro[be] = p;
+            bg.rn[be] = pbk;
+            if (pbk > 0) {
+                HIPCHK((geam<T, T>(c->st, pbk, n, C1(), adj(V<T>(E.s.bQ, c3, 1)), C0(),
+                                   V<T>(nsite + 2 * (long)p * n, n, 1))));
+                E.gemm(h, pbk, c3, C1(), V<T>((T*)c->site[i + 1], c3, 1), adj(V<T>(E.s.bK, c3, 1)), C0(),
+                       V<T>(tk + 2 * (long)p, 4L * c3, 1));
+            }
+            p += pbk;
+        }
+        if (p <= 0) throw Fail{MPDO_E_NUMERIC, "crosstalk: right neighbour vanished"};
+        HIPCHK((geam<T, T>(c->st, h, p, C1(), V<T>(tk, 4L * c3, 1), C0(), V<T>((T*)c->spare[1], p, 1))));
+        E.swap_site(i + 2, 0);
+        E.swap_site(i + 1, 1);
+        c->dims[i + 2] = p;
+        E.site_changed(i + 1);
+        E.site_changed(i + 2);
+    } else {
+        bg.ro[0] = 0;
+        bg.rn[0] = c3;
     }
-    c->lvalid = std::min(c->lvalid, std::max(0, i - 1));
-    c->rvalid = std::max(c->rvalid, std::min(N, i + 3));
-    // 3. the pair update with the block superoperators
+    // 3. the pair update with the block superoperators: the outer sites are isometries whose
+    //    bonds carry the classes, so theta is rho's coefficient matrix in orthonormal bases and
+    //    the cut to chi_max and PPT are those of an ordinary update
     E.update(i, nullptr, c->chi, info, &bg);
-    // 4. canonical form over lo .. hi = i-1 .. i+2.  A bond shrinks to its Schmidt rank when
-    //    the centre crosses it with both sides isometric: sweep to hi, back to lo (every site
-    //    right of lo, the enlarged i+2 included, becomes a right isometry), then to hi again,
-    //    where each move orthonormalises a site whose left side is isometric.
+    // 4. canonical form over lo .. hi = i-1 .. i+2, compressing the absorbed bonds to their
+    //    Schmidt ranks: sweep to hi, back to lo, then to hi again (each move orthonormalises a
+    //    site whose far side is already isometric)
     const int lo = left ? i - 1 : i, hi = right ? i + 2 : i + 1;
     while (c->centre < hi) E.move_right(c->centre);
     while (c->centre > lo) E.move_left(c->centre);

@@ -4,8 +4,9 @@ CZ gate with crosstalk") against the dense oracle, through the C ABI.
 Seeded random noisy states (two-atom Kraus maps and single-atom channels) on short chains,
 crosstalk gates with four random pair unitaries at both chain ends and in the middle, then the
 density matrix contracted from the GPU site tensors is compared entrywise with the oracle's
-dense density matrix.  The gate is exact (its pair is split without a cut), so the MPO result
-must equal the exact one: FP64 to 1e-10 of max|rho|, FP32 to 1e-5.  The sequences end with gates
+dense density matrix.  chi_max leaves the pair's cut empty there, so the MPO result must equal
+the exact one: FP64 to 1e-10 of max|rho|, FP32 to 1e-5.  A truncating case (cut to chi = 8 with
+PPT) is compared with the oracle's MPO form of the gate to 1e-10.  The sequences end with gates
 that touch every atom, so no queued channel is left outside the site tensors.
 """
 import numpy as np
@@ -152,12 +153,45 @@ def test_pair_that_does_not_fit_chi_max_is_rejected():
     m.init_product_state([_rho0(rng, d) for _ in range(n)])
     for s_ in (0, 2, 1):
         m.apply_gate_kraus(s_, _kraus2(rng, d))
-    print(f"[gpu] bonds {m.bond_dims()}: enlarged pair 36 x 9 x 9 x 36 needs chi_max >= 324", flush=True)
+    print(f"[gpu] bonds {m.bond_dims()}: pair (0, 1) would enlarge bond (1, 2) to 4 x 81 > 128", flush=True)
     assert m.bond_dims() == [9, 81, 9]
     V = _unitary(rng, d * d)
     with pytest.raises(mpdo.MpdoError):
-        m.apply_gate_crosstalk(1, 2, [V] * 4)
-    # the context is still usable after the rejected call
-    m.apply_gate_kraus(1, [V])
+        m.apply_gate_crosstalk(0, 2, [V] * 4)
+    # the context is still usable after the rejected call, and the middle pair fits
+    m.apply_gate_crosstalk(1, 2, [V] * 4)
     assert abs(m.trace() - 1.0) <= 1e-10
+    m.close()
+
+
+def test_truncating_crosstalk_matches_the_mpo_oracle():
+    """chi_max = 8 on six atoms: the pair's middle bond is cut to 8 with PPT; the oracle cuts the
+    same Schmidt decomposition of the contracted four-atom region (oracle.crosstalk.
+    apply_crosstalk_mpo), so the two density matrices must agree to 1e-10."""
+    mpdo = _gpu()
+    from oracle import channels, mpo
+    rng = np.random.default_rng(21)
+    d, n, chi = 2, 6, 8
+    rhos = [_rho0(rng, d) for _ in range(n)]
+    om = mpo.MPO(rhos, chi=chi)
+    m = mpdo.MPDO(n, d, chi, precision=mpdo.MPDO_FP64)
+    m.init_product_state(rhos)
+    for s_ in (0, 2, 4):
+        K = _kraus2(rng, d)
+        om.apply_2site(s_, channels.superop_2site(K, d))
+        m.apply_gate_kraus(s_, K)
+    for s_ in (1, 3):
+        K = _kraus1(rng, d)
+        om.apply_1site(s_, channels.superop_1site(K))
+        m.apply_channel(s_, K)
+    u4 = [_unitary(rng, d * d) for _ in range(4)]
+    crosstalk.apply_crosstalk_mpo(om, 2, u4, 1)
+    info = m.apply_gate_crosstalk(2, 1, u4, info=True)
+    print(f"[gpu] crosstalk cut: kept {info['kept']} discarded weight {info['discarded_weight']:.3e}, "
+          f"bonds gpu {m.bond_dims()} oracle {om.bond_dims()}", flush=True)
+    assert info["kept"] == chi and info["discarded_weight"] > 1e-6
+    got, ref = _dense_from_sites(m, n, d), om.to_dense()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"[gpu] max |rho - rho_oracle| / max|rho| = {err:.2e}", flush=True)
+    assert err <= 1e-10
     m.close()
