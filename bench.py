@@ -194,6 +194,53 @@ def _pulse_gate(n_steps: int) -> dict:
             "steps": n_steps, "ms_per_channel": 1e3 * t, "us_per_step": 1e6 * t / n_steps}
 
 
+def _crosstalk(layers: int) -> dict:
+    """The crosstalk gate on the benchmark chain (N=100, d=4, chi_max=512, FP64): every Ising
+    block of the first `layers` QAOA layers is applied as a crosstalk gate whose four pair
+    unitaries add a phase phi (a n_i + b n_{i+1}) on the Rydberg level 2 (n = |2><2|) of the
+    driven atoms when the left (a) or right (b) neighbour is in level 2, the blockade's detuning
+    shift over the block; the block's leak is queued on its two atoms, the mixer and the
+    single-atom noise follow as in the benchmark.  The first layer is untimed (it also
+    allocates the gate's block buffers); the others are timed."""
+    import numpy as np
+    from paper_2309_08572_amd import circuits
+    from paper_2309_08572_amd.mpdo import MPDO, MPDO_FP64
+    from workloads import config_m3
+    spec = config_m3(0)
+    n, d, phi = spec.n, spec.d, 0.3
+    nr = np.zeros(d)
+    nr[2] = 1.0
+    m = MPDO(n, d, spec.chi, precision=MPDO_FP64)
+    m.init_product_state([circuits.plus_rho(d)] * n)
+    timed_s, timed_gates = 0.0, 0
+    for k in range(min(layers, spec.p)):
+        zz = circuits.zz_gate(spec.gamma[k], d)
+        u4 = [np.diag(np.exp(-1j * phi * (a * np.kron(nr, np.ones(d)) + b * np.kron(np.ones(d), nr)))) @ zz
+              for b in (0, 1) for a in (0, 1)]
+        lk = circuits.leak_kraus(spec.p_leak, d)
+        t0 = time.perf_counter()
+        for i in circuits.bond_order(n):
+            m.apply_gate_crosstalk(i, 2, u4)
+            m.apply_channel(i, lk)
+            m.apply_channel(i + 1, lk)
+        for j in range(n):
+            m.apply_channel(j, [circuits.x_rotation(spec.beta[k], d)])
+            m.apply_channel(j, circuits.dephasing_kraus(spec.p_deph, d))
+            m.apply_channel(j, circuits.decay_kraus(spec.p_decay, d))
+        tr = m.trace()
+        if k > 0:
+            timed_s += time.perf_counter() - t0
+            timed_gates += n - 1
+    bonds = m.bond_dims()
+    m.close()
+    return {"workload": "noisy QAOA chain N=100, d=4, chi_max=512, Ising blocks as crosstalk gates "
+                        "(Rydberg level 2, phase 0.3 per neighbour class), FP64",
+            "timed_layers": max(0, min(layers, spec.p) - 1), "crosstalk_updates": timed_gates,
+            "updates_per_s": timed_gates / timed_s if timed_s > 0 else 0.0,
+            "ms_per_update": 1e3 * timed_s / timed_gates if timed_gates else 0.0,
+            "max_bond": max(bonds), "trace": [tr.real, tr.imag]}
+
+
 PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp64_vector": 78.6, "hbm_gbs": 8000.0}
 
 
@@ -276,6 +323,8 @@ def main() -> int:
     ap.add_argument("--saturated-layers", type=int, default=8,
                     help="at most this many untimed layers before the saturated chi=512 updates are timed "
                          "(0: skip that leg)")
+    ap.add_argument("--crosstalk-layers", type=int, default=2,
+                    help="layers of the crosstalk-gate leg (the first is untimed); 0 skips it")
     ap.add_argument("--pulse-steps", type=int, default=20000,
                     help="also time the pulse-level CZ gate builder with this many steps (0: skip)")
     args = ap.parse_args()
@@ -360,6 +409,11 @@ def main() -> int:
         out["pulse_gate"] = _pulse_gate(args.pulse_steps)
     if args.saturated_layers > 0:
         out["saturated"] = _saturated(args.saturated_layers, run)
+    if args.crosstalk_layers > 0:
+        try:
+            out["crosstalk"] = _crosstalk(args.crosstalk_layers)
+        except Exception as e:   # a rejected gate (bond too large for chi_max) is reported, not fatal
+            out["crosstalk"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(spec, args.cpu_baseline_seconds)
     print(json.dumps(out))
