@@ -323,7 +323,7 @@ def main() -> int:
     ap.add_argument("--saturated-layers", type=int, default=8,
                     help="at most this many untimed layers before the saturated chi=512 updates are timed "
                          "(0: skip that leg)")
-    ap.add_argument("--crosstalk-layers", type=int, default=2,
+    ap.add_argument("--crosstalk-layers", type=int, default=3,
                     help="layers of the crosstalk-gate leg (the first is untimed); 0 skips it")
     ap.add_argument("--pulse-steps", type=int, default=20000,
                     help="also time the pulse-level CZ gate builder with this many steps (0: skip)")
