@@ -409,7 +409,7 @@ struct Engine {
     // the eigenvectors in T
     void eig(int n) {
         int sw = 0;
-        HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, &sw, c.hint, ps()));
+        HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, &sw, c.hint, ps(), eps()));
         ++eig_calls;
         if (sw >= EIG_MAX_SWEEPS) throw Fail{MPDO_E_NUMERIC, "Jacobi eigensolver did not converge"};
         if (!std::is_same<T, double>::value)
@@ -432,7 +432,7 @@ struct Engine {
         } else if (n <= 64) {
             // one workgroup solves to convergence; its sweep count is read together with the
             // accepted count, in one synchronisation
-            HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, nullptr, c.hint, ps()));
+            HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, nullptr, c.hint, ps(), eps()));
             ++eig_calls;
             if (!std::is_same<T, double>::value)
                 HIPCHK((geam<double, T>(st, n, n, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));

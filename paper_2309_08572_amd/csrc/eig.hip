@@ -193,7 +193,7 @@ __device__ __forceinline__ int pair_index(int P, int Q, int x) {
 // ---------------------------------------------------------------- small matrices
 __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restrict__ H, int ld, int n,
                                                         const double* __restrict__ fro, double tol_rel,
-                                                        int max_sweeps, double* __restrict__ evals,
+                                                        double abs_eps, int max_sweeps, double* __restrict__ evals,
                                                         double* __restrict__ V, int ldv,
                                                         int* __restrict__ sweeps_out) {
     __shared__ PairLds<NS> L;
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restric
         }
     }
     __syncthreads();
-    const int sw = lds_jacobi<NS>(L, np, tol_rel, 2.220446049250313e-16 * fro[0], max_sweeps);
+    const int sw = lds_jacobi<NS>(L, np, tol_rel, abs_eps * fro[0], max_sweeps);
     if (tid < n) {
         const double lam = L.Hr[tid][tid];
         int rk = 0;
@@ -569,7 +569,7 @@ int* eigh_sweep_counter(void* work, int n) {
 }
 
 hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, double* evals, void* work,
-                int max_sweeps, int* sweeps_used, int* host_pinned, ProfSink* prof) {
+                int max_sweeps, int* sweeps_used, int* host_pinned, ProfSink* prof, double input_eps) {
     if (n <= 0) return hipSuccess;
     const double tol_rel = 1e-15;
     char* w = (char*)work;
@@ -587,8 +587,8 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
     hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, H, ldh, n, fro);
     if (n <= NS) {
         if (prof) prof->begin(s, PF_EIG_SMALL);
-        hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(1024), 0, s, H, ldh, n, fro, tol_rel, max_sweeps,
-                           evals, V, ldv, nrot);
+        hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(1024), 0, s, H, ldh, n, fro, tol_rel, input_eps,
+                           max_sweeps, evals, V, ldv, nrot);
         if (prof) prof->end(s, PF_EIG_SMALL, 0.0, 32.0 * n * n);
         if (sweeps_used) {
             hipMemcpyAsync(host_pinned, nrot, sizeof(int), hipMemcpyDeviceToHost, s);
