@@ -294,6 +294,7 @@ struct mpdo_ctx_s {
     void* SdevT = nullptr;        // same in the working precision
     double* xg = nullptr;         // crosstalk block superoperators (16 x D2^4 complex FP64), on first use
     void* xgT = nullptr;          // the same in the working precision (FP32 mode)
+    std::vector<double> xg_src;   // what the blocks in xg were built from (reused when it repeats)
     double* hbuf = nullptr;       // pinned host buffer
     int* hint = nullptr;
 
@@ -1292,7 +1293,7 @@ void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n
 //  3. the pair update applies block (alpha, beta) to its part of theta; theta is then rho's
 //     coefficient matrix in orthonormal bases, so the cut to chi_max and PPT are those of an
 //     ordinary update;
-//  4. canonical sweeps over i-1 .. i+2 compress the neighbour bonds to their Schmidt ranks
+//  4. canonical moves across both neighbour bonds compress them to their Schmidt ranks
 //     (range bases; nothing above the rounding floor is cut).
 // The class-split neighbour bonds (4x) must fit chi_max.
 template <typename T>
@@ -1312,16 +1313,34 @@ void do_crosstalk(mpdo_ctx c, Engine<T>& E, int i, int ryd, const double* u4, mp
         if (c->fp32 && hipMalloc(&c->xgT, 16 * blk * 2 * sizeof(float)) != hipSuccess)
             throw Fail{MPDO_E_NOMEM, "crosstalk blocks"};
     }
-    const zc* U = (const zc*)u4;
-    for (int al = 0; al < na; ++al)
-        for (int be = 0; be < nb; ++be) {
-            const int a = al & 1, ap = al >> 1, b = be & 1, bp = be >> 1;
-            std::vector<zc> S = superop_pair(U + (size_t)(a + 2 * b) * m2, U + (size_t)(ap + 2 * bp) * m2, d);
-            if (!c->pend_id[i] || !c->pend_id[i + 1]) fold_pending(c, i, S);
-            HIPCHK(hipMemcpyAsync(c->xg + 2 * (size_t)(4 * al + be) * blk, S.data(), blk * sizeof(zc),
-                                  hipMemcpyHostToDevice, c->st));
-            HIPCHK(hipStreamSynchronize(c->st));   // S is freed at the end of this iteration
-        }
+    // The blocks depend on the unitaries, the Rydberg level, the chain-end shape and the maps
+    // queued on the pair: the last set stays on the device and is rebuilt only when these differ.
+    std::vector<double> src(u4, u4 + (size_t)4 * m2 * 2);
+    src.push_back(ryd);
+    src.push_back(na);
+    src.push_back(nb);
+    for (int j : {i, i + 1}) {
+        src.push_back(c->pend_id[j]);
+        if (!c->pend_id[j])
+            src.insert(src.end(), (const double*)c->pending[j].data(), (const double*)c->pending[j].data() + 2 * D2 * D2);
+    }
+    if (src != c->xg_src) {
+        const zc* U = (const zc*)u4;
+        std::vector<zc> all(16 * blk, zc(0, 0));
+        for (int al = 0; al < na; ++al)
+            for (int be = 0; be < nb; ++be) {
+                const int a = al & 1, ap = al >> 1, b = be & 1, bp = be >> 1;
+                std::vector<zc> S = superop_pair(U + (size_t)(a + 2 * b) * m2, U + (size_t)(ap + 2 * bp) * m2, d);
+                if (!c->pend_id[i] || !c->pend_id[i + 1]) fold_pending(c, i, S);
+                std::copy(S.begin(), S.end(), all.begin() + (size_t)(4 * al + be) * blk);
+            }
+        c->xg_src.clear();   // a failed upload leaves no stale tag
+        upload(c, c->xg, all.data(), all.size() * sizeof(zc));
+        if (c->fp32)
+            HIPCHK((geam<double, float>(c->st, 16 * m2, m2, C1(), V<double>(c->xg, m2, 1), C0(),
+                                        V<float>((float*)c->xgT, m2, 1))));
+        c->xg_src.swap(src);
+    }
     BlockGate<T> bg;
     bg.na = na;
     bg.nb = nb;
@@ -1331,9 +1350,6 @@ void do_crosstalk(mpdo_ctx c, Engine<T>& E, int i, int ryd, const double* u4, mp
         else
             bg.G[q] = (const T*)(c->xg + 2 * (size_t)q * blk);
     }
-    if (c->fp32)
-        HIPCHK((geam<double, float>(c->st, 16 * m2, m2, C1(), V<double>(c->xg, m2, 1), C0(),
-                                    V<float>((float*)c->xgT, m2, 1))));
     // 1. centre to the pair; queued maps
     if (c->centre < i) c->dir = 1;
     else if (c->centre > i + 1) c->dir = -1;
@@ -1431,14 +1447,22 @@ void do_crosstalk(mpdo_ctx c, Engine<T>& E, int i, int ryd, const double* u4, mp
     //    bonds carry the classes, so theta is rho's coefficient matrix in orthonormal bases and
     //    the cut to chi_max and PPT are those of an ordinary update
     E.update(i, nullptr, c->chi, info, &bg);
-    // 4. canonical form over lo .. hi = i-1 .. i+2, compressing the absorbed bonds to their
-    //    Schmidt ranks: sweep to hi, back to lo, then to hi again (each move orthonormalises a
-    //    site whose far side is already isometric)
-    const int lo = left ? i - 1 : i, hi = right ? i + 2 : i + 1;
-    while (c->centre < hi) E.move_right(c->centre);
-    while (c->centre > lo) E.move_left(c->centre);
-    while (c->centre < hi) E.move_right(c->centre);
-    c->dir = 1;
+    // 4. compress the neighbour bonds to their Schmidt ranks.  After the update the chain is in
+    //    canonical form around the centre (i or i+1; the absorbed neighbours are isometries),
+    //    and a move orthonormalises a site whose far side is isometric: moving to a neighbour
+    //    and back across both neighbour bonds compresses each exactly.  The nearer side first.
+    auto to = [&](int target) {
+        while (c->centre < target) E.move_right(c->centre);
+        while (c->centre > target) E.move_left(c->centre);
+    };
+    const bool right_first = c->centre > i;
+    if (right_first) {
+        if (right) to(i + 2);
+        if (left) to(i - 1);
+    } else {
+        if (left) to(i - 1);
+        if (right) to(i + 2);
+    }
     E.orth_verify();
 }
 
