@@ -264,6 +264,12 @@ enum {
  * stream and clears earlier totals; enable = 0 stops recording (totals are kept). */
 mpdo_status mpdo_profile_enable(mpdo_ctx ctx, int enable);
 
+/* As mpdo_profile_enable(ctx, 1), recording only the families whose bit (1u << f) is set in
+ * family_mask: an event pair costs host time at every launch it brackets, so a measurement of
+ * one family's kernels leaves the rest of the stream as it runs unmeasured.  family_mask = 0
+ * stops recording. */
+mpdo_status mpdo_profile_enable_mask(mpdo_ctx ctx, unsigned family_mask);
+
 /* Totals since the last mpdo_profile_enable(ctx, 1): out[4 f + 0..3] = launches,
  * milliseconds, algorithmic flop and algorithmic bytes of family f, for f < n_families.
  * Synchronises the stream. */

@@ -180,6 +180,7 @@ struct EventProf : public ProfSink {
     std::vector<Rec> recs;
     hipEvent_t cur = nullptr;
     int cur_fam = -1;
+    unsigned mask = ~0u;   // families recorded (bit f)
     hipEvent_t get() {
         if (!pool.empty()) {
             hipEvent_t e = pool.back();
@@ -191,13 +192,15 @@ struct EventProf : public ProfSink {
         return e;
     }
     void begin(hipStream_t s, int fam) override {
+        if (!((mask >> fam) & 1u)) return;
         cur = get();
         cur_fam = fam;
         if (cur) (void)hipEventRecord(cur, s);
     }
     void end(hipStream_t s, int fam, double flop, double bytes) override {
+        if (!((mask >> fam) & 1u) || !cur) return;
         hipEvent_t b = get();
-        if (!cur || !b) return;
+        if (!b) return;
         (void)hipEventRecord(b, s);
         recs.push_back(Rec{cur, b, fam, flop, bytes});
         cur = nullptr;
@@ -2063,6 +2066,21 @@ mpdo_status mpdo_profile_enable(mpdo_ctx c, int enable) {
     } else if (c->prof) {
         c->prof->collect(c->prof_acc);
         c->prof.reset();
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_profile_enable_mask(mpdo_ctx c, unsigned family_mask) {
+    if (!c) return MPDO_E_ARG;
+    if (c->prof) {
+        c->prof->collect(c->prof_acc);
+        c->prof.reset();
+    }
+    if (family_mask) {
+        EventProf* p = new EventProf();
+        p->mask = family_mask;
+        c->prof.reset(p);
+        for (double& x : c->prof_acc) x = 0.0;
     }
     return MPDO_OK;
 }

@@ -25,7 +25,7 @@ EXPORTS = (
     "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus", "mpdo_apply_gate_crosstalk",
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_expect2", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
-    "mpdo_profile_enable", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
+    "mpdo_profile_enable", "mpdo_profile_enable_mask", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
 )
 
 PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other",
@@ -107,6 +107,7 @@ def load_library() -> C.CDLL:
     lib.mpdo_last_error.restype = C.c_char_p
     lib.mpdo_version.restype = C.c_char_p
     lib.mpdo_profile_enable.argtypes = [ctx, C.c_int]
+    lib.mpdo_profile_enable_mask.argtypes = [ctx, C.c_uint]
     lib.mpdo_batch_workspace_bytes.argtypes = [C.POINTER(Circuit), C.c_int]
     lib.mpdo_batch_workspace_bytes.restype = C.c_size_t
     lib.mpdo_run_batch.argtypes = [C.POINTER(Circuit), C.c_int, C.c_int, C.c_void_p, C.c_size_t]
@@ -257,6 +258,14 @@ class MPDO:
 
     def profile(self, enable: bool):
         self._check(self.lib.mpdo_profile_enable(self.ctx, int(enable)))
+
+    def profile_families(self, names):
+        """Record HIP events around the launches of the named families only (see
+        PROF_FAMILIES); an empty list stops recording."""
+        mask = 0
+        for nm in names:
+            mask |= 1 << PROF_FAMILIES.index(nm)
+        self._check(self.lib.mpdo_profile_enable_mask(self.ctx, mask))
 
     def profile_read(self) -> dict:
         nf = len(PROF_FAMILIES)
