@@ -353,15 +353,6 @@ __device__ __forceinline__ double collect(const double* red) {
     return s;
 }
 
-// sum over the 8 lanes of an aligned group, returned to all 8 (DPP: quad xor 1, quad xor 2,
-// then the mirror inside each half-row brings in the other quad; no LDS traffic)
-__device__ __forceinline__ double group8_sum(double x) {
-    x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
-    x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
-    x += dpp_mov<0x141>(x);   // row_half_mirror
-    return x;
-}
-
 __device__ __forceinline__ bool tile_live(int I, int J, int j) {
     return I >= 0 && RT * I + RT - 1 > j && RT * J + RT - 1 > j;
 }
@@ -402,19 +393,37 @@ __device__ __forceinline__ void hh_entry(const double* vabs, int c, int j, int n
     }
 }
 
-// p += A22 v over one tile.  Row sums of the tile row stay in the lane; the column
-// contributions of an off-diagonal tile (its mirror image above the diagonal) are summed over
-// the 8 lanes of the group by DPP moves, so that lane k adds column 8J + k: two atomics per
-// lane per tile, none of them to the same address within a group.  This lane's share of
-// v^H A22 v (real: A22 is Hermitian) goes to vav: conj(v_r) times the row sum, and for an
-// off-diagonal tile conj(v_c) times the mirrored column sum the lane receives.
+// p += A22 v over one tile.  Row sums of the tile row stay in the lane.  For an off-diagonal
+// tile the lane also forms its row's share of every mirrored column, conj(A_rc) v_r for the 8
+// columns c of the tile, and the group of 8 lanes reduce-scatters those 8 column sums so that
+// lane k ends with column 8J + k: three exchange steps over lane pairs that differ in bit 2
+// (half-row mirror, k <-> 7 - k), bit 1 and bit 0 (quad permutations), each halving the
+// values a lane holds (14 double moves per tile instead of an all-reduce per column).  Two
+// atomics per lane per tile follow, none of them to the same address within a group.  This
+// lane's share of v^H A22 v (real: A22 is Hermitian) goes to vav: conj(v_r) times the row sum,
+// and for an off-diagonal tile conj(v_c) times the column sum the lane receives.  All 8 lanes
+// of a group hold the same tile, so they are active together, as the moves need.
+template <int CTRL, int H>
+__device__ __forceinline__ void rs_step(const double (&xr)[2 * H], const double (&xi)[2 * H], bool hi,
+                                        double (&yr)[H], double (&yi)[H]) {
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        // keep the half this lane owns, send the other half to the partner (which owns it)
+        const double sr = hi ? xr[i] : xr[i + H], si = hi ? xi[i] : xi[i + H];
+        const double kr = hi ? xr[i + H] : xr[i], ki = hi ? xi[i + H] : xi[i];
+        yr[i] = kr + dpp_mov<CTRL>(sr);
+        yi[i] = ki + dpp_mov<CTRL>(si);
+    }
+}
+
 template <class TileRow>
 __device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, const double* v, double* pabs,
                                             double& vav) {
     __builtin_amdgcn_sched_barrier(0);   // keep one tile's operands live at a time
     const int r = RT * I + k;
     const double vrr = v[2 * r], vri = v[2 * r + 1];
-    double rr = 0.0, ri = 0.0, cr = 0.0, ci = 0.0;
+    double rr = 0.0, ri = 0.0;
+    double ar[RT], ai[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         const int c = RT * J + q;
@@ -422,20 +431,18 @@ __device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, con
         const double hr = x.re(q), hi = x.im(q);
         rr += hr * vcr - hi * vci;
         ri += hr * vci + hi * vcr;
-        if (I != J) {
-            // conj(A_rc) v_r, summed over the group's rows
-            const double a = group8_sum(hr * vrr + hi * vri), b = group8_sum(hr * vri - hi * vrr);
-            if (k == q) {
-                cr = a;
-                ci = b;
-            }
-        }
+        ar[q] = hr * vrr + hi * vri;   // conj(A_rc) v_r
+        ai[q] = hr * vri - hi * vrr;
     }
     if (I != J) {
+        double br[4], bi[4], cr2[2], ci2[2], cr[1], ci[1];
+        rs_step<0x141, 4>(ar, ai, (k & 4) != 0, br, bi);     // row_half_mirror: k <-> 7 - k
+        rs_step<0x4E, 2>(br, bi, (k & 2) != 0, cr2, ci2);    // quad_perm [2,3,0,1]: k <-> k ^ 2
+        rs_step<0xB1, 1>(cr2, ci2, (k & 1) != 0, cr, ci);    // quad_perm [1,0,3,2]: k <-> k ^ 1
         const int c = RT * J + k;
-        atomicAdd(&pabs[2 * c], cr);
-        atomicAdd(&pabs[2 * c + 1], ci);
-        vav += v[2 * c] * cr + v[2 * c + 1] * ci;
+        atomicAdd(&pabs[2 * c], cr[0]);
+        atomicAdd(&pabs[2 * c + 1], ci[0]);
+        vav += v[2 * c] * cr[0] + v[2 * c + 1] * ci[0];
     }
     atomicAdd(&pabs[2 * r], rr);
     atomicAdd(&pabs[2 * r + 1], ri);
