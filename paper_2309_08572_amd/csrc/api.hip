@@ -41,6 +41,7 @@ constexpr double EPS64 = 2.220446049250313e-16;
 constexpr double EPS32 = 1.1920928955078125e-07;
 constexpr int MAX_FACTOR_RANK = 16;   // operator-Schmidt terms kept in LDS by phys_* kernels
 constexpr int EIG_MAX_SWEEPS = 40;
+constexpr int EIG_JACOBI_MAX = 32;   // largest order eig_cut gives to the Jacobi solver
 // Range bases whose exact construction would need an eigenproblem above TRI_MAX are found by
 // block subspace iteration on theta theta^H: SUB_OVER extra directions beyond chi, at most
 // SUB_ITERS passes, stopping once the captured weight ||Q^H theta||_F^2 grows by less than the
@@ -422,18 +423,21 @@ struct Engine {
 
     // Eigenpairs of the Gram in s.Gd (order n) that a deflation level accepts (the rule of
     // spectrum_cut): returns the accepted count; s.sig/s.inv style outputs go to sig/inv, the
-    // eigenvectors to columns [0, count) of s.Vd (ld n) and s.bVT.  Orders 65..TRI_MAX use the
-    // tridiagonal solver, which computes only the accepted pairs; the others the Jacobi solver.
+    // eigenvectors to columns [0, count) of s.Vd (ld n) and s.bVT.  Orders above EIG_JACOBI_MAX
+    // up to TRI_MAX use the tridiagonal solver, which computes only the accepted pairs; smaller
+    // orders the one-workgroup Jacobi solver (a round of it costs about 1 us of barriers and
+    // LDS latency whatever the order, and a sweep has n - 1 rounds, so from order ~32 on the
+    // tridiagonal route is faster: orders 33..48 took 400 us by Jacobi, about 170 us this way).
     int eig_cut(int n, int level, double floor2, double noise, double tau, int cap, double* sig, double* inv) {
         int acc;
-        if (n > 64 && n <= TRI_MAX) {
+        if (n > EIG_JACOBI_MAX && n <= TRI_MAX) {
             HIPCHK(eigh_top(st, n, s.Gd, n, level, floor2, noise, tau, cap, s.st, s.cnt, s.evals, sig, inv, s.Vd, n,
                             s.eigwork, ps()));
             ++eig_calls;
             acc = read_int(s.cnt);
             if (!std::is_same<T, double>::value && acc > 0)
                 HIPCHK((geam<double, T>(st, n, acc, C1(), V<double>(s.Vd, n, 1), C0(), V<T>(s.bVT, n, 1))));
-        } else if (n <= 64) {
+        } else if (n <= EIG_JACOBI_MAX) {
             // one workgroup solves to convergence; its sweep count is read together with the
             // accepted count, in one synchronisation
             HIPCHK(eigh(st, n, s.Gd, n, s.Vd, n, s.evals, s.eigwork, EIG_MAX_SWEEPS, nullptr, c.hint, ps(), eps()));

@@ -47,6 +47,28 @@ struct PairLds {
     int flag;
 };
 
+// 1/sqrt(x) and 1/x (x > 0 finite, resp. x != 0) from the hardware estimates and two Newton
+// steps each, to a few ulp: a rotation needs c^2 + s^2 = 1 to rounding, not IEEE rounding of
+// every intermediate, and the estimate-and-refine chain is about half as long as sqrt + div.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double r = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, r, y);
+    }
+    return y;
+}
+__device__ __forceinline__ double rcp_nr2(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-x, y, 1.0);
+        y = fma(y, e, y);
+    }
+    return y;
+}
+
 __device__ __forceinline__ void circle_pair(int players, int round, int j, int& a, int& b) {
     // players is even; player players-1 stays fixed
     const int m = players - 1;
@@ -84,15 +106,28 @@ __device__ int lds_jacobi(PairLds<N>& L, int n, double tol_rel, double tol_abs, 
                 }
                 const double a = L.Hr[p][p], d = L.Hr[q][q];
                 const double br = L.Hr[p][q], bi = L.Hi[p][q];
-                const double ab = sqrt(br * br + bi * bi);
+                const double ab2 = br * br + bi * bi;
                 double c = 1.0, s = 0.0, er = 1.0, ei = 0.0;
-                if (ab > tol_rel * sqrt(fabs(a * d)) + tol_abs) {
-                    const double zeta = (d - a) / (2.0 * ab);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    c = 1.0 / sqrt(1.0 + t * t);
+                // |b| > tol, i.e. |b|^2 > tol^2 (tol >= 0)
+                const double tol = tol_rel * sqrt(fabs(a * d)) + tol_abs;
+                if (ab2 > tol * tol && ab2 > 0.0) {
+                    const double rab = rsqrt_nr(ab2);            // 1 / |b|
+                    const double zeta = 0.5 * (d - a) * rab;
+                    const double az = fabs(zeta);
+                    // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), the smaller root; for huge
+                    // |zeta| (no overflow of zeta^2) t = 1 / (2 zeta)
+                    double t;
+                    if (az < 1e100) {
+                        const double u = fma(zeta, zeta, 1.0);
+                        t = rcp_nr2(az + u * rsqrt_nr(u));
+                    } else {
+                        t = 0.5 / az;
+                    }
+                    if (zeta < 0.0) t = -t;
+                    c = rsqrt_nr(fma(t, t, 1.0));
                     s = t * c;
-                    er = br / ab;
-                    ei = bi / ab;
+                    er = br * rab;
+                    ei = bi * rab;
                     L.flag = 1;
                 }
                 L.c[tid] = c;
@@ -191,31 +226,42 @@ __device__ __forceinline__ int pair_index(int P, int Q, int x) {
 }
 
 // ---------------------------------------------------------------- small matrices
+// One workgroup of jac_small_threads(n) threads; ||H||_F (the absolute tolerance's scale) is
+// summed while the matrix is loaded.  Only the leading np x np corner of the LDS arrays is
+// used (np = n rounded up to even; the padding row and column are zero, with 1 on V's
+// diagonal).
 __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restrict__ H, int ld, int n,
-                                                        const double* __restrict__ fro, double tol_rel,
-                                                        double abs_eps, int max_sweeps, double* __restrict__ evals,
-                                                        double* __restrict__ V, int ldv,
+                                                        double tol_rel, double abs_eps, int max_sweeps,
+                                                        double* __restrict__ evals, double* __restrict__ V, int ldv,
                                                         int* __restrict__ sweeps_out) {
     __shared__ PairLds<NS> L;
     __shared__ int rank[NS];
+    __shared__ double red[1024 / 64];
     const int tid = threadIdx.x;
     const int np = (n + 1) & ~1;
-    for (int idx = tid; idx < NS * NS; idx += blockDim.x) {
-        const int x = idx / NS, y = idx % NS;
+    double f2 = 0.0;
+    for (int idx = tid; idx < np * np; idx += blockDim.x) {
+        const int x = idx / np, y = idx - (idx / np) * np;
         double hr = 0.0, hi = 0.0;
         if (x < n && y < n) {
             hr = H[2 * ((long)x * ld + y)];
             hi = H[2 * ((long)x * ld + y) + 1];
+            f2 += hr * hr + hi * hi;
         }
         L.Hr[x][y] = hr;
         L.Hi[x][y] = hi;
         L.Vr[x][y] = (x == y) ? 1.0 : 0.0;
         L.Vi[x][y] = 0.0;
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) f2 += __shfl_xor(f2, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = f2;
     __syncthreads();
+    double fro2 = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) fro2 += red[w];
     // Hermitian part: average the two triangles, real diagonal
-    for (int idx = tid; idx < NS * NS; idx += blockDim.x) {
-        const int x = idx / NS, y = idx % NS;
+    for (int idx = tid; idx < np * np; idx += blockDim.x) {
+        const int x = idx / np, y = idx - (idx / np) * np;
         if (x < y) {
             const double r = 0.5 * (L.Hr[x][y] + L.Hr[y][x]);
             const double i = 0.5 * (L.Hi[x][y] - L.Hi[y][x]);
@@ -228,7 +274,7 @@ __global__ __launch_bounds__(1024) void jac_small_kernel(const double* __restric
         }
     }
     __syncthreads();
-    const int sw = lds_jacobi<NS>(L, np, tol_rel, abs_eps * fro[0], max_sweeps);
+    const int sw = lds_jacobi<NS>(L, np, tol_rel, abs_eps * sqrt(fro2), max_sweeps);
     if (tid < n) {
         const double lam = L.Hr[tid][tid];
         int rk = 0;
@@ -553,7 +599,7 @@ size_t eigh_work_bytes(int n) {
     b += (size_t)n * n * 2 * sizeof(double);                  // accumulated eigenvectors
     b += 64 * sizeof(double);                                  // norms
     b += (size_t)(nblk / 2 + n + 64) * sizeof(int);            // skip flags, perm, counters
-    // the tridiagonal solver (orders 65..TRI_MAX) uses the same scratch at other times
+    // the tridiagonal solver (orders up to TRI_MAX) uses the same scratch at other times
     const size_t bt = tri_work_bytes(n < TRI_MAX ? n : TRI_MAX);
     return (b > bt ? b : bt) + 1024;
 }
@@ -584,10 +630,12 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
     int* perm = skip + nblk / 2;
     int* nrot = perm + n;
 
-    hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, H, ldh, n, fro);
     if (n <= NS) {
+        // a round of the small solver has (n/2)^2 + (n/2) n independent updates: one wave up
+        // to order 16, four up to 32; fewer waves make each round's two barriers cheaper
+        const int threads = n <= 16 ? 64 : (n <= 32 ? 256 : 1024);
         if (prof) prof->begin(s, PF_EIG_SMALL);
-        hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(1024), 0, s, H, ldh, n, fro, tol_rel, input_eps,
+        hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(threads), 0, s, H, ldh, n, tol_rel, input_eps,
                            max_sweeps, evals, V, ldv, nrot);
         if (prof) prof->end(s, PF_EIG_SMALL, 0.0, 32.0 * n * n);
         if (sweeps_used) {
@@ -598,6 +646,7 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
         }
         return hipGetLastError();
     }
+    hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, H, ldh, n, fro);
     static int inner_sweeps = -1;
     if (inner_sweeps < 0) {
         const char* e = getenv("MPDO_JACOBI_INNER_SWEEPS");

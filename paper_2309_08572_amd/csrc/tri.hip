@@ -1,4 +1,4 @@
-// Hermitian eigensolver for Gram matrices of order 65..TRI_MAX in FP64 (gfx950), restricted to
+// Hermitian eigensolver for Gram matrices of order up to TRI_MAX in FP64 (gfx950), restricted to
 // the eigenpairs one deflation level of the split accepts.
 //
 //   tri_reduce_*       Householder reduction H = Q T Q^H to a real symmetric
@@ -313,8 +313,8 @@ __global__ void tri_last_kernel(const double* __restrict__ H, int ld, int n, dou
 
 // On-chip reduction for orders <= RMAX.  The lower triangle is cut into 8 x 8 tiles (diagonal
 // tiles stored in full); a group of 8 lanes owns RS tiles, lane k row k of each (8 complex
-// values): RS_REG tiles in registers, the rest in LDS, so no matrix element leaves the chip
-// until the reflectors are written.  v and w live in LDS at absolute indices with zeros over
+// values, slot q holding column q ^ k of the tile): RS_REG tiles in registers, the rest in
+// LDS, so no matrix element leaves the chip until the reflectors are written.  v and w live in LDS at absolute indices with zeros over
 // the reduced part, so the arithmetic needs no masks.  Per column: Hermitian matvec (row sums
 // in registers, column sums and row totals by LDS f64 atomics), rank-2 update in place.
 constexpr int RB = 512;        // threads: 2 waves per SIMD leave 256 registers per lane
@@ -362,7 +362,7 @@ template <class TileRow>
 __device__ __forceinline__ void tile_extract(const TileRow& x, int I, int J, int j, int k, int n, double* vabs,
                                              double* dg, double& x2) {
     if (I < 0 || J != j / RT) return;
-    const int r = RT * I + k, jq = j - RT * (j / RT);
+    const int r = RT * I + k, jq = (j - RT * (j / RT)) ^ k;   // the slot of column j
     double a = 0.0, b = 0.0;
 #pragma unroll
     for (int q = 0; q < RT; ++q)
@@ -394,28 +394,17 @@ __device__ __forceinline__ void hh_entry(const double* vabs, int c, int j, int n
 }
 
 // p += A22 v over one tile.  Row sums of the tile row stay in the lane.  For an off-diagonal
-// tile the lane also forms its row's share of every mirrored column, conj(A_rc) v_r for the 8
-// columns c of the tile, and the group of 8 lanes reduce-scatters those 8 column sums so that
-// lane k ends with column 8J + k: three exchange steps over lane pairs that differ in bit 2
-// (half-row mirror, k <-> 7 - k), bit 1 and bit 0 (quad permutations), each halving the
-// values a lane holds (14 double moves per tile instead of an all-reduce per column).  Two
-// atomics per lane per tile follow, none of them to the same address within a group.  This
-// lane's share of v^H A22 v (real: A22 is Hermitian) goes to vav: conj(v_r) times the row sum,
-// and for an off-diagonal tile conj(v_c) times the column sum the lane receives.  All 8 lanes
-// of a group hold the same tile, so they are active together, as the moves need.
-template <int CTRL, int H>
-__device__ __forceinline__ void rs_step(const double (&xr)[2 * H], const double (&xi)[2 * H], bool hi,
-                                        double (&yr)[H], double (&yi)[H]) {
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        // keep the half this lane owns, send the other half to the partner (which owns it)
-        const double sr = hi ? xr[i] : xr[i + H], si = hi ? xi[i] : xi[i + H];
-        const double kr = hi ? xr[i + H] : xr[i], ki = hi ? xi[i + H] : xi[i];
-        yr[i] = kr + dpp_mov<CTRL>(sr);
-        yi[i] = ki + dpp_mov<CTRL>(si);
-    }
-}
-
+// tile the lane also forms its row's share of every mirrored column, conj(A_rc) v_r, in the
+// slot of that column, and the group of 8 lanes reduce-scatters the 8 column sums so that
+// lane k ends with column 8J + k.  Because slot q of lane k holds column q ^ k, the partner
+// k ^ m of an exchange holds the same column in slot q ^ m, so every lane sends the same
+// registers: the half-row mirror (k <-> k ^ 7) adds slots 7..4 into 0..3, the quad
+// permutations (k ^ 2, then k ^ 1) slots 2, 3 into 0, 1 and slot 1 into 0, which then holds
+// column 0 ^ k = k.  14 double moves and no selects per tile.  Two atomics per lane per tile
+// follow, none of them to the same address within a group.  This lane's share of v^H A22 v
+// (real: A22 is Hermitian) goes to vav: conj(v_r) times the row sum, and for an off-diagonal
+// tile conj(v_c) times the column sum the lane receives.  All 8 lanes of a group hold the
+// same tile, so they are active together, as the moves need.
 template <class TileRow>
 __device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, const double* v, double* pabs,
                                             double& vav) {
@@ -426,7 +415,7 @@ __device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, con
     double ar[RT], ai[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
-        const int c = RT * J + q;
+        const int c = RT * J + (q ^ k);
         const double vcr = v[2 * c], vci = v[2 * c + 1];
         const double hr = x.re(q), hi = x.im(q);
         rr += hr * vcr - hi * vci;
@@ -435,14 +424,22 @@ __device__ __forceinline__ void tile_matvec(TileRow& x, int I, int J, int k, con
         ai[q] = hr * vri - hi * vrr;
     }
     if (I != J) {
-        double br[4], bi[4], cr2[2], ci2[2], cr[1], ci[1];
-        rs_step<0x141, 4>(ar, ai, (k & 4) != 0, br, bi);     // row_half_mirror: k <-> 7 - k
-        rs_step<0x4E, 2>(br, bi, (k & 2) != 0, cr2, ci2);    // quad_perm [2,3,0,1]: k <-> k ^ 2
-        rs_step<0xB1, 1>(cr2, ci2, (k & 1) != 0, cr, ci);    // quad_perm [1,0,3,2]: k <-> k ^ 1
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ar[q] += dpp_mov<0x141>(ar[7 - q]);   // row_half_mirror: lane k ^ 7, slot q ^ 7
+            ai[q] += dpp_mov<0x141>(ai[7 - q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            ar[q] += dpp_mov<0x4E>(ar[q + 2]);    // quad_perm [2,3,0,1]: lane k ^ 2, slot q ^ 2
+            ai[q] += dpp_mov<0x4E>(ai[q + 2]);
+        }
+        ar[0] += dpp_mov<0xB1>(ar[1]);            // quad_perm [1,0,3,2]: lane k ^ 1, slot 1
+        ai[0] += dpp_mov<0xB1>(ai[1]);
         const int c = RT * J + k;
-        atomicAdd(&pabs[2 * c], cr[0]);
-        atomicAdd(&pabs[2 * c + 1], ci[0]);
-        vav += v[2 * c] * cr[0] + v[2 * c + 1] * ci[0];
+        atomicAdd(&pabs[2 * c], ar[0]);
+        atomicAdd(&pabs[2 * c + 1], ai[0]);
+        vav += v[2 * c] * ar[0] + v[2 * c + 1] * ai[0];
     }
     atomicAdd(&pabs[2 * r], rr);
     atomicAdd(&pabs[2 * r + 1], ri);
@@ -458,7 +455,7 @@ __device__ __forceinline__ void tile_update(TileRow& x, int I, int J, int k, con
     const double vr = vabs[2 * r], vi = vabs[2 * r + 1], wr = wabs[2 * r], wi = wabs[2 * r + 1];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
-        const int c = RT * J + q;
+        const int c = RT * J + (q ^ k);
         const double vcr = vabs[2 * c], vci = vabs[2 * c + 1], wcr = wabs[2 * c], wci = wabs[2 * c + 1];
         x.set(q, x.re(q) - (vr * wcr + vi * wci + wr * vcr + wi * vci),
               x.im(q) - (vi * wcr - vr * wci + wi * vcr - wr * vci));
@@ -523,7 +520,7 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
         double xr[RT], xi[RT];
 #pragma unroll
         for (int q = 0; q < RT; ++q) {
-            const int c = RT * J + q;
+            const int c = RT * J + (q ^ k);   // slot q holds column q ^ k
             xr[q] = 0.0;
             xi[q] = 0.0;
             if (I >= 0 && r < n && c < n) {
