@@ -680,6 +680,18 @@ __device__ __forceinline__ double rcp_nr(double q) {
     const double e = fma(-q, r, 1.0);
     return fma(r, e, r);
 }
+// 1/q to a few ulp (two Newton steps) for the inverse-iteration factors; q is a nonzero
+// pivot (a zero pivot is replaced by eps ||T|| first) of a normal magnitude whose reciprocal
+// is normal too, as for any Gram matrix of these states
+__device__ __forceinline__ double rcp_nr2(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-q, r, 1.0);
+        r = fma(r, e, r);
+    }
+    return r;
+}
 
 // number of eigenvalues of T below x (Sturm sequence in ratio form with the LAPACK pivot guard)
 __device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
@@ -698,21 +710,35 @@ __device__ __forceinline__ double bis_tol(double lo, double hi, double tnorm) {
     return 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + EPS * tnorm;
 }
 
-// One wave narrows [lo, hi] around the eigenvalue of ascending index idx (count(lo) <= idx <
-// count(hi)) with 64 shifts per pass (6 bits); every lane returns the same bracket.  One
-// shift per lane: the pass is issue-bound, so more shifts per lane would buy fewer bits per
-// cycle.
-__device__ void wave_multisect(const double* d, const double* e2, int n, int idx, double pivmin, double tnorm,
-                               double& lo, double& hi) {
-    const int lane = threadIdx.x & 63;
+// A workgroup of MS_WAVES waves (one per SIMD) narrows [lo, hi] around the eigenvalue of
+// ascending index idx (count(lo) <= idx < count(hi)) with 64 MS_WAVES shifts per pass, one per
+// lane (8 bits per pass); every thread returns the same bracket.  A Sturm count is a chain of
+// dependent steps, so one wave per SIMD runs it at the chain's latency and the extra waves
+// buy bits per pass at no cost in pass time (one wave: 6 bits per pass).
+constexpr int MS_WAVES = 4;
+constexpr int MS_THREADS = 64 * MS_WAVES;
+__device__ void block_multisect(const double* d, const double* e2, int n, int idx, double pivmin, double tnorm,
+                                double& lo, double& hi, double* red) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int it = 0; it < 24; ++it) {
-        if (hi - lo <= bis_tol(lo, hi, tnorm)) break;
-        const double h = (hi - lo) / 65.0;
-        const double x = lo + (double)(lane + 1) * h;
+        if (hi - lo <= bis_tol(lo, hi, tnorm)) break;   // the same in every thread
+        const double h = (hi - lo) / (double)(MS_THREADS + 1);
+        const double x = lo + (double)(tid + 1) * h;
         const int c = sturm_count(d, e2, n, x, pivmin);
-        double nlo = c <= idx ? x : lo, nhi = c <= idx ? hi : x;
-        lo = wave_max(nlo);
-        hi = wave_min(nhi);
+        double nlo = wave_max(c <= idx ? x : lo), nhi = wave_min(c <= idx ? hi : x);
+        if (lane == 0) {
+            red[2 * w] = nlo;
+            red[2 * w + 1] = nhi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MS_WAVES; ++q) {
+            nlo = fmax(nlo, red[2 * q]);
+            nhi = fmin(nhi, red[2 * q + 1]);
+        }
+        lo = nlo;
+        hi = nhi;
+        __syncthreads();   // red is rewritten in the next pass
     }
 }
 
@@ -728,17 +754,17 @@ __device__ __forceinline__ unsigned hash32(unsigned x) {
 // par[] written by tri_top_kernel and read by the later kernels
 enum { P_TNORM = 0, P_PIVMIN = 1, P_TOP = 2, P_THR = 3, P_COUNT = 8 };
 
-// One wave: Gershgorin bounds, the largest eigenvalue, the level's threshold t and the
+// One workgroup: Gershgorin bounds, the largest eigenvalue, the level's threshold t and the
 // accepted count m (cnt[0]); st as spectrum_cut writes it.
-__global__ __launch_bounds__(64) void tri_top_kernel(const double* __restrict__ dg, const double* __restrict__ off,
+__global__ __launch_bounds__(MS_THREADS) void tri_top_kernel(const double* __restrict__ dg, const double* __restrict__ off,
                                                      int n, int level, double floor2, double noise, double tau_rel,
                                                      int cap, const double* __restrict__ trace,
                                                      double* __restrict__ st, int* __restrict__ cnt,
                                                      double* __restrict__ par) {
-    __shared__ double d[TRI_MAX], e2[TRI_MAX];
-    const int lane = threadIdx.x;
+    __shared__ double d[TRI_MAX], e2[TRI_MAX], red[4 * MS_WAVES];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     double gmax = -INFINITY, gmin = INFINITY, e2max = 0.0, dmax = -INFINITY;
-    for (int i = lane; i < n; i += 64) {
+    for (int i = tid; i < n; i += MS_THREADS) {
         const double di = dg[i];
         const double el = i > 0 ? fabs(off[i - 1]) : 0.0, er = i < n - 1 ? fabs(off[i]) : 0.0;
         d[i] = di;
@@ -752,12 +778,26 @@ __global__ __launch_bounds__(64) void tri_top_kernel(const double* __restrict__ 
     gmin = wave_min(gmin);
     e2max = wave_max(e2max);
     dmax = wave_max(dmax);
+    if (lane == 0) {
+        red[4 * w] = gmax;
+        red[4 * w + 1] = gmin;
+        red[4 * w + 2] = e2max;
+        red[4 * w + 3] = dmax;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MS_WAVES; ++q) {
+        gmax = fmax(gmax, red[4 * q]);
+        gmin = fmin(gmin, red[4 * q + 1]);
+        e2max = fmax(e2max, red[4 * q + 2]);
+        dmax = fmax(dmax, red[4 * q + 3]);
+    }
     __syncthreads();
     const double tnorm = fmax(fabs(gmin), fabs(gmax));
     const double pivmin = DBL_MIN * fmax(1.0, e2max);
     double lo = dmax, hi = gmax + EPS * tnorm + pivmin;   // count(lo) <= n-1 < count(hi)
-    wave_multisect(d, e2, n, n - 1, pivmin, tnorm, lo, hi);
-    if (lane == 0) {
+    block_multisect(d, e2, n, n - 1, pivmin, tnorm, lo, hi, red);
+    if (tid == 0) {
         const double lmax = 0.5 * (lo + hi);
         const double st0 = level == 0 ? lmax : st[0];
         double t = floor2 * st0;
@@ -782,22 +822,22 @@ __global__ __launch_bounds__(64) void tri_top_kernel(const double* __restrict__ 
     }
 }
 
-// Wave k < m: eigenvalue k (descending) by multisection on [t, top].
-__global__ __launch_bounds__(64) void tri_eval_kernel(const double* __restrict__ dg, const double* __restrict__ off,
+// Workgroup k < m: eigenvalue k (descending) by multisection on [t, top].
+__global__ __launch_bounds__(MS_THREADS) void tri_eval_kernel(const double* __restrict__ dg, const double* __restrict__ off,
                                                       int n, const int* __restrict__ cnt,
                                                       const double* __restrict__ par, double* __restrict__ evals,
                                                       double* __restrict__ sig, double* __restrict__ inv) {
-    __shared__ double d[TRI_MAX], e2[TRI_MAX];
-    const int k = blockIdx.x, lane = threadIdx.x;
+    __shared__ double d[TRI_MAX], e2[TRI_MAX], red[2 * MS_WAVES];
+    const int k = blockIdx.x, tid = threadIdx.x;
     if (k >= cnt[0]) return;
-    for (int i = lane; i < n; i += 64) {
+    for (int i = tid; i < n; i += MS_THREADS) {
         d[i] = dg[i];
         e2[i] = i < n - 1 ? off[i] * off[i] : 0.0;
     }
     __syncthreads();
     double lo = par[P_THR], hi = par[P_TOP];
-    wave_multisect(d, e2, n, n - 1 - k, par[P_PIVMIN], par[P_TNORM], lo, hi);
-    if (lane == 0) {
+    block_multisect(d, e2, n, n - 1 - k, par[P_PIVMIN], par[P_TNORM], lo, hi, red);
+    if (tid == 0) {
         const double lk = 0.5 * (lo + hi);
         evals[k] = lk;
         const double sk = sqrt(fmax(lk, 0.0));
@@ -838,10 +878,11 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ 
                     const double xn = z[i + 1];
                     if (fabs(p0) >= fabs(sub)) {
                         if (p0 == 0.0) p0 = tiny;
-                        const double mlt = sub / p0;
+                        const double r0 = rcp_nr2(p0);
+                        const double mlt = sub * r0;
                         fm[i] = mlt;
                         sw[i] = 0;
-                        u0[i] = 1.0 / p0;
+                        u0[i] = r0;
                         u1[i] = p1;
                         u2[i] = 0.0;
                         yv[i] = y;
@@ -849,10 +890,11 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ 
                         p1 = ns;
                         y = xn - mlt * y;
                     } else {
-                        const double mlt = p0 / sub;
+                        const double r0 = rcp_nr2(sub);
+                        const double mlt = p0 * r0;
                         fm[i] = mlt;
                         sw[i] = 1;
-                        u0[i] = 1.0 / sub;
+                        u0[i] = r0;
                         u1[i] = nd;
                         u2[i] = ns;
                         yv[i] = xn;
@@ -863,7 +905,7 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ 
                     }
                 }
                 if (p0 == 0.0) p0 = tiny;
-                u0[n - 1] = 1.0 / p0;
+                u0[n - 1] = rcp_nr2(p0);
             } else {
                 for (int i = 0; i < n - 1; ++i) {
                     const double xn = z[i + 1];
@@ -1069,10 +1111,10 @@ hipError_t eigh_top(hipStream_t s, int n, double* H, int ldh, int level, double 
     // once per column
     if (prof) prof->end(s, PF_TRI_REDUCE, 16.0 / 3.0 * nn * nn * nn, 16.0 * nn * nn * 2.0);
     if (prof) prof->begin(s, PF_TRI_SOLVE);
-    hipLaunchKernelGGL(tri_top_kernel, dim3(1), dim3(64), 0, s, dg, off, n, level, floor2, noise, tau, cap, trace,
+    hipLaunchKernelGGL(tri_top_kernel, dim3(1), dim3(MS_THREADS), 0, s, dg, off, n, level, floor2, noise, tau, cap, trace,
                        st, cnt, par);
     if (cap > 0) {
-        hipLaunchKernelGGL(tri_eval_kernel, dim3(cap), dim3(64), 0, s, dg, off, n, cnt, par, evals, sig, inv);
+        hipLaunchKernelGGL(tri_eval_kernel, dim3(cap), dim3(MS_THREADS), 0, s, dg, off, n, cnt, par, evals, sig, inv);
         hipLaunchKernelGGL(tri_vec_kernel, dim3(cap), dim3(64), 0, s, dg, off, n, cnt, par, evals, Z);
         hipLaunchKernelGGL(tri_mgs_kernel, dim3(1), dim3(TB), 0, s, n, cnt, par, evals, Z);
     }
