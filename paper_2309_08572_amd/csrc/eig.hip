@@ -47,7 +47,7 @@ struct PairLds {
     int flag;
 };
 
-// 1/sqrt(x) and 1/x (x > 0 finite, resp. x != 0) from the hardware estimates and two Newton
+// 1/sqrt(x) and 1/x (1e-290 <= |x| <= 1e290) from the hardware estimates and two Newton
 // steps each, to a few ulp: a rotation needs c^2 + s^2 = 1 to rounding, not IEEE rounding of
 // every intermediate, and the estimate-and-refine chain is about half as long as sqrt + div.
 __device__ __forceinline__ double rsqrt_nr(double x) {
@@ -111,7 +111,9 @@ __device__ int lds_jacobi(PairLds<N>& L, int n, double tol_rel, double tol_abs, 
                 // |b| > tol, i.e. |b|^2 > tol^2 (tol >= 0)
                 const double tol = tol_rel * sqrt(fabs(a * d)) + tol_abs;
                 if (ab2 > tol * tol && ab2 > 0.0) {
-                    const double rab = rsqrt_nr(ab2);            // 1 / |b|
+                    // 1 / |b|; |b|^2 below 1e-290 (not seen at Gram scales) takes the IEEE route,
+                    // where the hardware estimate could overflow
+                    const double rab = ab2 >= 1e-290 ? rsqrt_nr(ab2) : 1.0 / sqrt(ab2);
                     const double zeta = 0.5 * (d - a) * rab;
                     const double az = fabs(zeta);
                     // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), the smaller root; for huge

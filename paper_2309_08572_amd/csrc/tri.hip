@@ -311,6 +311,30 @@ __global__ void tri_last_kernel(const double* __restrict__ H, int ld, int n, dou
     if (threadIdx.x == 0) dg[n - 1] = H[2 * ((long)(n - 1) * ld + (n - 1))];
 }
 
+// 1/q from the hardware reciprocal and one Newton step (the Sturm count tolerates a last-bit
+// difference from IEEE division; |q| >= pivmin keeps q normal)
+__device__ __forceinline__ double rcp_nr(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    const double e = fma(-q, r, 1.0);
+    return fma(r, e, r);
+}
+// 1/q to a few ulp (two Newton steps) for 1e-290 <= |q| <= 1e290; outside that range the
+// hardware estimate can overflow or flush, and callers divide instead (pivot_rcp)
+__device__ __forceinline__ double rcp_nr2(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-q, r, 1.0);
+        r = fma(r, e, r);
+    }
+    return r;
+}
+
+__device__ __forceinline__ double pivot_rcp(double q) {
+    const double a = fabs(q);
+    return (a >= 1e-290 && a <= 1e290) ? rcp_nr2(q) : 1.0 / q;
+}
+
 // On-chip reduction for orders <= RMAX.  The lower triangle is cut into 8 x 8 tiles (diagonal
 // tiles stored in full); a group of 8 lanes owns RS tiles, lane k row k of each (8 complex
 // values, slot q holding column q ^ k of the tile): RS_REG tiles in registers, the rest in
@@ -590,6 +614,8 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
             if (x2 == 0.0 && aii == 0.0) {
                 beta = arr;
             } else {
+                // IEEE divisions: |alpha - beta|^2 underflows for columns below ~1e-154, where
+                // a hardware reciprocal would overflow
                 beta = -copysign(sqrt(arr * arr + aii * aii + x2), arr);
                 tr_ = (beta - arr) / beta;
                 ti_ = -aii / beta;
@@ -673,26 +699,6 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
 }
 
 // ------------------------------------------------------------------ eigenvalues / vectors
-// 1/q from the hardware reciprocal and one Newton step (the Sturm count tolerates a last-bit
-// difference from IEEE division; |q| >= pivmin keeps q normal)
-__device__ __forceinline__ double rcp_nr(double q) {
-    double r = __builtin_amdgcn_rcp(q);
-    const double e = fma(-q, r, 1.0);
-    return fma(r, e, r);
-}
-// 1/q to a few ulp (two Newton steps) for the inverse-iteration factors; q is a nonzero
-// pivot (a zero pivot is replaced by eps ||T|| first) of a normal magnitude whose reciprocal
-// is normal too, as for any Gram matrix of these states
-__device__ __forceinline__ double rcp_nr2(double q) {
-    double r = __builtin_amdgcn_rcp(q);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double e = fma(-q, r, 1.0);
-        r = fma(r, e, r);
-    }
-    return r;
-}
-
 // number of eigenvalues of T below x (Sturm sequence in ratio form with the LAPACK pivot guard)
 __device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
     double q = d[0] - x;
@@ -878,8 +884,8 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ 
                     const double xn = z[i + 1];
                     if (fabs(p0) >= fabs(sub)) {
                         if (p0 == 0.0) p0 = tiny;
-                        const double r0 = rcp_nr2(p0);
-                        const double mlt = sub * r0;
+                        const double r0 = pivot_rcp(p0);
+                        const double mlt = fabs(p0) >= 1e-290 ? sub * r0 : sub / p0;
                         fm[i] = mlt;
                         sw[i] = 0;
                         u0[i] = r0;
@@ -890,8 +896,8 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ 
                         p1 = ns;
                         y = xn - mlt * y;
                     } else {
-                        const double r0 = rcp_nr2(sub);
-                        const double mlt = p0 * r0;
+                        const double r0 = pivot_rcp(sub);
+                        const double mlt = fabs(sub) >= 1e-290 ? p0 * r0 : p0 / sub;
                         fm[i] = mlt;
                         sw[i] = 1;
                         u0[i] = r0;
@@ -905,7 +911,7 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double* __restrict__ 
                     }
                 }
                 if (p0 == 0.0) p0 = tiny;
-                u0[n - 1] = rcp_nr2(p0);
+                u0[n - 1] = pivot_rcp(p0);
             } else {
                 for (int i = 0; i < n - 1; ++i) {
                     const double xn = z[i + 1];
