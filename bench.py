@@ -310,6 +310,24 @@ def roofline_of(prof: dict, fam: str, fp64: bool) -> dict:
     return rf
 
 
+def _truncation_summary(infos, obs) -> dict:
+    """Per-update truncation records of one circuit (mpdo_trunc_info), summarised: discarded
+    weight (1 - sum of the kept Lambda^2 over |Lambda|^2, per update), the trace drift of each
+    cut (PPT keeps xi = tr rho^2 / (tr rho)^2, not the trace) and how well xi was kept."""
+    dw = [i["discarded_weight"] for i in infos]
+    tdrift = [abs(i["trace_after"] - i["trace_before"]) / abs(i["trace_before"])
+              for i in infos if i["trace_before"] != 0.0]
+    xdrift = [abs(i["xi_after"] - i["xi_before"]) / abs(i["xi_before"])
+              for i in infos if i["xi_before"] != 0.0]
+    tr = obs["trace"]
+    return {"updates": len(infos), "updates_truncated": int(sum(1 for x in dw if x > 0.0)),
+            "discarded_weight_sum": float(sum(dw)), "discarded_weight_max": float(max(dw) if dw else 0.0),
+            "trace_drift_per_update_max": float(max(tdrift) if tdrift else 0.0),
+            "trace_drift_circuit": float(abs(complex(tr) - 1.0)),
+            "xi_rel_change_per_update_max": float(max(xdrift) if xdrift else 0.0),
+            "ppt_infeasible": int(sum(1 for i in infos if not i["ppt_feasible"]))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,11 +374,13 @@ def main() -> int:
         # and picks the roofline family.  Event pairs cost host time at every launch they bracket
         # (a quarter of the step when all ~170 launches of an update carry them), so the timed
         # steps record events only around the roofline family's launches.
+        # The same untimed step collects each update's truncation record (a host read per update).
         m.profile(True)
+        infos = []
         torch.cuda.synchronize()
         tp = time.perf_counter()
-        circuits.run_circuit(spec, m=m)
-        circuits.observables(m)
+        circuits.run_circuit(spec, m=m, infos=infos)
+        obs_p = circuits.observables(m)
         torch.cuda.synchronize()
         tp = time.perf_counter() - tp
         prof = m.profile_read()
@@ -376,6 +396,7 @@ def main() -> int:
         prof_timed = m.profile_read()
         m.profile(False)
         results[name] = {"seconds": dt, "obs": obs, "prof": prof, "profiled_seconds": tp, "fam": fam,
+                         "truncation": _truncation_summary(infos, obs_p),
                          "prof_timed": prof_timed, "bonds": max(m.bond_dims())}
         m.close()
 
@@ -419,6 +440,9 @@ def main() -> int:
             "abs_err_energy_per_site_vs_fp64": abs(a["energy_per_site"] - b["energy_per_site"]),
             "abs_err_populations_vs_fp64": float(np.max(np.abs(a["populations"] - b["populations"]))),
         }
+    out["truncation"] = r["truncation"]
+    if "fp32" in results and "fp64" in results:
+        out["fp32"]["truncation"] = results["fp32"]["truncation"]
     out["observables"] = {"energy_per_site": r["obs"]["energy_per_site"],
                           "p_success": r["obs"]["p_success"],
                           "trace": [r["obs"]["trace"].real, r["obs"]["trace"].imag]}
