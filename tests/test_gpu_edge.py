@@ -148,3 +148,32 @@ def test_chi_one_matches_the_mpo_oracle():
           f"discarded {[round(i['discarded_weight'], 4) for i in infos]}", flush=True)
     m.close()
     assert err <= 1e-10
+
+
+def test_empty_expectation_lists_and_a_cut_that_removes_nothing():
+    """No terms: empty results, no error.  mpdo_truncate to the bond's own dimension cuts only
+    Schmidt values at the 1e-14 cutoff, and PPT is the identity when nothing is discarded, so
+    the density matrix is unchanged to rounding."""
+    mpdo = _gpu()
+    rng = np.random.default_rng(61)
+    d, n = 3, 5
+    rhos = [_rho0(rng, d) for _ in range(n)]
+    m = mpdo.MPDO(n, d, 81, precision=mpdo.MPDO_FP64)
+    m.init_product_state(rhos)
+    for s_ in (0, 2, 1, 3):
+        m.apply_gate_kraus(s_, _kraus2(rng, d))
+    print("[gpu] empty expect lists, no-op truncate N=5 d=3", flush=True)
+    before = _dense_from_sites(m, n, d)
+    assert m.expect([]).shape == (0,)
+    assert m.expect2([]).shape == (0,)
+    b = m.bond_dims()
+    info = m.truncate(1, b[1])
+    after = _dense_from_sites(m, n, d)
+    err = np.abs(after - before).max() / np.abs(before).max()
+    print(f"[gpu] bonds {b} -> {m.bond_dims()}, discarded {info['discarded_weight']:.1e}, change {err:.1e}",
+          flush=True)
+    bonds_after = m.bond_dims()
+    m.close()
+    assert bonds_after[1] <= b[1]
+    assert info["discarded_weight"] <= 1e-24
+    assert err <= 1e-12
