@@ -175,5 +175,6 @@ def test_empty_expectation_lists_and_a_cut_that_removes_nothing():
     bonds_after = m.bond_dims()
     m.close()
     assert bonds_after[1] <= b[1]
-    assert info["discarded_weight"] <= 1e-24
+    # 1 - sum_kept Lambda^2 / |Lambda|^2: zero up to the rounding of the two sums
+    assert info["discarded_weight"] <= 1e-14
     assert err <= 1e-12
