@@ -118,14 +118,9 @@ __device__ __forceinline__ void block_maxmin(double& a, double& b, double* red) 
 // trace[0] = sum of the diagonal of H.
 //
 // The trailing matrix does not fit on chip above RMAX, and one workgroup streaming it through
-// L2 once per column is bound by that one compute unit.  So each column is two launches over
-// many workgroups, the rows of the trailing matrix split between their waves (ROWS_PER_WAVE
-// rows at a time):
-//   tri_hh_symv_kernel  every workgroup forms the Householder vector of column j itself (the
-//                       same arithmetic in the same order, so all agree), workgroup 0 writes the
-//                       outputs of column j and v; then p = tau A22 v for the workgroup's rows
-//   tri_rank2_kernel    every workgroup forms w = p - (tau/2)(p^H v) v and applies
-//                       A22 -= v w^H + w v^H to its rows.
+// L2 once per column is bound by that one compute unit.  So each column is a launch over many
+// workgroups (tri_col_kernel below), the rows of the trailing matrix split between their waves
+// (ROWS_PER_WAVE rows at a time).
 constexpr int RW = 256;                 // threads of the multi-workgroup reduction kernels
 constexpr int RWV = RW / 64;
 constexpr int ROWS_PER_WAVE = 4;
@@ -164,152 +159,6 @@ __global__ __launch_bounds__(RW) void tri_trace_kernel(const double* __restrict_
     if (threadIdx.x == 0) trace[0] = tr;
 }
 
-__global__ __launch_bounds__(RW) void tri_hh_symv_kernel(const double* __restrict__ H, int ld, int n, int j,
-                                                         double* __restrict__ dg, double* __restrict__ off,
-                                                         double* __restrict__ tau, double* __restrict__ refl,
-                                                         double* __restrict__ vbuf, double* __restrict__ pbuf) {
-    __shared__ double v[2 * TRI_MAX];
-    __shared__ double red[2 * RWV];
-    __shared__ double sc[4];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int m = n - j - 1;
-    // x = column j below the diagonal, read as the conjugate of row j right of the diagonal
-    // (contiguous; the trailing updates keep the matrix Hermitian to rounding)
-    double x2 = 0.0, unused = 0.0;
-    for (int i = tid; i < m; i += RW) {
-        const double* h = H + 2 * ((long)j * ld + (j + 1 + i));
-        v[2 * i] = h[0];
-        v[2 * i + 1] = -h[1];
-        if (i > 0) x2 += h[0] * h[0] + h[1] * h[1];
-    }
-    block_sum2<RWV>(x2, unused, red);
-    if (tid == 0) {
-        const double ar = v[0], ai = v[1];
-        double beta, tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
-        if (x2 == 0.0 && ai == 0.0) {
-            beta = ar;   // already reduced: H_j = I
-        } else {
-            beta = -copysign(sqrt(ar * ar + ai * ai + x2), ar);
-            tr_ = (beta - ar) / beta;
-            ti_ = -ai / beta;
-            const double dr = ar - beta, di = ai, den = dr * dr + di * di;   // 1/(alpha - beta)
-            sr = dr / den;
-            si = -di / den;
-        }
-        sc[0] = tr_;
-        sc[1] = ti_;
-        sc[2] = sr;
-        sc[3] = si;
-        if (blockIdx.x == 0) {
-            off[j] = beta;
-            tau[2 * j] = tr_;
-            tau[2 * j + 1] = ti_;
-            dg[j] = H[2 * ((long)j * ld + j)];
-        }
-    }
-    __syncthreads();
-    const double tr_ = sc[0], ti_ = sc[1], sr = sc[2], si = sc[3];
-    for (int i = tid; i < m; i += RW) {
-        double vr = 1.0, vi = 0.0;
-        if (i > 0) {
-            const double xr = v[2 * i], xi = v[2 * i + 1];
-            vr = xr * sr - xi * si;
-            vi = xr * si + xi * sr;
-        }
-        v[2 * i] = vr;
-        v[2 * i + 1] = vi;
-        if (blockIdx.x == 0) {
-            refl[2 * ((long)j * n + i)] = vr;
-            refl[2 * ((long)j * n + i) + 1] = vi;
-            vbuf[2 * i] = vr;
-            vbuf[2 * i + 1] = vi;
-        }
-    }
-    __syncthreads();
-    // p = tau A22 v over this workgroup's rows
-    const long base = (long)(j + 1) * ld + (j + 1);
-    const int nw = gridDim.x * RWV;
-    for (int r0 = ROWS_PER_WAVE * (blockIdx.x * RWV + w); r0 < m; r0 += ROWS_PER_WAVE * nw) {
-        double ar[ROWS_PER_WAVE], ai[ROWS_PER_WAVE];
-#pragma unroll
-        for (int q = 0; q < ROWS_PER_WAVE; ++q) ar[q] = ai[q] = 0.0;
-        for (int c = lane; c < m; c += 64) {
-            const double vr = v[2 * c], vi = v[2 * c + 1];
-#pragma unroll
-            for (int q = 0; q < ROWS_PER_WAVE; ++q) {
-                if (r0 + q < m) {
-                    const double* h = H + 2 * (base + (long)(r0 + q) * ld + c);
-                    const double hr = h[0], hi = h[1];
-                    ar[q] += hr * vr - hi * vi;
-                    ai[q] += hr * vi + hi * vr;
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < ROWS_PER_WAVE; ++q) {
-            const double qr = wave_sum(ar[q]), qi = wave_sum(ai[q]);
-            if (lane == 0 && r0 + q < m) {
-                pbuf[2 * (r0 + q)] = tr_ * qr - ti_ * qi;
-                pbuf[2 * (r0 + q) + 1] = tr_ * qi + ti_ * qr;
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(RW) void tri_rank2_kernel(double* __restrict__ H, int ld, int n, int j,
-                                                       const double* __restrict__ tau,
-                                                       const double* __restrict__ vbuf,
-                                                       const double* __restrict__ pbuf) {
-    __shared__ double v[2 * TRI_MAX];
-    __shared__ double p[2 * TRI_MAX];
-    __shared__ double red[2 * RWV];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int m = n - j - 1;
-    const double tr_ = tau[2 * j], ti_ = tau[2 * j + 1];
-    if (tr_ == 0.0 && ti_ == 0.0) return;   // H_j = I: the same for every workgroup
-    double hr = 0.0, hi = 0.0;
-    for (int i = tid; i < 2 * m; i += RW) {
-        v[i] = vbuf[i];
-        p[i] = pbuf[i];
-    }
-    __syncthreads();
-    // w = p - (tau/2) (p^H v) v
-    for (int i = tid; i < m; i += RW) {
-        const double pr = p[2 * i], pi = p[2 * i + 1], vr = v[2 * i], vi = v[2 * i + 1];
-        hr += pr * vr + pi * vi;
-        hi += pr * vi - pi * vr;
-    }
-    block_sum2<RWV>(hr, hi, red);
-    const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
-    for (int i = tid; i < m; i += RW) {
-        const double vr = v[2 * i], vi = v[2 * i + 1];
-        p[2 * i] += a2r * vr - a2i * vi;
-        p[2 * i + 1] += a2r * vi + a2i * vr;
-    }
-    __syncthreads();
-    // A22 -= v w^H + w v^H over this workgroup's rows
-    const long base = (long)(j + 1) * ld + (j + 1);
-    const int nw = gridDim.x * RWV;
-    for (int r0 = ROWS_PER_WAVE * (blockIdx.x * RWV + w); r0 < m; r0 += ROWS_PER_WAVE * nw) {
-        for (int c = lane; c < m; c += 64) {
-            const double vcr = v[2 * c], vci = v[2 * c + 1], wcr = p[2 * c], wci = p[2 * c + 1];
-#pragma unroll
-            for (int q = 0; q < ROWS_PER_WAVE; ++q) {
-                const int r = r0 + q;
-                if (r < m) {
-                    const double vr = v[2 * r], vi = v[2 * r + 1], wr = p[2 * r], wi = p[2 * r + 1];
-                    double* h = H + 2 * (base + (long)r * ld + c);
-                    h[0] -= vr * wcr + vi * wci + wr * vcr + wi * vci;
-                    h[1] -= vi * wcr - vr * wci + wi * vcr - wr * vci;
-                }
-            }
-        }
-    }
-}
-
-__global__ void tri_last_kernel(const double* __restrict__ H, int ld, int n, double* __restrict__ dg) {
-    if (threadIdx.x == 0) dg[n - 1] = H[2 * ((long)(n - 1) * ld + (n - 1))];
-}
 
 // 1/q from the hardware reciprocal and one Newton step (the Sturm count tolerates a last-bit
 // difference from IEEE division; |q| >= pivmin keeps q normal)
@@ -698,6 +547,176 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
     }
 }
 
+// One launch per column for orders above RMAX (column j = 0 .. n-1; j = n - 1 only finishes).
+// The rank-2 update of column j - 1 is deferred into launch j and fused with the matrix-vector
+// product of column j, so the trailing matrix is read and written once per column:
+//   1. every workgroup loads v and p = tau A v of column j - 1 (double buffers, by column
+//      parity), forms w = p - (tau/2)(p^H v) v, and computes the updated row j itself (O(n));
+//      row j is never written back (no later column reads it), so no workgroup waits for
+//      another;
+//   2. every workgroup forms the Householder vector of column j from that row (the same
+//      arithmetic in the same order, so all agree); workgroup 0 writes dg[j], off[j], tau[j],
+//      the reflector row and v;
+//   3. each wave applies A -= v w^H + w v^H (column j - 1) to its rows j+1.. of the trailing
+//      matrix and, in the same pass over the columns, accumulates p = tau A v of column j for
+//      those rows; a lane re-reads only entries it wrote itself.
+// The arithmetic is that of the two-launch form (same formulas, same summation order).
+// vbuf and pbuf hold two vectors of n complex entries each (4 n doubles).
+__global__ __launch_bounds__(RW) void tri_col_kernel(double* __restrict__ H, int ld, int n, int j,
+                                                     double* __restrict__ dg, double* __restrict__ off,
+                                                     double* __restrict__ tau, double* __restrict__ refl,
+                                                     double* __restrict__ vbuf, double* __restrict__ pbuf) {
+    __shared__ double vp[2 * TRI_MAX];   // v of column j - 1, rows j .. n-1
+    __shared__ double wp[2 * TRI_MAX];   // w of column j - 1, rows j .. n-1
+    __shared__ double rw[2 * TRI_MAX];   // updated row j, columns j .. n-1
+    __shared__ double v[2 * TRI_MAX];    // v of column j, rows j+1 .. n-1
+    __shared__ double red[2 * RWV];
+    __shared__ double sc[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int mp = n - j;       // rows j .. n-1
+    const int m = n - j - 1;    // rows j+1 .. n-1
+    const double* vprev = vbuf + 2 * (size_t)n * ((j + 1) & 1);
+    const double* pprev = pbuf + 2 * (size_t)n * ((j + 1) & 1);
+    double* vcur = vbuf + 2 * (size_t)n * (j & 1);
+    double* pcur = pbuf + 2 * (size_t)n * (j & 1);
+    bool upd = false;
+    if (j > 0) {
+        const double tr_ = tau[2 * (j - 1)], ti_ = tau[2 * (j - 1) + 1];
+        upd = tr_ != 0.0 || ti_ != 0.0;   // the same in every workgroup
+        if (upd) {
+            double hr = 0.0, hi = 0.0;
+            for (int i = tid; i < mp; i += RW) {
+                const double vr = vprev[2 * i], vi = vprev[2 * i + 1], pr = pprev[2 * i], pi = pprev[2 * i + 1];
+                vp[2 * i] = vr;
+                vp[2 * i + 1] = vi;
+                wp[2 * i] = pr;
+                wp[2 * i + 1] = pi;
+                hr += pr * vr + pi * vi;
+                hi += pr * vi - pi * vr;
+            }
+            block_sum2<RWV>(hr, hi, red);   // its barriers also publish vp, wp
+            const double a2r = -0.5 * (tr_ * hr - ti_ * hi), a2i = -0.5 * (tr_ * hi + ti_ * hr);
+            for (int i = tid; i < mp; i += RW) {
+                const double vr = vp[2 * i], vi = vp[2 * i + 1];
+                wp[2 * i] += a2r * vr - a2i * vi;
+                wp[2 * i + 1] += a2r * vi + a2i * vr;
+            }
+            __syncthreads();
+        }
+    }
+    // row j, columns j .. n-1, with column j - 1's update applied (relative row 0 of its block)
+    for (int c = tid; c < mp; c += RW) {
+        const double* h = H + 2 * ((long)j * ld + (j + c));
+        double a = h[0], b = h[1];
+        if (upd) {
+            const double vr = vp[0], vi = vp[1], wr = wp[0], wi = wp[1];
+            const double vcr = vp[2 * c], vci = vp[2 * c + 1], wcr = wp[2 * c], wci = wp[2 * c + 1];
+            a -= vr * wcr + vi * wci + wr * vcr + wi * vci;
+            b -= vi * wcr - vr * wci + wi * vcr - wr * vci;
+        }
+        rw[2 * c] = a;
+        rw[2 * c + 1] = b;
+    }
+    __syncthreads();
+    if (m <= 0) {   // last column: only its diagonal entry remains
+        if (blockIdx.x == 0 && tid == 0) dg[j] = rw[0];
+        return;
+    }
+    // x = column j below the diagonal = conj(row j right of the diagonal): x_i = conj(rw[i + 1])
+    double x2 = 0.0, unused = 0.0;
+    for (int i = tid; i < m; i += RW)
+        if (i > 0) x2 += rw[2 * (i + 1)] * rw[2 * (i + 1)] + rw[2 * (i + 1) + 1] * rw[2 * (i + 1) + 1];
+    block_sum2<RWV>(x2, unused, red);
+    if (tid == 0) {
+        const double ar = rw[2], ai = -rw[3];
+        double beta, tr_ = 0.0, ti_ = 0.0, sr = 0.0, si = 0.0;
+        if (x2 == 0.0 && ai == 0.0) {
+            beta = ar;   // already reduced: H_j = I
+        } else {
+            beta = -copysign(sqrt(ar * ar + ai * ai + x2), ar);
+            tr_ = (beta - ar) / beta;
+            ti_ = -ai / beta;
+            const double dr = ar - beta, di = ai, den = dr * dr + di * di;   // 1/(alpha - beta)
+            sr = dr / den;
+            si = -di / den;
+        }
+        sc[0] = tr_;
+        sc[1] = ti_;
+        sc[2] = sr;
+        sc[3] = si;
+        if (blockIdx.x == 0) {
+            off[j] = beta;
+            tau[2 * j] = tr_;
+            tau[2 * j + 1] = ti_;
+            dg[j] = rw[0];
+        }
+    }
+    __syncthreads();
+    const double tr_ = sc[0], ti_ = sc[1], sr = sc[2], si = sc[3];
+    for (int i = tid; i < m; i += RW) {
+        double vr = 1.0, vi = 0.0;
+        if (i > 0) {
+            const double xr = rw[2 * (i + 1)], xi = -rw[2 * (i + 1) + 1];
+            vr = xr * sr - xi * si;
+            vi = xr * si + xi * sr;
+        }
+        v[2 * i] = vr;
+        v[2 * i + 1] = vi;
+        if (blockIdx.x == 0) {
+            refl[2 * ((long)j * n + i)] = vr;
+            refl[2 * ((long)j * n + i) + 1] = vi;
+            vcur[2 * i] = vr;
+            vcur[2 * i + 1] = vi;
+        }
+    }
+    __syncthreads();
+    // rows j+1 .. n-1 of this workgroup: apply column j - 1's update (relative index + 1 in its
+    // vectors), store, and accumulate tau A v of column j
+    const long base = (long)(j + 1) * ld + (j + 1);
+    const int nw = gridDim.x * RWV;
+    for (int r0 = ROWS_PER_WAVE * (blockIdx.x * RWV + w); r0 < m; r0 += ROWS_PER_WAVE * nw) {
+        double ar[ROWS_PER_WAVE], ai[ROWS_PER_WAVE];
+#pragma unroll
+        for (int q = 0; q < ROWS_PER_WAVE; ++q) ar[q] = ai[q] = 0.0;
+        for (int c = lane; c < m; c += 64) {
+            const double vcr = v[2 * c], vci = v[2 * c + 1];
+            double pvr = 0.0, pvi = 0.0, pwr = 0.0, pwi = 0.0;
+            if (upd) {
+                pvr = vp[2 * (c + 1)];
+                pvi = vp[2 * (c + 1) + 1];
+                pwr = wp[2 * (c + 1)];
+                pwi = wp[2 * (c + 1) + 1];
+            }
+#pragma unroll
+            for (int q = 0; q < ROWS_PER_WAVE; ++q) {
+                const int r = r0 + q;
+                if (r < m) {
+                    double* h = H + 2 * (base + (long)r * ld + c);
+                    double hr = h[0], hi = h[1];
+                    if (upd) {
+                        const double vr = vp[2 * (r + 1)], vi = vp[2 * (r + 1) + 1];
+                        const double wr = wp[2 * (r + 1)], wi = wp[2 * (r + 1) + 1];
+                        hr -= vr * pwr + vi * pwi + wr * pvr + wi * pvi;
+                        hi -= vi * pwr - vr * pwi + wi * pvr - wr * pvi;
+                        h[0] = hr;
+                        h[1] = hi;
+                    }
+                    ar[q] += hr * vcr - hi * vci;
+                    ai[q] += hr * vci + hi * vcr;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ROWS_PER_WAVE; ++q) {
+            const double qr = wave_sum(ar[q]), qi = wave_sum(ai[q]);
+            if (lane == 0 && r0 + q < m) {
+                pcur[2 * (r0 + q)] = tr_ * qr - ti_ * qi;
+                pcur[2 * (r0 + q) + 1] = tr_ * qi + ti_ * qr;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ eigenvalues / vectors
 // number of eigenvalues of T below x (Sturm sequence in ratio form with the LAPACK pivot guard)
 __device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
@@ -1078,7 +1097,7 @@ size_t tri_work_bytes(int n) {
     b += P_COUNT * sizeof(double);                // par
     b += (size_t)n * n * 2 * sizeof(double);      // reflector rows
     b += (size_t)n * n * sizeof(double);          // Z
-    b += (size_t)n * 4 * sizeof(double);          // v and p of the multi-workgroup reduction
+    b += (size_t)n * 8 * sizeof(double);          // v and p of the multi-workgroup reduction (two each)
     return b + 1024;
 }
 
@@ -1096,7 +1115,7 @@ hipError_t eigh_top(hipStream_t s, int n, double* H, int ldh, int level, double 
     double* refl = par + P_COUNT;
     double* Z = refl + (size_t)n * n * 2;
     double* vbuf = Z + (size_t)n * n;
-    double* pbuf = vbuf + 2 * (size_t)n;
+    double* pbuf = vbuf + 4 * (size_t)n;
     const double nn = (double)n;
     if (prof) prof->begin(s, PF_TRI_REDUCE);
     if (n <= RMAX)
@@ -1105,13 +1124,10 @@ hipError_t eigh_top(hipStream_t s, int n, double* H, int ldh, int level, double 
     {
         hipLaunchKernelGGL(tri_herm_kernel, dim3(reduce_groups(n)), dim3(RW), 0, s, H, ldh, n);
         hipLaunchKernelGGL(tri_trace_kernel, dim3(1), dim3(RW), 0, s, H, ldh, n, trace);
-        for (int j = 0; j < n - 1; ++j) {
-            const int g = reduce_groups(n - j - 1);
-            hipLaunchKernelGGL(tri_hh_symv_kernel, dim3(g), dim3(RW), 0, s, H, ldh, n, j, dg, off, tv, refl, vbuf,
-                               pbuf);
-            hipLaunchKernelGGL(tri_rank2_kernel, dim3(g), dim3(RW), 0, s, H, ldh, n, j, tv, vbuf, pbuf);
-        }
-        hipLaunchKernelGGL(tri_last_kernel, dim3(1), dim3(64), 0, s, H, ldh, n, dg);
+        // one launch per column; the last one applies column n - 2's update to dg[n - 1]
+        for (int j = 0; j < n; ++j)
+            hipLaunchKernelGGL(tri_col_kernel, dim3(reduce_groups(n - j - 1)), dim3(RW), 0, s, H, ldh, n, j, dg, off,
+                               tv, refl, vbuf, pbuf);
     }
     // Hermitian tridiagonal reduction: 16/3 n^3 real flop; the matrix is read and rewritten
     // once per column
