@@ -560,7 +560,8 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
 //   3. each wave applies A -= v w^H + w v^H (column j - 1) to its rows j+1.. of the trailing
 //      matrix and, in the same pass over the columns, accumulates p = tau A v of column j for
 //      those rows; a lane re-reads only entries it wrote itself.
-// The arithmetic is that of the two-launch form (same formulas, same summation order).
+// The arithmetic is that of applying each column's rank-2 update before the next column's
+// product (same formulas, same summation order); only the launch boundaries move.
 // vbuf and pbuf hold two vectors of n complex entries each (4 n doubles).
 __global__ __launch_bounds__(RW) void tri_col_kernel(double* __restrict__ H, int ld, int n, int j,
                                                      double* __restrict__ dg, double* __restrict__ off,
