@@ -641,8 +641,9 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
                            max_sweeps, evals, V, ldv, nrot);
         if (prof) prof->end(s, PF_EIG_SMALL, 0.0, 32.0 * n * n);
         if (sweeps_used) {
-            hipMemcpyAsync(host_pinned, nrot, sizeof(int), hipMemcpyDeviceToHost, s);
-            hipError_t e = hipStreamSynchronize(s);
+            hipError_t e = hipMemcpyAsync(host_pinned, nrot, sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+            e = hipStreamSynchronize(s);
             if (e != hipSuccess) return e;
             *sweeps_used = host_pinned[0];
         }
@@ -682,8 +683,9 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
                                r, Vp, skip);
             if (prof) prof->end(s, PF_EIG_ROT, rotflop, rotbytes);
         }
-        hipMemcpyAsync(host_pinned, nrot, sizeof(int), hipMemcpyDeviceToHost, s);
-        hipError_t e = hipStreamSynchronize(s);
+        hipError_t e = hipMemcpyAsync(host_pinned, nrot, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
         if (host_pinned[0] == 0) break;
         if (sweep + 1 >= JAC_RELAX_AFTER) abs_factor = std::min(4.0 * abs_factor, 64.0 * n * eps);

@@ -271,7 +271,6 @@ __global__ void sumsq_kernel(CView<T> X, int M, int N, double* __restrict__ out,
 __global__ void spectrum_cut_kernel(const double* __restrict__ lam, int n, int level, double floor2,
                                     double noise, double tau, int cap, double* __restrict__ st,
                                     int* __restrict__ cnt, double* __restrict__ sig, double* __restrict__ inv) {
-    __shared__ double thr;
     __shared__ int c;
     if (threadIdx.x == 0) {
         const double l0 = n > 0 ? lam[0] : 0.0;
@@ -285,7 +284,6 @@ __global__ void spectrum_cut_kernel(const double* __restrict__ lam, int n, int l
         double t = floor2 * st[0];
         if (noise * l0 > t) t = noise * l0;
         if (tau * l0 > t) t = tau * l0;
-        thr = t;
         int k = 0;
         while (k < n && k < cap && lam[k] > t && lam[k] > 0.0) ++k;
         if (!(l0 > 0.0)) k = 0;
@@ -407,7 +405,6 @@ __global__ void ppt_kernel(const double* __restrict__ sig, const double* __restr
         __syncthreads();
     }
     __shared__ double xs, cterm, scale_all;
-    __shared__ int feasible, degen;
     if (tid == 0) {
         const double tt = red[0][0], tl_ = red[1][0], ll = red[2][0];
         const double trr = sc[0], n2 = sc[4];
@@ -438,8 +435,6 @@ __global__ void ppt_kernel(const double* __restrict__ sig, const double* __restr
         //          = (1 + x) Lambda' - x (T'.Lambda' / |T'|^2) T'
         xs = dg ? 0.0 : x;
         cterm = (nT > 0.0) ? tl_ / tt : 0.0;
-        feasible = feas;
-        degen = dg;
         out[0] = trr;                         // tr rho before
         out[1] = n2 > 0.0 ? n2 / (trr * trr) : 0.0;  // xi before
         out[2] = theta;
