@@ -41,6 +41,8 @@
  *   MPDO_GEMM_AUTOTUNE=1        time the launch plan (tile size and k split) of each GEMM
  *                               shape bucket on first use and keep the fastest (default: a
  *                               cost model of matrix-core time per compute unit)
+ *   MPDO_JACOBI_INNER_SWEEPS=k  sweeps of each 32 x 32 pair problem per round of the block
+ *                               Jacobi solver (orders above 1024; default 1)
  */
 #ifndef MPDO_H
 #define MPDO_H

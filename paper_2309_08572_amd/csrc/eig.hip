@@ -650,10 +650,10 @@ hipError_t eigh(hipStream_t s, int n, double* H, int ldh, double* V, int ldv, do
         return hipGetLastError();
     }
     hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, H, ldh, n, fro);
-    static int inner_sweeps = -1;
-    if (inner_sweeps < 0) {
-        const char* e = getenv("MPDO_JACOBI_INNER_SWEEPS");
-        inner_sweeps = e ? atoi(e) : 1;
+    // read per call (no shared state between the batch workers' threads)
+    int inner_sweeps = 1;
+    if (const char* e = getenv("MPDO_JACOBI_INNER_SWEEPS")) {
+        inner_sweeps = atoi(e);
         if (inner_sweeps < 1) inner_sweeps = 1;
     }
     const long nn = (long)n * n;
