@@ -656,12 +656,7 @@ struct Engine {
                 gemm(a, a, b, C1(), R, adj(R), C0(), V<T>(s.bG, a, 1));
                 HIPCHK((geam<T, double>(st, a, a, C1(), V<T>(s.bG, a, 1), C0(), V<double>(s.Gd, a, 1))));
             }
-            // level 0 takes lambda > 1e-6 lambda_max: its eigenvalues carry an absolute error of
-            // ~eps lambda_max, 2e-10 of the smallest it accepts, so the order of near-ties there
-            // is resolved to that; smaller values are left to the residual levels, whose
-            // lambda_max is smaller.  (Schmidt values for PPT are row norms of U^H F, not these
-            // eigenvalues.)
-            const double tau = (lev == 0) ? 1e-6 : 0.0;
+            const double tau = (lev == 0) ? 1e-4 : 0.0;
             const int acc = eig_cut(a, lev, std::max(c.cutoff * c.cutoff, rfloor), noise_of(a), tau, chi - kacc,
                                     s.sig + kacc, s.inv);
             if (acc <= 0) break;
