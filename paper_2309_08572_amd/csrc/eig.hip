@@ -81,6 +81,78 @@ __device__ __forceinline__ void circle_pair(int players, int round, int j, int& 
     }
 }
 
+constexpr int JAC_ITEMS = 3;   // updates per thread per round in every launch of this solver
+
+// One update of a round: the 2 x 2 block (rows of pair a) x (columns of pair b) of H.
+template <int N>
+__device__ __forceinline__ void jac_h_item(PairLds<N>& L, int a, int b) {
+    // H block: rows {p_a, q_a} x columns {p_b, q_b}
+    const double sa = L.s[a], sb = L.s[b];
+    if (sa == 0.0 && sb == 0.0) return;
+    const int pa = L.p[a], qa = L.q[a], pb = L.p[b], qb = L.q[b];
+    double h11r = L.Hr[pa][pb], h11i = L.Hi[pa][pb];
+    double h12r = L.Hr[pa][qb], h12i = L.Hi[pa][qb];
+    double h21r = L.Hr[qa][pb], h21i = L.Hi[qa][pb];
+    double h22r = L.Hr[qa][qb], h22i = L.Hi[qa][qb];
+    if (sa != 0.0) {
+        // rows: new_p = c h_p - s e h_q ; new_q = s h_p + c e h_q
+        const double c = L.c[a], er = L.er[a], ei = L.ei[a];
+        const double e1r = er * h21r - ei * h21i, e1i = er * h21i + ei * h21r;
+        const double e2r = er * h22r - ei * h22i, e2i = er * h22i + ei * h22r;
+        const double n11r = c * h11r - sa * e1r, n11i = c * h11i - sa * e1i;
+        const double n12r = c * h12r - sa * e2r, n12i = c * h12i - sa * e2i;
+        h21r = sa * h11r + c * e1r;
+        h21i = sa * h11i + c * e1i;
+        h22r = sa * h12r + c * e2r;
+        h22i = sa * h12i + c * e2i;
+        h11r = n11r;
+        h11i = n11i;
+        h12r = n12r;
+        h12i = n12i;
+    }
+    if (sb != 0.0) {
+        // columns: new_p = c x_p - s conj(e) x_q ; new_q = s x_p + c conj(e) x_q
+        const double c = L.c[b], er = L.er[b], ei = -L.ei[b];
+        const double e1r = er * h12r - ei * h12i, e1i = er * h12i + ei * h12r;
+        const double e2r = er * h22r - ei * h22i, e2i = er * h22i + ei * h22r;
+        const double n11r = c * h11r - sb * e1r, n11i = c * h11i - sb * e1i;
+        const double n21r = c * h21r - sb * e2r, n21i = c * h21i - sb * e2i;
+        h12r = sb * h11r + c * e1r;
+        h12i = sb * h11i + c * e1i;
+        h22r = sb * h21r + c * e2r;
+        h22i = sb * h21i + c * e2i;
+        h11r = n11r;
+        h11i = n11i;
+        h21r = n21r;
+        h21i = n21i;
+    }
+    L.Hr[pa][pb] = h11r;
+    L.Hi[pa][pb] = h11i;
+    L.Hr[pa][qb] = h12r;
+    L.Hi[pa][qb] = h12i;
+    L.Hr[qa][pb] = h21r;
+    L.Hi[qa][pb] = h21i;
+    L.Hr[qa][qb] = h22r;
+    L.Hi[qa][qb] = h22i;
+}
+
+// One update of a round: row k of V on the columns of pair b.
+template <int N>
+__device__ __forceinline__ void jac_v_item(PairLds<N>& L, int b, int k) {
+    // V <- V J on the columns of pair b, row k
+    const double sb = L.s[b];
+    if (sb == 0.0) return;
+    const double c = L.c[b], er = L.er[b], ei = -L.ei[b];
+    const int pb = L.p[b], qb = L.q[b];
+    const double xpr = L.Vr[k][pb], xpi = L.Vi[k][pb];
+    const double xqr = L.Vr[k][qb], xqi = L.Vi[k][qb];
+    const double eqr = er * xqr - ei * xqi, eqi = er * xqi + ei * xqr;
+    L.Vr[k][pb] = c * xpr - sb * eqr;
+    L.Vi[k][pb] = c * xpi - sb * eqi;
+    L.Vr[k][qb] = sb * xpr + c * eqr;
+    L.Vi[k][qb] = sb * xpi + c * eqi;
+}
+
 // Diagonalise the Hermitian n x n matrix in L (n even, <= 64); L.V accumulates the
 // rotations (starts as identity).  Each round computes the rotations of the n/2 disjoint
 // pairs, then applies H <- J^+ H J and V <- V J in one pass: a thread owns the 2 x 2 block
@@ -91,6 +163,27 @@ __device__ int lds_jacobi(PairLds<N>& L, int n, double tol_rel, double tol_abs, 
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     const int half = n / 2;
+    // A round has half^2 H-block and half * n V-row updates.  Every launch of this solver gives
+    // a thread at most JAC_ITEMS of them, the same ones in every round: their indices are
+    // computed once here instead of by two integer divisions per update per round.
+    const int total = half * half + half * n;
+    const bool fixed = total <= JAC_ITEMS * nt;
+    int kind[JAC_ITEMS], ia[JAC_ITEMS], ib[JAC_ITEMS];
+#pragma unroll
+    for (int q = 0; q < JAC_ITEMS; ++q) {
+        const int idx = tid + q * nt;
+        kind[q] = -1;
+        ia[q] = ib[q] = 0;
+        if (idx < half * half) {
+            kind[q] = 0;
+            ia[q] = idx / half;
+            ib[q] = idx - ia[q] * half;
+        } else if (idx < total) {
+            kind[q] = 1;
+            ia[q] = (idx - half * half) / n;
+            ib[q] = (idx - half * half) - ia[q] * n;
+        }
+    }
     int sweeps = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         if (tid == 0) L.flag = 0;
@@ -141,72 +234,20 @@ __device__ int lds_jacobi(PairLds<N>& L, int n, double tol_rel, double tol_abs, 
             }
             __syncthreads();
             const int nh = half * half;
-            for (int idx = tid; idx < nh + half * n; idx += nt) {
-                if (idx < nh) {
-                    // H block: rows {p_a, q_a} x columns {p_b, q_b}
-                    const int a = idx / half, b = idx - (idx / half) * half;
-                    const double sa = L.s[a], sb = L.s[b];
-                    if (sa == 0.0 && sb == 0.0) continue;
-                    const int pa = L.p[a], qa = L.q[a], pb = L.p[b], qb = L.q[b];
-                    double h11r = L.Hr[pa][pb], h11i = L.Hi[pa][pb];
-                    double h12r = L.Hr[pa][qb], h12i = L.Hi[pa][qb];
-                    double h21r = L.Hr[qa][pb], h21i = L.Hi[qa][pb];
-                    double h22r = L.Hr[qa][qb], h22i = L.Hi[qa][qb];
-                    if (sa != 0.0) {
-                        // rows: new_p = c h_p - s e h_q ; new_q = s h_p + c e h_q
-                        const double c = L.c[a], er = L.er[a], ei = L.ei[a];
-                        const double e1r = er * h21r - ei * h21i, e1i = er * h21i + ei * h21r;
-                        const double e2r = er * h22r - ei * h22i, e2i = er * h22i + ei * h22r;
-                        const double n11r = c * h11r - sa * e1r, n11i = c * h11i - sa * e1i;
-                        const double n12r = c * h12r - sa * e2r, n12i = c * h12i - sa * e2i;
-                        h21r = sa * h11r + c * e1r;
-                        h21i = sa * h11i + c * e1i;
-                        h22r = sa * h12r + c * e2r;
-                        h22i = sa * h12i + c * e2i;
-                        h11r = n11r;
-                        h11i = n11i;
-                        h12r = n12r;
-                        h12i = n12i;
-                    }
-                    if (sb != 0.0) {
-                        // columns: new_p = c x_p - s conj(e) x_q ; new_q = s x_p + c conj(e) x_q
-                        const double c = L.c[b], er = L.er[b], ei = -L.ei[b];
-                        const double e1r = er * h12r - ei * h12i, e1i = er * h12i + ei * h12r;
-                        const double e2r = er * h22r - ei * h22i, e2i = er * h22i + ei * h22r;
-                        const double n11r = c * h11r - sb * e1r, n11i = c * h11i - sb * e1i;
-                        const double n21r = c * h21r - sb * e2r, n21i = c * h21i - sb * e2i;
-                        h12r = sb * h11r + c * e1r;
-                        h12i = sb * h11i + c * e1i;
-                        h22r = sb * h21r + c * e2r;
-                        h22i = sb * h21i + c * e2i;
-                        h11r = n11r;
-                        h11i = n11i;
-                        h21r = n21r;
-                        h21i = n21i;
-                    }
-                    L.Hr[pa][pb] = h11r;
-                    L.Hi[pa][pb] = h11i;
-                    L.Hr[pa][qb] = h12r;
-                    L.Hi[pa][qb] = h12i;
-                    L.Hr[qa][pb] = h21r;
-                    L.Hi[qa][pb] = h21i;
-                    L.Hr[qa][qb] = h22r;
-                    L.Hi[qa][qb] = h22i;
-                } else {
-                    // V <- V J on the columns of pair b, row k
-                    const int rem = idx - nh;
-                    const int b = rem / n, k = rem - (rem / n) * n;
-                    const double sb = L.s[b];
-                    if (sb == 0.0) continue;
-                    const double c = L.c[b], er = L.er[b], ei = -L.ei[b];
-                    const int pb = L.p[b], qb = L.q[b];
-                    const double xpr = L.Vr[k][pb], xpi = L.Vi[k][pb];
-                    const double xqr = L.Vr[k][qb], xqi = L.Vi[k][qb];
-                    const double eqr = er * xqr - ei * xqi, eqi = er * xqi + ei * xqr;
-                    L.Vr[k][pb] = c * xpr - sb * eqr;
-                    L.Vi[k][pb] = c * xpi - sb * eqi;
-                    L.Vr[k][qb] = sb * xpr + c * eqr;
-                    L.Vi[k][qb] = sb * xpi + c * eqi;
+            if (fixed) {
+#pragma unroll
+                for (int q = 0; q < JAC_ITEMS; ++q) {
+                    if (kind[q] == 0)
+                        jac_h_item(L, ia[q], ib[q]);
+                    else if (kind[q] == 1)
+                        jac_v_item(L, ia[q], ib[q]);
+                }
+            } else {
+                for (int idx = tid; idx < nh + half * n; idx += nt) {
+                    if (idx < nh)
+                        jac_h_item(L, idx / half, idx - (idx / half) * half);
+                    else
+                        jac_v_item(L, (idx - nh) / n, (idx - nh) - ((idx - nh) / n) * n);
                 }
             }
             __syncthreads();
