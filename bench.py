@@ -121,15 +121,21 @@ def _second_order(spec, reps: int) -> dict:
 
 
 def _saturated(max_warm: int, precisions) -> dict:
-    """The saturated steady state at chi = 512: the benchmark circuit's gate set (seed-0 angles,
-    rates 1e-3) on a 20-atom chain, layers run untimed until the three centre bonds are at 512
-    (at most `max_warm` layers; six in FP64, seven in FP32), then one more layer in which only
-    the two-site updates whose three bonds are all 512 (theta of 8192 x 8192 at rank <= 4608)
-    are timed, each bracketed by synchronisations.  The FP32 run uses a cutoff of 1e-12
-    sigma_1 instead of its default 1e-6 so that its bonds grow to the same size; its energy
-    is compared with the FP64 run's after the same number of layers where both ran as many.
-    FP32 products resolve Schmidt values only down to their rounding floor, so the FP32 run
-    may not saturate at all; its record then shows no timed updates and its largest bond."""
+    """The saturated steady state at chi = 512, FP32 matrix cores against FP64 on the same updates.
+
+    The benchmark circuit's gate set (seed-0 angles, rates 1e-3) runs on a 20-atom chain in FP64,
+    untimed, layer by layer until the three centre bonds are at 512 (at most `max_warm` layers),
+    then through the even bonds of one more layer.  After the even bonds every atom has taken
+    its queued single-atom maps, so the state is the chain alone.  Each update of the odd bonds
+    whose three bonds are all 512 (theta of 8192 x 8192, rank <= 4608) is then run twice from
+    the same state, the canonical centre already on the pair (moved there untimed in FP64): by
+    the FP64 context, and by an FP32 context loaded with that state (mpdo_set_state with the
+    FP64 context's canonical centre).  Both are timed, bracketed by
+    synchronisations, with HIP events on the theta contraction (merge and gate products), the
+    other products and the eigensolver families; after each, the per-site energy and the
+    populations of the two results are compared.  The per-update cost does not depend on N
+    (only on the three bond dimensions and d), so the 20-atom chain stands for the saturated
+    bulk of the N=100 chain."""
     import numpy as np
     import torch
     from paper_2309_08572_amd import circuits, mpdo
@@ -137,73 +143,114 @@ def _saturated(max_warm: int, precisions) -> dict:
     n, chi = 20, 512
     spec = config_m3(0, n=n, p=10, chi=chi)          # one fixed angle set for up to 10 layers
     max_warm = min(max_warm, spec.p - 1)
-    modes = {"fp64": mpdo.MPDO_FP64, "fp32": mpdo.MPDO_FP32}
-    res = {}
+    d = spec.d
 
-    def layer(m, k, timed):
-        kr = circuits.block_kraus(spec.gamma[k], spec.p_leak, spec.d)
-        times, prof = [], None
-        for i in circuits.bond_order(n):
-            b = m.bond_dims()
-            sat = 0 < i < n - 2 and b[i - 1] >= chi and b[i] >= chi and b[i + 1] >= chi
-            if timed and sat:
-                m.profile(True)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-            m.apply_gate_kraus(i, kr)
-            if timed and sat:
-                m.synchronize()
-                times.append(time.perf_counter() - t0)
-                p = m.profile_read()
-                m.profile(False)
-                prof = p if prof is None else {f: {q: prof[f][q] + p[f][q] for q in p[f]} for f in p}
+    def maps(m, k):
         for j in range(n):
-            m.apply_channel(j, [circuits.x_rotation(spec.beta[k], spec.d)])
-            m.apply_channel(j, circuits.dephasing_kraus(spec.p_deph, spec.d))
-            m.apply_channel(j, circuits.decay_kraus(spec.p_decay, spec.d))
-        return times, prof
+            m.apply_channel(j, [circuits.x_rotation(spec.beta[k], d)])
+            m.apply_channel(j, circuits.dephasing_kraus(spec.p_deph, d))
+            m.apply_channel(j, circuits.decay_kraus(spec.p_decay, d))
 
-    for name in precisions:
-        m = mpdo.MPDO(n, spec.d, chi, precision=modes[name], cutoff_rel=1e-14 if name == "fp64" else 1e-12)
-        m.init_product_state([circuits.plus_rho(spec.d)] * n)
-        warm = 0
-        while warm < max_warm and min(m.bond_dims()[n // 2 - 2:n // 2 + 1]) < chi:
-            layer(m, warm, False)
-            warm += 1
-        times, prof = layer(m, warm, True)
-        obs = circuits.observables(m)
-        g = prof["gemm"] if prof else {"flops": 0.0, "ms": 0.0, "launches": 0}
-        t = float(np.sum(times)) if times else 0.0
-        res[name] = {
-            "untimed_layers": warm,
-            "saturated_updates": len(times),
-            "updates_per_s": len(times) / t if t else 0.0,
-            "ms_per_update": 1e3 * t / len(times) if times else 0.0,
-            "gemm_tflops_per_update_time": g["flops"] / t / 1e12 if t else 0.0,
-            "gemm": {"launches": g["launches"], "ms": g["ms"], "flop": g["flops"],
-                     "achieved_tflops": g["flops"] / (1e-3 * g["ms"]) / 1e12 if g["ms"] else 0.0,
-                     "peak_tflops": PEAK["fp64_mfma"] if name == "fp64" else PEAK["fp32_mfma"]},
-            "roofline": {"bound": "mfma", "kernel_family": "gemm",
-                         "achieved": g["flops"] / (1e-3 * g["ms"]) / 1e12 if g["ms"] else 0.0,
-                         "peak": PEAK["fp64_mfma"] if name == "fp64" else PEAK["fp32_mfma"], "unit": "TFLOP/s",
-                         "frac": (g["flops"] / (1e-3 * g["ms"]) / 1e12 if g["ms"] else 0.0) /
-                                 (PEAK["fp64_mfma"] if name == "fp64" else PEAK["fp32_mfma"]),
-                         "traffic": None, "launches": g["launches"],
-                         "avg_launch_us": 1e3 * g["ms"] / g["launches"] if g["launches"] else 0.0},
-            "kernel_ms": {f: v["ms"] for f, v in (prof or {}).items() if v["launches"]},
-            "energy_per_site": obs["energy_per_site"],
-            "max_bond": max(m.bond_dims()),
+    a = mpdo.MPDO(n, d, chi, precision=mpdo.MPDO_FP64)
+    a.init_product_state([circuits.plus_rho(d)] * n)
+    warm = 0
+    while warm < max_warm and min(a.bond_dims()[n // 2 - 2:n // 2 + 1]) < chi:
+        kr = circuits.block_kraus(spec.gamma[warm], spec.p_leak, d)
+        for i in circuits.bond_order(n):
+            a.apply_gate_kraus(i, kr)
+        maps(a, warm)
+        warm += 1
+    kr = circuits.block_kraus(spec.gamma[warm], spec.p_leak, d)
+    for i in range(0, n - 1, 2):
+        a.apply_gate_kraus(i, kr)
+    b = mpdo.MPDO(n, d, chi, precision=mpdo.MPDO_FP32) if "fp32" in precisions else None
+    fams = ("theta", "gemm", "tri_reduce", "tri_solve", "tri_back", "eig_small", "phys", "other")
+    acc = {"fp64": {"t": [], "prof": None, "kept": []}, "fp32": {"t": [], "prof": None, "kept": []}}
+    errs_e, errs_p = [], []
+
+    def timed(m, i, key):
+        m.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf = m.apply_gate_kraus(i, kr, info=True)
+        m.synchronize()
+        acc[key]["t"].append(time.perf_counter() - t0)
+        p = m.profile_read()
+        m.profile(False)
+        pr = acc[key]["prof"]
+        acc[key]["prof"] = p if pr is None else {f: {q: pr[f][q] + p[f][q] for q in p[f]} for f in p}
+        acc[key]["kept"].append(inf["kept"])
+        return inf
+
+    for i in list(range(1, n - 1, 2))[::-1]:
+        bd = a.bond_dims()
+        sat = 0 < i < n - 2 and bd[i - 1] >= chi and bd[i] >= chi and bd[i + 1] >= chi
+        if not sat:
+            a.apply_gate_kraus(i, kr)
+            continue
+        # the centre moves onto the pair first (untimed, in FP64), so that both precisions time
+        # the update alone and the FP32 context starts from exactly the FP64 chain (an FP32
+        # canonical move would itself compress the bonds it crosses to what FP32 resolves)
+        a.move_centre(i + 1)
+        if b is not None:
+            bonds, sites, centre = a.get_state()
+            b.set_state(bonds, sites, centre)
+            del sites
+            timed(b, i, "fp32")
+        timed(a, i, "fp64")
+        if b is not None:
+            oa, ob = circuits.observables(a), circuits.observables(b)
+            errs_e.append(abs(oa["energy_per_site"] - ob["energy_per_site"]))
+            errs_p.append(float(np.max(np.abs(oa["populations"] - ob["populations"]))))
+    res = {}
+    for key in ("fp64", "fp32"):
+        t, prof = acc[key]["t"], acc[key]["prof"]
+        if not t:
+            continue
+        tot = float(np.sum(t))
+        peak = PEAK["fp64_mfma"] if key == "fp64" else PEAK["fp32_mfma"]
+        fam_rec = {}
+        for f in fams:
+            v = prof[f]
+            if not v["launches"]:
+                continue
+            r = {"launches": v["launches"], "ms": v["ms"], "share_of_update_time": 1e-3 * v["ms"] / tot}
+            if f in ("theta", "gemm"):
+                r["flop"] = v["flops"]
+                r["tflops"] = v["flops"] / (1e-3 * v["ms"]) / 1e12 if v["ms"] else 0.0
+                r["frac_of_peak"] = r["tflops"] / peak
+            fam_rec[f] = r
+        th = prof["theta"]
+        res[key] = {
+            "saturated_updates": len(t),
+            "updates_per_s": len(t) / tot,
+            "ms_per_update": 1e3 * tot / len(t),
+            "kept": acc[key]["kept"],
+            "families": fam_rec,
+            # algorithmic a2 work per update at chi = 512, d = 4: merge 2.75e11 + gate 1.37e11 flop
+            "theta_contraction": {"flop_per_update_algorithmic": 4.12e11,
+                                  "ms_per_update": th["ms"] / len(t),
+                                  "tflops": th["flops"] / (1e-3 * th["ms"]) / 1e12 if th["ms"] else 0.0,
+                                  "peak_tflops": peak,
+                                  "frac": (th["flops"] / (1e-3 * th["ms"]) / 1e12 / peak) if th["ms"] else 0.0},
+            # every executed product (theta, subspace passes, Grams, rebuild) over the update time
+            "gemm_executed_tflops_per_update_time": (prof["gemm"]["flops"] + th["flops"]) / tot / 1e12,
+            "mfma_algorithmic_tflops_per_update_time": 2.9e12 * len(t) / tot / 1e12,
         }
-        m.close()
-    out = {"workload": f"noisy QAOA gate set, N={n} atoms, d=4, chi_max={chi}, seed 0, rates 1e-3: untimed "
-                       f"layers until the centre bonds reach {chi}, then the updates of the next layer with "
-                       f"chi_l = chi_m = chi_r = {chi}",
-           **res}
-    if "fp64" in res and "fp32" in res and res["fp32"]["updates_per_s"] and res["fp64"]["updates_per_s"]:
-        out["fp32_speedup_vs_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
-        if res["fp32"]["untimed_layers"] == res["fp64"]["untimed_layers"]:
-            out["fp32_abs_err_energy_per_site_vs_fp64"] = abs(res["fp32"]["energy_per_site"] -
-                                                              res["fp64"]["energy_per_site"])
+    a.close()
+    if b is not None:
+        b.close()
+    out = {"workload": f"noisy QAOA gate set, N={n} atoms, d=4, chi_max={chi}, seed 0, rates 1e-3: FP64 layers "
+                       f"until the centre bonds reach {chi} ({warm} layers), the even bonds of the next; then each "
+                       f"odd-bond update with chi_l = chi_m = chi_r = {chi} run from the same state in FP64 and "
+                       f"in FP32 (state loaded with mpdo_set_state)",
+           "untimed_layers": warm, **res}
+    if "fp64" in res and "fp32" in res:
+        out["fp32_speedup_vs_fp64"] = res["fp64"]["ms_per_update"] / res["fp32"]["ms_per_update"]
+        out["fp32_theta_speedup_vs_fp64"] = (res["fp64"]["theta_contraction"]["ms_per_update"] /
+                                             res["fp32"]["theta_contraction"]["ms_per_update"])
+        out["fp32_abs_err_energy_per_site_vs_fp64_max"] = max(errs_e)
+        out["fp32_abs_err_populations_vs_fp64_max"] = max(errs_p)
     return out
 
 
@@ -316,7 +363,7 @@ def roofline_of(prof: dict, fam: str, fp64: bool) -> dict:
     n = max(1, d["launches"])
     avg_s = d["ms"] * 1e-3 / n
     flop, byts = d["flops"] / n, d["bytes"] / n
-    if fam in ("gemm", "eig_rotate"):
+    if fam in ("gemm", "theta", "eig_rotate"):
         peak = PEAK["fp64_mfma"] if (fp64 or fam == "eig_rotate") else PEAK["fp32_mfma"]
         ach = flop / avg_s / 1e12 if avg_s > 0 else 0.0
         rf = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s"}
@@ -354,7 +401,8 @@ def _truncation_summary(infos, obs) -> dict:
             "trace_drift_per_update_max": float(max(tdrift) if tdrift else 0.0),
             "trace_drift_circuit": float(abs(complex(tr) - 1.0)),
             "xi_rel_change_per_update_max": float(max(xdrift) if xdrift else 0.0),
-            "ppt_infeasible": int(sum(1 for i in infos if not i["ppt_feasible"]))}
+            "ppt_infeasible": int(sum(1 for i in infos if not i["ppt_feasible"])),
+            "updates_recomputed": int(sum(i.get("retried", 0) for i in infos))}
 
 
 def main() -> int:
@@ -367,7 +415,7 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "fp32", "both"], default="both")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-circuits", type=int, default=0,
+    ap.add_argument("--batch-circuits", type=int, default=32,
                     help="also time this many circuits of the 256-circuit batch workload "
                          "(one per worker stream vs one at a time)")
     ap.add_argument("--workers", type=int, default=16)
@@ -453,8 +501,10 @@ def main() -> int:
                    "n": spec.n, "d": spec.d, "chi_max": spec.chi, "p": spec.p,
                    "updates_per_step": updates, "max_bond_reached": r["bonds"]},
     }
-    gemm = r["prof"]["gemm"]
-    out["tflops_gemm_algorithmic"] = (gemm["flops"] / (1e-3 * gemm["ms"]) / 1e12) if gemm["ms"] else 0.0
+    # executed product flop (every GEMM the update ran, theta included) over their event time
+    gf = r["prof"]["gemm"]["flops"] + r["prof"]["theta"]["flops"]
+    gms = r["prof"]["gemm"]["ms"] + r["prof"]["theta"]["ms"]
+    out["tflops_gemm_executed"] = (gf / (1e-3 * gms) / 1e12) if gms else 0.0
     out["roofline"] = roofline_of(r["prof_timed"], r["fam"], main_mode == "fp64")
     # the breakdown below comes from the untimed profiled step (events around every launch)
     out["kernel_time_share"] = {k: v["ms"] / (1e3 * r["profiled_seconds"]) for k, v in r["prof"].items()

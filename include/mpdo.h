@@ -25,13 +25,18 @@
  * Numerical safeguards of the two-site update (apply_gate, apply_gate_kraus, truncate)
  *  - Every orthonormal basis built by the split (range bases, Schmidt vectors) is checked
  *    before the new sites are written: ||Q||_F^2 must equal its column count to 1e-9 (FP64)
- *    or 1e-3 (FP32) with no non-finite entry, otherwise the update returns MPDO_E_NUMERIC
- *    ("orthonormal basis lost accuracy") instead of committing a wrong state.
+ *    or 1e-3 (FP32) with no non-finite entry.  The check runs before the pair's new sites are
+ *    written; an update that fails it is recomputed once from the same sites, and a second
+ *    failure returns MPDO_E_NUMERIC ("orthonormal basis lost accuracy", naming the basis)
+ *    instead of committing a wrong state.
+ *  - Products whose k range is split over workgroups add their partial tiles in a fixed order,
+ *    so a call gives the same result bits on every run.
  *  - Splits whose exact range basis would need a Hermitian eigenproblem above order 1024
- *    (the saturated chi = 512 regime) build the basis of the dominant left singular subspace
- *    by block subspace iteration (chi + 256 directions, stopped when the captured weight
- *    changes by less than 1e-10 of itself) and split its core exactly; the weight it misses
- *    lies below the chi cut.
+ *    (the saturated chi = 512 regime) form theta explicitly, build the basis of its dominant
+ *    left singular subspace by block subspace iteration (chi + 256 directions, stopped when
+ *    the captured weight changes by less than 1e-10 of itself) and split its core exactly;
+ *    the weight it misses lies below the chi cut.  tr(rho) and ||theta||_F^2, which PPT
+ *    reads (Eq. (xiformula)), are taken from the whole theta.
  *
  * Environment (read at each use)
  *   MPDO_DEBUG_CHECKS=1         print every orthonormality check and block-Jacobi sweep count
@@ -100,6 +105,20 @@ typedef struct {
     double max_abs_imag_t;  /* largest |Im T'_i Lambda'_i| relative to |tr rho|          */
     double sigma_max;       /* largest Schmidt value                                     */
     double sigma_min_kept;  /* smallest kept Schmidt value                               */
+    double sigma_next;      /* largest discarded Schmidt value: exact (to the Gram
+                               eigenvalue's accuracy, ~sqrt(eps) sigma_max) when the chi
+                               cap made the cut at a deflation level that resolved it;
+                               otherwise an upper bound from that level's acceptance
+                               threshold; 0 when the cut was not made by chi (everything
+                               dropped lies below cutoff_rel or the rounding floor)      */
+    double sigma_gap_at_cut;/* sigma_min_kept - sigma_next.  Where it is ~0 (a tie at
+                               the cut) the truncated state is not unique (Sec. III.A
+                               cuts the least significant values; the paper does not say
+                               how ties are broken): results may differ from another
+                               correct implementation by the weight of the tied pair    */
+    int sigma_next_exact;   /* 1 when sigma_next is the resolved value, 0 for a bound    */
+    int retried;            /* 1 when the update was recomputed after a failed basis
+                               check (see the safeguards above), else 0                 */
 } mpdo_trunc_info;
 
 /* Create a context for a chain described by cfg.  Allocates nothing on the device until
@@ -208,6 +227,32 @@ mpdo_status mpdo_bond_dims(mpdo_ctx ctx, int* out);
  * applied); shape[0..2] receives its dimensions.  out may be NULL to query the shape. */
 mpdo_status mpdo_get_site(mpdo_ctx ctx, int site, double* out, int* shape);
 
+/* Replace the chain by the caller's site tensors (Sec. III, Eq. (MPO)), for instance the state
+ * of another context of the same chain read back with mpdo_get_site, possibly in the other
+ * precision.  bond_dims: N-1 bond dimensions (bond j between atoms j and j+1), each in
+ * [1, chi_max].  sites: the N tensors concatenated, each complex [chi_l][D2][chi_r] (host,
+ * interleaved doubles), converted to the working precision.  centre >= 0: the caller vouches
+ * that every site left of `centre` is a left isometry and every site right of it a right
+ * isometry (the mixed canonical form of Sec. III.A that PPT relies on; mpdo_canonical_centre
+ * returns it for a context's own state).  centre = -1: the library brings the chain into that
+ * form itself by range-basis moves from atom 0 to atom N-1 (rho is kept to rounding; nothing
+ * is cut) and the centre ends on atom N-1.  Queued single-atom channels are cleared.
+ * E_ARG for a null pointer, a bond outside [1, chi_max], a non-finite entry or centre
+ * outside [-1, N-1]. */
+mpdo_status mpdo_set_state(mpdo_ctx ctx, const int* bond_dims, const double* sites, int centre);
+
+/* out[0]: the atom holding the canonical centre; out[1]: +1 or -1, the direction of the last
+ * sweep (the side of the pair the centre moves to after the next update). */
+mpdo_status mpdo_canonical_centre(mpdo_ctx ctx, int* out);
+
+/* Move the canonical centre to atom `site` (the canonisation identities of Sec. III.A) by
+ * range-basis moves across the bonds in between: every site passed becomes a left (moving
+ * right) or right (moving left) isometry.  rho is kept: a move drops only directions below the
+ * rounding floor of the working precision (1e-14 relative in FP64; in FP32 the floor of FP32
+ * products, so an FP32 move can shrink a bond that carries values below it).  E_ARG for a site
+ * outside [0, N-1] or before a state exists. */
+mpdo_status mpdo_move_centre(mpdo_ctx ctx, int site);
+
 /* ---------------------------------------------------------------- batches of circuits
  * Many independent circuits (QAOA angle sets x noise rates, of uneven N and chi): each is
  * an ordered list of Kraus maps applied to a product state, then linear observables.
@@ -258,7 +303,9 @@ enum {
     MPDO_PROF_TRI_REDUCE = 7,  /* Householder reduction to tridiagonal form (one workgroup)    */
     MPDO_PROF_TRI_SOLVE = 8,   /* bisection + inverse iteration for the accepted eigenpairs    */
     MPDO_PROF_TRI_BACK = 9,    /* back-transformation of the accepted eigenvectors             */
-    MPDO_PROF_FAMILIES = 10
+    MPDO_PROF_THETA = 10,      /* the theta contraction: the merge and gate products that form
+                                  theta explicitly (GEMM kernel, timed apart from family 0)    */
+    MPDO_PROF_FAMILIES = 11
 };
 
 /* Measurement switch (instrumentation, not part of the method): with enable = 1 the

@@ -27,6 +27,7 @@
 
 #include "../../include/mpdo.h"
 #include "common.h"
+#include "chol.h"
 #include "eig.h"
 #include "tri.h"
 #include "gemm.h"
@@ -48,6 +49,8 @@ constexpr int EIG_JACOBI_MAX = 32;   // largest order eig_cut gives to the Jacob
 // tolerance (relative; FP64 1e-10, FP32 1e-6), far below the weight a chi-cut discards there.
 constexpr int SUB_OVER = 256;
 constexpr int SUB_ITERS = 8;
+// largest block the subspace iteration orthonormalises by shifted Cholesky QR
+constexpr int CHOL_MAX = 2048;
 
 // Order above which a split uses the subspace iteration: TRI_MAX, or MPDO_SUBSPACE_MIN_ORDER
 // from the environment (lower values let tests run the subspace path where the exact path
@@ -61,6 +64,7 @@ int subspace_min_order() {
 struct Fail {
     mpdo_status st;
     std::string msg;
+    bool retry = false;   // an update that failed this way may be recomputed once
 };
 
 #define HIPCHK(expr)                                                                          \
@@ -117,7 +121,15 @@ struct Scratch {
     unsigned* sqc;  // arrival counter of sumsq (0 between calls)
     int* cnt;
     void* eigwork;
+    void* skw;           // partial tiles of k-split products (GemmOpts::ws)
+    size_t skw_bytes;
+    double* cholw;       // Cholesky QR: shift and diagonal-block inverses (order <= CHOL_MAX)
 
+    // k-split workspace: eight n_max^2 complex outputs, capped at 128 MiB
+    static size_t split_ws_bytes(int nmax) {
+        const size_t b = (size_t)8 * nmax * nmax * 2 * sizeof(T);
+        return std::max((size_t)1 << 20, std::min(b, (size_t)128 << 20));
+    }
     static size_t bytes(int nmax) {
         const size_t n2 = (size_t)nmax * nmax * 2;
         size_t b = 0;
@@ -126,6 +138,8 @@ struct Scratch {
         b += 14 * ((size_t)nmax * 2 * sizeof(double) + 256) + 4096 + 2048;
         b += 2 * SUMSQ_MAX_BLOCKS * sizeof(double) + 256 + 256;   // sumsq partials and counter
         b += eigh_work_bytes(nmax) + 256;
+        b += split_ws_bytes(nmax) + 256;
+        b += chol_work_doubles(CHOL_MAX) * sizeof(double) + 256;
         return b;
     }
     void carve(Arena& a, int n) {
@@ -167,6 +181,9 @@ struct Scratch {
         sqc = a.take<unsigned>(64);
         cnt = a.take<int>(64);
         eigwork = (void*)a.take<char>(eigh_work_bytes(n));
+        skw_bytes = split_ws_bytes(n);
+        skw = (void*)a.take<char>(skw_bytes);
+        cholw = a.take<double>(chol_work_doubles(CHOL_MAX));
     }
 };
 
@@ -274,6 +291,7 @@ struct mpdo_ctx_s {
     hipStream_t st = nullptr;
     std::string err;
     bool poisoned = false;
+    long retries = 0;             // updates recomputed after a failed basis check
     bool ready = false;
 
     // memory
@@ -337,6 +355,11 @@ struct Engine {
     hipStream_t st;
     int eig_calls = 0;
     int sub_iters = 0;   // subspace-iteration passes of the current update
+    // Where the last split found the largest discarded Schmidt value: >= 0, its index in s.sig;
+    // -1, the cut was not made by the chi cap (everything discarded lies below the cutoff or
+    // the rounding floor); -2 - level, the cap was met with the next value below the threshold
+    // of that deflation level (s.st[1 + level], an eigenvalue bound).
+    int cut_next = -1;
 
     Engine(mpdo_ctx_s& ctx, Scratch<T>& sc) : c(ctx), s(sc), st(ctx.st) {}
 
@@ -389,13 +412,20 @@ struct Engine {
 
     ProfSink* ps() { return c.prof.get(); }
 
+    // product options carrying this scratch's k-split workspace (deterministic split sums)
+    GemmOpts wso() const {
+        GemmOpts o;
+        o.ws = s.skw;
+        o.ws_bytes = s.skw_bytes;
+        return o;
+    }
     void gemm(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_, int batch = 1, long sA = 0,
               long sB = 0, long sC = 0) {
-        HIPCHK(cgemm<T>(st, M, N, K, a, A, B, b, C_, batch, sA, sB, sC, ps()));
+        HIPCHK(cgemm_ex<T>(st, M, N, K, a, A, B, b, C_, wso(), ps(), batch, sA, sB, sC));
     }
     // C = A (B diag(f)) for a device array f of N real factors
     void gemm_cols(int M, int N, int K, CView<T> A, CView<T> B, const double* f, CView<T> C_) {
-        GemmOpts o;
+        GemmOpts o = wso();
         o.b_col = f;
         HIPCHK(cgemm_ex<T>(st, M, N, K, C1(), A, B, C0(), C_, o, ps()));
     }
@@ -495,8 +525,14 @@ struct Engine {
             if (dbg)
                 fprintf(stderr, "[mpdo check] %s level %d order %d cols %d |Q|^2/q - 1 = %.3e nonfinite %g\n",
                         chk_stage[k], chk_level[k], chk_order[k], chk_q[k], dev, buf[2 * k + 1]);
-            if (buf[2 * k + 1] != 0.0 || !(fabs(dev) <= tol))
-                throw Fail{MPDO_E_NUMERIC, "orthonormal basis lost accuracy in the split (eigensolver accuracy)"};
+            if (buf[2 * k + 1] != 0.0 || !(fabs(dev) <= tol)) {
+                char msg[256];
+                snprintf(msg, sizeof(msg),
+                         "orthonormal basis lost accuracy in the split (%s, level %d, order %d, %d columns: "
+                         "|Q|^2/q - 1 = %.3e, non-finite %g)",
+                         chk_stage[k], chk_level[k], chk_order[k], chk_q[k], dev, buf[2 * k + 1]);
+                throw Fail{MPDO_E_NUMERIC, msg, true};
+            }
         }
     }
 
@@ -509,7 +545,7 @@ struct Engine {
             gemm(q, q, n, C1(), adj(V<T>(cur, ldc, 1)), V<T>(cur, ldc, 1), C0(), V<T>(s.bG, q, 1));
             T* nxt = cur == Q ? s.bW : Q;
             const long ldn = cur == Q ? (long)q : ldq;
-            GemmOpts o;
+            GemmOpts o = wso();
             o.b_scale = -0.5;
             o.b_diag = 1.5;
             HIPCHK(cgemm_ex<T>(st, n, q, q, C1(), V<T>(cur, ldc, 1), V<T>(s.bG, q, 1), C0(), V<T>(nxt, ldn, 1), o,
@@ -573,52 +609,85 @@ struct Engine {
         return q;
     }
 
-    // Orthonormal basis Q (na x q) of the dominant left singular subspace of theta = Fa Fb
-    // (Fb null: theta = Fa, na x nb), for splits whose exact range basis would need an
-    // eigenproblem above TRI_MAX (the saturated regime: theta up to 8192 x 8192 of rank 4608).
-    // Block subspace iteration from a seeded random block of m = min(chi + SUB_OVER, na, nb,
-    // rank bound) columns: Q = orth(theta X); then repeatedly Z = orth(theta^H Q),
-    // Q = orth(theta Z).  Every application of theta or theta^H is orthonormalised by orth2
-    // (eigenproblems of order <= m), so a block never spans more than the sigma_max / sigma_j
-    // of one application and directions down to orth2's rounding floor survive.  Stops when
-    // ||Q^H theta||_F^2, the weight of theta captured by Q, grows by less than the tolerance,
-    // or at once when m reaches the rank bound (one pass then spans range(theta)).  The later
-    // cut keeps at most chi directions of this basis, so what the basis misses lies below the
-    // truncation; ||theta||^2 seen by PPT is the captured weight.
-    // Outputs: Q -> Qout (ld ldq), Q^H Fa -> Kout (q x k, ld ldk; with Fb null, k = nb).
-    int subspace_basis(CView<T> Fa, const CView<T>* Fb, int na, int k, int nb, int chi, uint64_t seed, T* Qout,
-                       long ldq, T* Kout, long ldk) {
-        const int rank_bound = Fb ? std::min(k, std::min(na, nb)) : std::min(na, nb);
+    // Orthonormal basis of range(Y) for an n x m block (n >= m, m <= CHOL_MAX) whose condition
+    // number is below ~1/eps64, by shifted Cholesky QR (one pass with the shift, two without):
+    // Gram products, 64-wide Cholesky blocks and block triangular solves, no eigenproblem.  The
+    // passes run in FP64 (an FP32 block is widened first and the basis rounded back, so FP32
+    // rounding of Y only adds noise directions far below its cut).  Y (ld m) is overwritten; Q
+    // (n x m, ld m) receives the basis.  Returns false when a pivot broke down or the result is
+    // not orthonormal (a block too close to rank deficiency): the caller then uses orth2 on the
+    // input, recomputed.
+    bool orth_chol(T* Y, int n, int m, T* Q) {
+        if (m > CHOL_MAX || m > n || m < 1) return false;
+        const bool f64 = std::is_same<T, double>::value;
+        double* Yd = f64 ? (double*)Y : s.Gd;
+        double* Qd = f64 ? (double*)Q : s.Vd;
+        double* G = f64 ? s.Gd : (double*)s.bG;
+        double* L = f64 ? s.Vd : (double*)s.bW;
+        if (!f64) HIPCHK((geam<T, double>(st, n, m, C1(), V<T>(Y, m, 1), C0(), V<double>(Yd, m, 1))));
+        int* flag = s.cnt + 32;
+        HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+        const double coef = 11.0 * ((double)n * m + (double)m * (m + 1)) * EPS64;
+        double* in = Yd;
+        double* out = Qd;
+        for (int pass = 0; pass < 3; ++pass) {
+            HIPCHK(cgemm_ex<double>(st, m, m, n, C1(), adj(V<double>(in, m, 1)), V<double>(in, m, 1), C0(),
+                                    V<double>(G, m, 1), wso(), ps()));
+            HIPCHK(cholesky_lower(st, G, m, m, pass == 0 ? coef : 0.0, L, m, s.cholw, flag, wso(), ps()));
+            HIPCHK(trsm_right_lower_adj(st, in, m, n, m, L, m, s.cholw, out, m, wso(), ps()));
+            std::swap(in, out);
+        }
+        // an odd number of passes leaves the basis in Qd
+        if (!f64) HIPCHK((geam<double, T>(st, n, m, C1(), V<double>(Qd, m, 1), C0(), V<T>(Q, m, 1))));
+        HIPCHK(sumsq<T>(st, V<T>(Q, m, 1), n, m, s.sums, s.sqp, s.sqc));
+        HIPCHK(hipMemcpyAsync(c.hint, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        double w[2];
+        read_doubles(s.sums, 2, w);
+        const double tol = f64 ? 1e-12 : 1e-5;
+        const bool ok = c.hint[0] == 0 && w[1] == 0.0 && fabs(w[0] / m - 1.0) <= tol;
+        if (getenv("MPDO_DEBUG_CHECKS"))
+            fprintf(stderr, "[mpdo check] cholqr order %d cols %d |Q|^2/q - 1 = %.3e breakdown %d -> %s\n", n, m,
+                    w[0] / m - 1.0, c.hint[0], ok ? "ok" : "orth2");
+        return ok;
+    }
+
+    // Orthonormal basis Q (na x q) of the dominant left singular subspace of the na x nb view
+    // Th (theta), for splits whose exact range basis would need an eigenproblem above TRI_MAX
+    // (the saturated regime: theta up to 8192 x 8192 of rank 4608).  Block subspace iteration
+    // from a seeded random block of m = min(chi + SUB_OVER, na, nb) columns: Q = orth(theta X);
+    // then repeatedly Z = orth(theta^H Q), Q = orth(theta Z).  Every block is orthonormalised
+    // by orth2 (eigenproblems of order <= m), so a block never spans more than the
+    // sigma_max / sigma_j of one application and directions down to orth2's rounding floor
+    // survive.  Stops when ||Q^H theta||_F^2, the weight of theta captured by Q, grows by less
+    // than the tolerance, or at once when m reaches min(na, nb) (one pass then spans
+    // range(theta)).  The later cut keeps at most chi directions of this basis, so what the
+    // basis misses lies below the truncation; PPT still reads ||theta||_F^2 and tr(rho) of
+    // the whole theta.
+    // Outputs: Q -> Qout (ld ldq), Q^H theta -> Kout (q x nb, ld ldk).
+    int subspace_basis(CView<T> Th, int na, int nb, int chi, uint64_t seed, T* Qout, long ldq, T* Kout, long ldk) {
+        const int rank_bound = std::min(na, nb);
         const int m = std::min(chi + SUB_OVER, rank_bound);
         const double tol = std::is_same<T, double>::value ? 1e-10 : 1e-6;
         T* X = s.bR;     // nb x cols: random start block, then orth(theta^H Q)
-        T* T1 = s.bU;    // k x cols, Fb X
         T* Y = s.bC;     // na x cols
         T* Qt = s.bQ2;   // orth2's basis of Y (ld cols)
         T* Kt = s.bK2;   // orth2's coefficients (unused)
-        T* Kq = s.bB2;   // Q^H Fa (q x k, ld k)
         T* Cq = s.bU2;   // Q^H theta (q x nb, ld nb)
-        auto apply = [&](CView<T> Xv, int cols) {   // Y = theta Xv (nb x cols)
-            if (Fb) {
-                gemm(k, cols, nb, C1(), *Fb, Xv, C0(), V<T>(T1, cols, 1));
-                gemm(na, cols, k, C1(), Fa, V<T>(T1, cols, 1), C0(), V<T>(Y, cols, 1));
-            } else {
-                gemm(na, cols, nb, C1(), Fa, Xv, C0(), V<T>(Y, cols, 1));
-            }
-        };
         HIPCHK(fill_random<T>(st, V<T>(X, m, 1), nb, m, seed));
-        apply(V<T>(X, m, 1), m);
+        gemm(na, m, nb, C1(), Th, V<T>(X, m, 1), C0(), V<T>(Y, m, 1));
         int cols = m, q = 0;
         double w_old = -1.0;
         for (int it = 0;; ++it) {
-            q = orth2(V<T>(Y, cols, 1), na, cols, Qt, Kt);
-            if (q <= 0) return 0;
-            if (Fb) {
-                gemm(q, k, na, C1(), adj(V<T>(Qt, cols, 1)), Fa, C0(), V<T>(Kq, k, 1));
-                gemm(q, nb, k, C1(), V<T>(Kq, k, 1), *Fb, C0(), V<T>(Cq, nb, 1));
+            // Y = theta X (X: the start block, then Z): shifted Cholesky QR, or orth2 where the
+            // block is too close to rank deficiency for it
+            if (orth_chol(Y, na, cols, Qt)) {
+                q = cols;
             } else {
-                gemm(q, nb, na, C1(), adj(V<T>(Qt, cols, 1)), Fa, C0(), V<T>(Cq, nb, 1));
+                gemm(na, cols, nb, C1(), Th, V<T>(X, cols, 1), C0(), V<T>(Y, cols, 1));
+                q = orth2(V<T>(Y, cols, 1), na, cols, Qt, Kt);
             }
+            if (q <= 0) return 0;
+            gemm(q, nb, na, C1(), adj(V<T>(Qt, cols, 1)), Th, C0(), V<T>(Cq, nb, 1));
             ++sub_iters;
             if (m >= rank_bound) break;
             HIPCHK(sumsq<T>(st, V<T>(Cq, nb, 1), q, nb, s.sums, s.sqp, s.sqc));
@@ -628,16 +697,15 @@ struct Engine {
             if ((w_old >= 0.0 && w[0] - w_old <= tol * w[0]) || it + 1 >= SUB_ITERS) break;
             w_old = w[0];
             // Z = orth(theta^H Q) (nb x z), then Y = theta Z
-            const int z = orth2(adj(V<T>(Cq, nb, 1)), nb, q, X, Kt);
+            HIPCHK((geam<T, T>(st, nb, q, C1(), adj(V<T>(Cq, nb, 1)), C0(), V<T>(Kt, q, 1))));
+            int z = q;
+            if (!orth_chol(Kt, nb, q, X)) z = orth2(adj(V<T>(Cq, nb, 1)), nb, q, X, Kt);
             if (z <= 0) return 0;
-            apply(V<T>(X, q, 1), z);
+            gemm(na, z, nb, C1(), Th, V<T>(X, q, 1), C0(), V<T>(Y, z, 1));
             cols = z;
         }
         HIPCHK((geam<T, T>(st, na, q, C1(), V<T>(Qt, cols, 1), C0(), V<T>(Qout, ldq, 1))));
-        if (Fb)
-            HIPCHK((geam<T, T>(st, q, k, C1(), V<T>(Kq, k, 1), C0(), V<T>(Kout, ldk, 1))));
-        else
-            HIPCHK((geam<T, T>(st, q, nb, C1(), V<T>(Cq, nb, 1), C0(), V<T>(Kout, ldk, 1))));
+        HIPCHK((geam<T, T>(st, q, nb, C1(), V<T>(Cq, nb, 1), C0(), V<T>(Kout, ldk, 1))));
         return q;
     }
 
@@ -646,6 +714,7 @@ struct Engine {
     int split_left(CView<T> F, int a, int b, int chi, T* Ub, long ldu, T* Bb) {
         const double e = eps();
         int kacc = 0;
+        cut_next = -1;
         double rfloor = 0.0;   // residual rounding floor 8 eps ||F||_F, as a fraction of lambda_max
         CView<T> R = F;
         for (int lev = 0; lev < 3; ++lev) {
@@ -657,8 +726,15 @@ struct Engine {
                 HIPCHK((geam<T, double>(st, a, a, C1(), V<T>(s.bG, a, 1), C0(), V<double>(s.Gd, a, 1))));
             }
             const double tau = (lev == 0) ? 1e-4 : 0.0;
-            const int acc = eig_cut(a, lev, std::max(c.cutoff * c.cutoff, rfloor), noise_of(a), tau, chi - kacc,
-                                    s.sig + kacc, s.inv);
+            // one pair beyond the chi cap is asked for: when it is accepted, the cap decides the
+            // cut at this level and its value is the largest discarded Schmidt value, left in
+            // s.sig[chi] (the gap at the cut; ties there make the truncated state non-unique)
+            const int cap = chi - kacc;
+            const int accd = eig_cut(a, lev, std::max(c.cutoff * c.cutoff, rfloor), noise_of(a), tau,
+                                     std::min(cap + 1, a), s.sig + kacc, s.inv);
+            const int acc = std::min(accd, cap);
+            if (accd > cap) cut_next = kacc + acc;
+            else if (kacc + acc >= chi) cut_next = -2 - lev;   // capped, next value below the level threshold
             if (acc <= 0) break;
             T* Vn = Ub + 2 * kacc;   // columns kacc.. of U
             // Eigenvectors of R R^H lean out of range(R) by about eps lambda_max / lambda_j; the
@@ -821,7 +897,13 @@ struct Engine {
         const int na = dir > 0 ? nL : nR;
         const int nb = dir > 0 ? nR : nL;
         const int r = gf ? gf->r : 0;
-        const bool factored = !bg && gf && r <= MAX_FACTOR_RANK && (long)r * cm < (long)na;
+        // The factored split needs an exact range basis of M_L (eigenproblems of order r chi_mid).
+        // Where that order is above the subspace switch, theta is formed instead: the subspace
+        // iteration then runs on theta itself (one product per application instead of two), and
+        // ||theta||_F^2 and tr(rho), which PPT reads (Eq. (xiformula)), are those of the whole
+        // merged tensor, not of the part the subspace captures.
+        const bool factored = !bg && gf && r <= MAX_FACTOR_RANK && (long)r * cm < (long)na &&
+                              (long)r * cm <= (long)subspace_min_order();
         int kept = 0;
         double n2 = 0.0;
         T* Left = nullptr;   // new site i  (nL x kept), unscaled
@@ -844,9 +926,7 @@ struct Engine {
             HIPCHK(dot(st, s.vtmp, s.vtmp2, k, s.sc));
             CView<T> Fa = dir > 0 ? ML : adj(MR);
             CView<T> Fb = dir > 0 ? MR : adj(ML);
-            const int q = k > subspace_min_order() ? subspace_basis(Fa, &Fb, na, k, nb, chi, 0x5EED0000ull + (uint64_t)i, s.bQ, k,
-                                                       s.bK, k)
-                                      : orth2(Fa, na, k, s.bQ, s.bK);
+            const int q = orth2(Fa, na, k, s.bQ, s.bK);
             if (q <= 0) throw Fail{MPDO_E_NUMERIC, "merged tensor vanished"};
             // core C = K Fb (q x nb)
             gemm(q, nb, k, C1(), V<T>(s.bK, k, 1), Fb, C0(), V<T>(s.bC, nb, 1));
@@ -869,7 +949,10 @@ struct Engine {
         } else {
             // explicit theta: merge then gate
             const int m2 = D2 * D2;
-            gemm(nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(), V<T>(s.bT1, nR, 1));
+            ProfRename th(ps(), PF_GEMM, PF_THETA);
+            ProfSink* tps = ps() ? &th : nullptr;
+            HIPCHK(cgemm_ex<T>(st, nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(),
+                               V<T>(s.bT1, nR, 1), wso(), tps));
             if (bg) {
                 // theta[l][eta eta'][r] as cl blocks of m2 x cr: block (alpha, beta) = rows
                 // l in [lo, lo + ln) of alpha, columns r in [ro, ro + rn) of beta
@@ -877,13 +960,14 @@ struct Engine {
                     for (int b = 0; b < bg->nb; ++b) {
                         if (bg->ln[a] <= 0 || bg->rn[b] <= 0) continue;
                         const long off = 2 * ((long)bg->lo[a] * m2 * cr + (long)bg->ro[b]);
-                        gemm(m2, bg->rn[b], m2, C1(), V<T>((T*)bg->G[4 * a + b], m2, 1), V<T>(s.bT1 + off, cr, 1),
-                             C0(), V<T>(s.bA + off, cr, 1), bg->ln[a], 0, (long)m2 * cr, (long)m2 * cr);
+                        HIPCHK(cgemm_ex<T>(st, m2, bg->rn[b], m2, C1(), V<T>((T*)bg->G[4 * a + b], m2, 1),
+                                           V<T>(s.bT1 + off, cr, 1), C0(), V<T>(s.bA + off, cr, 1), wso(), tps,
+                                           bg->ln[a], 0, (long)m2 * cr, (long)m2 * cr));
                     }
             } else {
                 load_superop();
-                gemm(m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(), V<T>(s.bA, cr, 1), cl, 0,
-                     (long)m2 * cr, (long)m2 * cr);
+                HIPCHK(cgemm_ex<T>(st, m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(),
+                                   V<T>(s.bA, cr, 1), wso(), tps, cl, 0, (long)m2 * cr, (long)m2 * cr));
             }
             CView<T> Th = V<T>(s.bA, nR, 1);
             HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
@@ -896,8 +980,7 @@ struct Engine {
             CView<T> Fa = dir > 0 ? Th : adj(Th);
             if (std::min(na, nb) > subspace_min_order()) {
                 // range basis by subspace iteration, then the exact split of the q x nb core
-                const int q = subspace_basis(Fa, nullptr, na, nb, nb, chi, 0x5EED0000ull + (uint64_t)i, s.bQ, nb,
-                                             s.bK, nb);
+                const int q = subspace_basis(Fa, na, nb, chi, 0x5EED0000ull + (uint64_t)i, s.bQ, nb, s.bK, nb);
                 if (q <= 0) throw Fail{MPDO_E_NUMERIC, "merged tensor vanished"};
                 kept = svd_left(V<T>(s.bK, nb, 1), q, nb, chi, s.bU2);
                 if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
@@ -960,6 +1043,20 @@ struct Engine {
             info->max_abs_imag_t = po[0] != 0.0 ? po[6] / fabs(po[0]) : po[6];
             info->sigma_max = sg[0];
             info->sigma_min_kept = smin;
+            // the largest discarded Schmidt value: from the level whose chi cap made the cut,
+            // else bounded by that level's threshold (an eigenvalue of the Gram), else below the
+            // cutoff (reported as 0)
+            double snext = 0.0;
+            if (cut_next >= 0) {
+                read_doubles(s.sig + cut_next, 1, &snext);
+            } else if (cut_next <= -2) {
+                double st4[4];
+                read_doubles(s.st, 4, st4);
+                snext = sqrt(std::max(0.0, st4[1 + (-2 - cut_next)]));
+            }
+            info->sigma_next = snext;
+            info->sigma_gap_at_cut = smin - snext;
+            info->sigma_next_exact = cut_next >= 0 ? 1 : 0;
         }
     }
 };
@@ -1278,12 +1375,25 @@ void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n
     }
     c->Scur = &e.S;   // loaded to the device only if the update takes the explicit path
     c->Scur_id = e.id;
-    if (c->fp32) {
-        Engine<float> E(*c, c->sf);
-        E.update(i, gf.X ? &gf : nullptr, chi, info);
-    } else {
-        Engine<double> E(*c, c->sd);
-        E.update(i, gf.X ? &gf : nullptr, chi, info);
+    // A failed basis check is raised before the pair's new sites are written (the canonical
+    // moves before it keep rho exactly), so the update can be recomputed from the same sites;
+    // it is, once, and a second failure is returned.
+    for (int attempt = 0;; ++attempt) {
+        try {
+            if (c->fp32) {
+                Engine<float> E(*c, c->sf);
+                E.update(i, gf.X ? &gf : nullptr, chi, info);
+            } else {
+                Engine<double> E(*c, c->sd);
+                E.update(i, gf.X ? &gf : nullptr, chi, info);
+            }
+            if (info) info->retried = attempt;
+            c->retries += attempt;
+            return;
+        } catch (const Fail& f) {
+            if (!f.retry || attempt > 0) throw;
+            if (getenv("MPDO_DEBUG_CHECKS")) fprintf(stderr, "[mpdo] recomputing update %d: %s\n", i, f.msg.c_str());
+        }
     }
 }
 
@@ -2049,6 +2159,114 @@ mpdo_status mpdo_get_site(mpdo_ctx c, int site, double* out, int* shape) {
         set_err(c, f);
         return f.st;
     }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_set_state(mpdo_ctx c, const int* bond_dims, const double* sites, int centre) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!bond_dims || !sites || centre < -1 || centre >= c->N) {
+        c->err = "set_state: null pointer or centre out of range";
+        return MPDO_E_ARG;
+    }
+    std::vector<int> dims(c->N + 1, 1);
+    size_t total = 0;
+    for (int j = 0; j + 1 < c->N; ++j) {
+        if (bond_dims[j] < 1 || bond_dims[j] > c->chi) {
+            c->err = "set_state: bond dimension outside [1, chi_max]";
+            return MPDO_E_ARG;
+        }
+        dims[j + 1] = bond_dims[j];
+    }
+    for (int j = 0; j < c->N; ++j) total += (size_t)dims[j] * c->D2 * dims[j + 1] * 2;
+    if (!all_finite(sites, total)) {
+        c->err = "set_state: non-finite entry";
+        return MPDO_E_ARG;
+    }
+    try {
+        if (!c->ready) {
+            // ovec and the trace-vector ends as for a product state, then the sites below
+            std::vector<double> rho((size_t)c->N * c->D2 * 2, 0.0);
+            for (int j = 0; j < c->N; ++j) rho[(size_t)j * c->D2 * 2] = 1.0;
+            const mpdo_status st0 = mpdo_init_product_state(c, rho.data());
+            if (st0 != MPDO_OK) return st0;
+        }
+        size_t off = 0;
+        for (int j = 0; j < c->N; ++j) {
+            const size_t n = (size_t)dims[j] * c->D2 * dims[j + 1] * 2;
+            if (c->fp32) {
+                std::vector<float> hf(n);
+                for (size_t e = 0; e < n; ++e) hf[e] = (float)sites[off + e];
+                upload(c, c->site[j], hf.data(), n * sizeof(float));
+            } else {
+                upload(c, c->site[j], sites + off, n * sizeof(double));
+            }
+            off += n;
+        }
+        HIPCHK(hipStreamSynchronize(c->st));
+        c->dims = dims;
+        c->pend_id.assign(c->N, 1);
+        c->pending.assign(c->N, std::vector<zc>());
+        c->lvalid = 0;
+        c->rvalid = c->N;
+        c->dir = 1;
+        if (centre >= 0) {
+            c->centre = centre;
+        } else {
+            // sweep the centre from atom 0 to atom N-1: range-basis moves keep rho exactly
+            c->centre = 0;
+            if (c->fp32) {
+                Engine<float> E(*c, c->sf);
+                for (int j = 0; j + 1 < c->N; ++j) E.move_right(j);
+                E.orth_verify();
+            } else {
+                Engine<double> E(*c, c->sd);
+                for (int j = 0; j + 1 < c->N; ++j) E.move_right(j);
+                E.orth_verify();
+            }
+        }
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_move_centre(mpdo_ctx c, int site) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!c->ready || site < 0 || site >= c->N) {
+        c->err = "move_centre: no state or site out of range";
+        return MPDO_E_ARG;
+    }
+    try {
+        if (c->fp32) {
+            Engine<float> E(*c, c->sf);
+            while (c->centre < site) E.move_right(c->centre);
+            while (c->centre > site) E.move_left(c->centre);
+            E.orth_verify();
+        } else {
+            Engine<double> E(*c, c->sd);
+            while (c->centre < site) E.move_right(c->centre);
+            while (c->centre > site) E.move_left(c->centre);
+            E.orth_verify();
+        }
+    } catch (const Fail& f) {
+        set_err(c, f);
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_canonical_centre(mpdo_ctx c, int* out) {
+    mpdo_status g = guard(c);
+    if (g != MPDO_OK) return g;
+    if (!out || !c->ready) {
+        c->err = "canonical_centre: null pointer or no state";
+        return MPDO_E_ARG;
+    }
+    out[0] = c->centre;
+    out[1] = c->dir;
     return MPDO_OK;
 }
 

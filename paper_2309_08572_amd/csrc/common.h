@@ -54,13 +54,25 @@ struct cd {
 // Kernel families timed by the profiling sink.
 enum ProfFamily { PF_GEMM = 0, PF_EIG_PAIR = 1, PF_EIG_ROT = 2, PF_EIG_SMALL = 3, PF_PHYS = 4,
                   PF_TRANSFER = 5, PF_OTHER = 6, PF_TRI_REDUCE = 7, PF_TRI_SOLVE = 8, PF_TRI_BACK = 9,
-                  PF_COUNT = 10 };
+                  PF_THETA = 10, PF_COUNT = 11 };
 
 // Receives begin/end marks around kernel launches when measurement is on (else null).
 struct ProfSink {
     virtual void begin(hipStream_t s, int family) = 0;
     virtual void end(hipStream_t s, int family, double flop, double bytes) = 0;
     virtual ~ProfSink() {}
+};
+
+// Forwards to another sink with one family renamed (e.g. the GEMMs that form theta, timed
+// apart from the other products).
+struct ProfRename : public ProfSink {
+    ProfSink* to;
+    int from_fam, to_fam;
+    ProfRename(ProfSink* t, int f, int g) : to(t), from_fam(f), to_fam(g) {}
+    void begin(hipStream_t s, int family) override { to->begin(s, family == from_fam ? to_fam : family); }
+    void end(hipStream_t s, int family, double flop, double bytes) override {
+        to->end(s, family == from_fam ? to_fam : family, flop, bytes);
+    }
 };
 
 }  // namespace mpdo

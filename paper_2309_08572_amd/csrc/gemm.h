@@ -8,7 +8,7 @@ namespace mpdo {
 // C = alpha * A * B + beta * C over `batch` problems; A is M x K, B is K x N, C is M x N as
 // strided views (see CView); batch strides sA, sB, sC are in complex elements.  C must not
 // alias A or B.  prof (may be null) brackets the matrix-core kernel as PF_GEMM with its
-// algorithmic flop and bytes, and the output pre-scaling of split-k products as PF_OTHER.
+// algorithmic flop and bytes.  No workspace: k is never split (see GemmOpts).
 // Returns the launch status.
 template <typename T>
 hipError_t cgemm(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta,
@@ -22,6 +22,12 @@ struct GemmOpts {
     double b_scale = 1.0;
     double b_diag = 0.0;
     const double* b_col = nullptr;
+    // Device workspace for k-split products (the partial tiles of every k-chunk, added in
+    // chunk order by a second launch).  Without one, or when it is too small for the plan's
+    // split, the product runs with k unsplit.  Either way the result does not depend on the
+    // order in which workgroups run.
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
 };
 
 // cgemm with operand transforms.  C must not alias A or B.

@@ -12,8 +12,9 @@
 // a quadrant of 2 x 2 or 1 x 1 MFMA 16x16 tiles.  Tiles of A and B are staged through LDS as
 // separate real and imaginary planes; the global loader walks the contiguous dimension of
 // each view so loads coalesce whichever way the view is laid out.  Large-k products with a
-// small output (Gram matrices of tall factors) split k over blockIdx.z and accumulate with
-// FP64/FP32 atomics into a zeroed output.
+// small output (Gram matrices of tall factors) split k over blockIdx.z when the caller lends
+// a workspace: every k-chunk writes its partial tile there and a second launch adds the
+// partials in chunk order, so a product gives the same bits on every run (no atomics).
 //
 // One FP64 16x16x4 MFMA occupies a SIMD for 64 cycles (78.6 TFLOP/s over 1024 SIMDs), so a
 // workgroup needs 64 WM^2 cycles per unit of k on its compute unit: the small products of an
@@ -71,7 +72,8 @@ struct GemmArgs {
     CView<T> A, B, C;
     long sA, sB, sC;   // batch strides in complex elements
     double ar, ai, br, bi;
-    int atomic;        // 1: accumulate alpha*AB into C with atomics (beta ignored)
+    T* part;           // non-null: write alpha*AB of k-chunk kc and batch b to part (dense
+                       // M x N per (kc, b), beta ignored); the reduce launch forms C
     int bshift;        // 1: op(B) is replaced by bsc op(B) + bdg I as it is loaded
     double bsc, bdg;
     const double* bcol;   // non-null: column n of op(B) is scaled by bcol[n] as it is loaded
@@ -227,11 +229,12 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
                 const double xr = (double)cr[i][j][r], xi = (double)ci[i][j][r];
                 const double vr = g.ar * xr - g.ai * xi;
                 const double vi = g.ar * xi + g.ai * xr;
-                const long off = 2 * ((long)gm * g.C.rs + (long)gn * g.C.cs);
-                if (g.atomic) {
-                    atomicAdd(&Cp[off], (T)vr);
-                    atomicAdd(&Cp[off + 1], (T)(g.C.conj ? -vi : vi));
+                if (g.part) {
+                    T* pp = g.part + 2 * (((long)kc * g.batch + b) * g.M * (long)g.N + (long)gm * g.N + gn);
+                    pp[0] = (T)vr;
+                    pp[1] = (T)vi;
                 } else {
+                    const long off = 2 * ((long)gm * g.C.rs + (long)gn * g.C.cs);
                     double or_ = 0.0, oi = 0.0;
                     if (g.br != 0.0 || g.bi != 0.0) {
                         const double cr0 = (double)Cp[off];
@@ -247,22 +250,38 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
             }
 }
 
+// C = beta C + sum over the ks k-chunks of the partial products, added in chunk order (FP64
+// sums), one thread per output element of every batch.
 template <typename T>
-__global__ void cscale_kernel(CView<T> C, int M, int N, double br, double bi) {
+__global__ void csplit_reduce_kernel(const T* __restrict__ part, int ks, int batch, int M, int N, CView<T> C,
+                                     long sC, double br, double bi) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)M * N) return;
-    const int m = (int)(idx / N), n = (int)(idx % N);
-    const long off = 2 * ((long)m * C.rs + (long)n * C.cs);
-    if (br == 0.0 && bi == 0.0) {
-        C.p[off] = 0;
-        C.p[off + 1] = 0;
-        return;
+    const long mn = (long)M * N;
+    if (idx >= mn * batch) return;
+    const int b = (int)(idx / mn);
+    const long e = idx - (long)b * mn;
+    const int m = (int)(e / N), n = (int)(e - (long)(e / N) * N);
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < ks; ++k) {
+        const T* pp = part + 2 * (((long)k * batch + b) * mn + e);
+        sr += (double)pp[0];
+        si += (double)pp[1];
     }
-    const double cr = (double)C.p[off];
-    const double ci = C.conj ? -(double)C.p[off + 1] : (double)C.p[off + 1];
-    const double vr = br * cr - bi * ci, vi = br * ci + bi * cr;
-    C.p[off] = (T)vr;
-    C.p[off + 1] = (T)(C.conj ? -vi : vi);
+    T* Cp = C.p + 2 * (long)b * sC;
+    const long off = 2 * ((long)m * C.rs + (long)n * C.cs);
+    if (br != 0.0 || bi != 0.0) {
+        const double cr = (double)Cp[off];
+        const double ci = C.conj ? -(double)Cp[off + 1] : (double)Cp[off + 1];
+        sr += br * cr - bi * ci;
+        si += br * ci + bi * cr;
+    }
+    Cp[off] = (T)sr;
+    Cp[off + 1] = (T)(C.conj ? -si : si);
+}
+
+template <typename T>
+size_t split_bytes(int M, int N, int batch, int ks) {
+    return (size_t)ks * batch * (size_t)M * N * 2 * sizeof(T);
 }
 
 // Launch plan: block tile (32 wm)^2 with wm = 2 or 1, and the k range split ks ways.
@@ -283,8 +302,8 @@ int chunk_of(int K, int ks) { return (((K + ks - 1) / ks + BK - 1) / BK) * BK; }
 // per compute unit (a unit that holds two shares its matrix cores between them).  Operand
 // traffic: every workgroup reads a (32 wm) x chunk tile of A and of B, at ~16 TB/s from L2
 // and the memory-side cache, counted at a quarter weight (it mostly overlaps the matrix work;
-// it decides between plans of equal matrix time).  A split adds its atomic updates of the
-// output (~2 TB/s), the pre-scaling launch and ~5 us of fixed cost; every launch ~2 us.
+// it decides between plans of equal matrix time).  A split adds its partial tiles, written and
+// read back by the reduce launch (~4 TB/s), and ~5 us of fixed cost; every launch ~2 us.
 double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p) {
     const double tsz = fp64 ? 8.0 : 4.0;
     const double W = (double)tiles_of(M, N, batch, p.wm) * p.ks;
@@ -292,17 +311,17 @@ double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p) {
     const double cyc = (fp64 ? 64.0 : 32.0) * p.wm * p.wm * chunk;
     const double mfma_us = std::ceil(W / 256.0) * cyc / 2400.0;
     const double bytes = W * chunk * 64.0 * p.wm * 2.0 * tsz;
-    const double atomic_us = p.ks > 1 ? W * 1024.0 * p.wm * p.wm * 2.0 * tsz / 2e6 : 0.0;
-    return mfma_us + 0.25 * bytes / 16e6 + atomic_us + 2.0 + (p.ks > 1 ? 5.0 : 0.0);
+    const double part_us = p.ks > 1 ? 2.0 * W * 1024.0 * p.wm * p.wm * 2.0 * tsz / 4e6 : 0.0;
+    return mfma_us + 0.25 * bytes / 16e6 + part_us + 2.0 + (p.ks > 1 ? 5.0 : 0.0);
 }
 
 // wm_max = 1 restricts the plan to 32 x 32 tiles (the kernel with operand transforms needs
 // more registers than two waves per SIMD allow at 64 x 64)
-Plan plan_of(int M, int N, int K, int batch, bool fp64, int wm_max = 2) {
+Plan plan_of(int M, int N, int K, int batch, bool fp64, int wm_max = 2, int ks_max = 64) {
     Plan best{wm_max, 1};
     double best_t = plan_cost(M, N, K, batch, fp64, best);
     for (int wm = wm_max; wm >= 1; --wm)
-        for (int ks = 1; ks <= 64; ks *= 2) {
+        for (int ks = 1; ks <= ks_max; ks *= 2) {
             if (ks > 1 && K < 2 * BK) break;
             const int k_eff = ks > 1 ? (K + chunk_of(K, ks) - 1) / chunk_of(K, ks) : 1;
             if (ks > 1 && k_eff < 2) continue;
@@ -336,7 +355,7 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
     g.ai = alpha.im;
     g.br = beta.re;
     g.bi = beta.im;
-    g.atomic = 0;
+    g.part = nullptr;
     g.bshift = (opt.b_scale != 1.0 || opt.b_diag != 0.0) ? 1 : 0;
     g.bsc = opt.b_scale;
     g.bdg = opt.b_diag;
@@ -348,20 +367,12 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
     if (ks >= 2) {
         const int chunk = chunk_of(g.K, ks);
         ks = (g.K + chunk - 1) / chunk;
-        if (ks >= 2) {
-            // C <- beta*C first, then accumulate alpha*AB atomically
-            const long tot = (long)M * N;
-            if (prof) prof->begin(s, PF_OTHER);
-            for (int bb = 0; bb < batch; ++bb) {
-                CView<T> Cb = C;
-                Cb.p = C.p + 2 * (long)bb * sC;
-                hipLaunchKernelGGL(cscale_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Cb, M, N,
-                                   beta.re, beta.im);
-            }
-            if (prof) prof->end(s, PF_OTHER, 0.0, 2.0 * sizeof(T) * (double)tot * batch);
+        // the partials need ks M N complex per batch in the caller's workspace; without room the
+        // product runs unsplit (the same result, computed by fewer workgroups)
+        if (ks >= 2 && split_bytes<T>(M, N, batch, ks) <= opt.ws_bytes && opt.ws) {
             g.ksplit = ks;
             g.kchunk = chunk;
-            g.atomic = 1;
+            g.part = (T*)opt.ws;
         }
     }
     const int bt = 32 * plan.wm;
@@ -378,6 +389,11 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
             hipLaunchKernelGGL((cgemm_kernel<T, 1, 1>), grid, dim3(256), 0, s, g);
         else
             hipLaunchKernelGGL((cgemm_kernel<T, 1, 0>), grid, dim3(256), 0, s, g);
+    }
+    if (g.part) {
+        const long tot = (long)M * N * batch;
+        hipLaunchKernelGGL(csplit_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g.part,
+                           g.ksplit, batch, M, N, C, sC, beta.re, beta.im);
     }
     if (prof) {
         // algorithmic: 8 flop per complex multiply-add; A, B read and C written once (and read
@@ -424,7 +440,7 @@ bool autotune_on() {
 
 template <typename T>
 Plan tune_plan(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T> B, cd beta, CView<T> C,
-               int batch, long sA, long sB, long sC) {
+               int batch, long sA, long sB, long sC, const GemmOpts& opt, int ks_max) {
     const bool fp64 = std::is_same<T, double>::value;
     const TuneKey key{log2_bucket(M), log2_bucket(N), log2_bucket(K), log2_bucket(batch), fp64 ? 1 : 0};
     {
@@ -432,12 +448,12 @@ Plan tune_plan(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T
         auto it = g_tune.find(key);
         if (it != g_tune.end()) return it->second;
     }
-    const Plan h = plan_of(M, N, K, batch, fp64);
+    const Plan h = plan_of(M, N, K, batch, fp64, 2, ks_max);
     Plan cands[16];
     int nc = 0;
     cands[nc++] = h;
     for (int wm = 2; wm >= 1; --wm)
-        for (int ks = 1; ks <= 64 && nc < 16; ks *= 2) {
+        for (int ks = 1; ks <= ks_max && nc < 16; ks *= 2) {
             if (ks > 1 && ks > K / 64) break;
             if (!(wm == h.wm && ks == h.ks)) cands[nc++] = Plan{wm, ks};
         }
@@ -451,10 +467,10 @@ Plan tune_plan(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T
     }
     for (int i = 0; i < nc; ++i) {
         // one untimed run, then one timed
-        if (cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, cands[i], nullptr) != hipSuccess)
+        if (cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, cands[i], nullptr, opt) != hipSuccess)
             continue;
         (void)hipEventRecord(e0, s);
-        (void)cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, cands[i], nullptr);
+        (void)cgemm_launch<T>(s, M, N, K, alpha, A, B, beta, C, batch, sA, sB, sC, cands[i], nullptr, opt);
         (void)hipEventRecord(e1, s);
         if (hipEventSynchronize(e1) != hipSuccess) continue;
         float ms = 0.0f;
@@ -478,9 +494,12 @@ hipError_t cgemm_ex(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CV
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     const int k = K < 0 ? 0 : K;
     const bool plain = opt.b_scale == 1.0 && opt.b_diag == 0.0 && !opt.b_col;
-    Plan plan = plan_of(M, N, k, batch, std::is_same<T, double>::value, plain ? 2 : 1);
+    // the largest k split whose partials fit the workspace
+    int ks_max = 1;
+    while (ks_max < 64 && opt.ws && split_bytes<T>(M, N, batch, 2 * ks_max) <= opt.ws_bytes) ks_max *= 2;
+    Plan plan = plan_of(M, N, k, batch, std::is_same<T, double>::value, plain ? 2 : 1, ks_max);
     if (plain && autotune_on() && beta.re == 0.0 && beta.im == 0.0 && K >= 128)
-        plan = tune_plan<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC);
+        plan = tune_plan<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, opt, ks_max);
     return cgemm_launch<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, plan, prof, opt);
 }
 

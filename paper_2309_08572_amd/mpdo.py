@@ -24,12 +24,12 @@ EXPORTS = (
     "mpdo_create", "mpdo_destroy", "mpdo_workspace_bytes", "mpdo_bind_workspace",
     "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus", "mpdo_apply_gate_crosstalk",
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_expect2", "mpdo_trace", "mpdo_bond_dims",
-    "mpdo_get_site", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
+    "mpdo_get_site", "mpdo_set_state", "mpdo_canonical_centre", "mpdo_move_centre", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
     "mpdo_profile_enable", "mpdo_profile_enable_mask", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
 )
 
 PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other",
-                 "tri_reduce", "tri_solve", "tri_back")
+                 "tri_reduce", "tri_solve", "tri_back", "theta")
 
 
 class Config(C.Structure):
@@ -45,7 +45,9 @@ class TruncInfo(C.Structure):
                 ("trace_after", C.c_double), ("xi_before", C.c_double),
                 ("xi_after", C.c_double), ("ppt_theta", C.c_double),
                 ("discarded_weight", C.c_double), ("max_abs_imag_t", C.c_double),
-                ("sigma_max", C.c_double), ("sigma_min_kept", C.c_double)]
+                ("sigma_max", C.c_double), ("sigma_min_kept", C.c_double),
+                ("sigma_next", C.c_double), ("sigma_gap_at_cut", C.c_double),
+                ("sigma_next_exact", C.c_int), ("retried", C.c_int)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -102,6 +104,9 @@ def load_library() -> C.CDLL:
     lib.mpdo_trace.argtypes = [ctx, dp]
     lib.mpdo_bond_dims.argtypes = [ctx, ip]
     lib.mpdo_get_site.argtypes = [ctx, C.c_int, dp, ip]
+    lib.mpdo_set_state.argtypes = [ctx, ip, dp, C.c_int]
+    lib.mpdo_canonical_centre.argtypes = [ctx, ip]
+    lib.mpdo_move_centre.argtypes = [ctx, C.c_int]
     lib.mpdo_synchronize.argtypes = [ctx]
     lib.mpdo_last_error.argtypes = [ctx]
     lib.mpdo_last_error.restype = C.c_char_p
@@ -255,6 +260,28 @@ class MPDO:
         out = np.zeros(int(np.prod(shape)), dtype=np.complex128)
         self._check(self.lib.mpdo_get_site(self.ctx, j, _dptr(out), sp))
         return out.reshape(tuple(int(x) for x in shape))
+
+    def canonical_centre(self):
+        """(atom holding the canonical centre, direction of the last sweep)."""
+        out = np.zeros(2, dtype=np.int32)
+        self._check(self.lib.mpdo_canonical_centre(self.ctx, out.ctypes.data_as(C.POINTER(C.c_int))))
+        return int(out[0]), int(out[1])
+
+    def move_centre(self, site: int):
+        """Move the canonical centre to atom `site` (exact up to the rounding floor)."""
+        self._check(self.lib.mpdo_move_centre(self.ctx, int(site)))
+
+    def get_state(self):
+        """(bond dimensions, list of site tensors, canonical centre) of the chain."""
+        return self.bond_dims(), [self.get_site(j) for j in range(self.n)], self.canonical_centre()[0]
+
+    def set_state(self, bonds, sites, centre: int = -1):
+        """Load site tensors [chi_l][D2][chi_r]; centre >= 0 vouches for the mixed canonical
+        form about that atom, -1 lets the library canonicalise."""
+        b = np.ascontiguousarray(bonds, dtype=np.int32)
+        data = _cplx(np.concatenate([np.asarray(a).reshape(-1) for a in sites]))
+        self._check(self.lib.mpdo_set_state(self.ctx, b.ctypes.data_as(C.POINTER(C.c_int)), _dptr(data),
+                                            int(centre)))
 
     def profile(self, enable: bool):
         self._check(self.lib.mpdo_profile_enable(self.ctx, int(enable)))

@@ -44,3 +44,40 @@ def test_batch_rejects_bad_circuit():
     d["chi"] = 0
     with pytest.raises(mpdo.MpdoError):
         mpdo.run_batch([d], n_workers=1)
+
+
+def test_batch_of_m2_circuits_matches_oracle_and_single_runs():
+    """The first 8 circuits of the 256-circuit batch workload (N 23..91, chi 64/128/256, p 1..3,
+    rates log-uniform in [1e-4, 1e-2]) through mpdo_run_batch on 4 worker streams: each must
+    match the stored CPU oracle values (tests/golden/make_m3_oracle.py m2) to the FP64 bar and
+    the same circuit run alone through the single-circuit entry points."""
+    import json
+    import os
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08572_amd import circuits, mpdo
+    from workloads import config_m2_batch
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "m2_seed0_first8_oracle.json")) as f:
+        gold = json.load(f)["circuits"]
+    specs = config_m2_batch(0)[:8]
+    print("[gpu] batch of the first 8 M2 circuits", [(s.n, s.chi, s.p) for s in specs], flush=True)
+    res = mpdo.run_batch([circuits.describe(s) for s in specs], n_workers=4)
+    for c, (spec, r, o) in enumerate(zip(specs, res, gold)):
+        assert r["status"] == 0
+        g = circuits.summarize(r["values"], spec.n, spec.d)
+        scale = max(1.0, abs(o["energy_per_site"]))
+        assert abs(g["energy_per_site"] - o["energy_per_site"]) <= 1e-10 * scale, c
+        np.testing.assert_allclose(g["populations"], np.array(o["populations"]), rtol=0, atol=1e-10)
+        assert abs(g["p_success"] - o["p_success"]) <= 1e-10, c
+        assert abs(r["trace"] - complex(*o["trace"])) <= 1e-10, c
+        diff = [a - b for a, b in zip(r["bonds"], o["bond_dims"])]
+        assert sum(abs(x) for x in diff) <= 2, (c, r["bonds"], o["bond_dims"])
+        if c in (0, 3, 5):   # one circuit per depth, alone on the stream of the caller
+            m = circuits.run_circuit(spec)
+            s = circuits.observables(m)
+            assert abs(s["energy_per_site"] - g["energy_per_site"]) <= 1e-10 * scale, c
+            np.testing.assert_allclose(s["populations"], g["populations"], rtol=0, atol=1e-10)
+            assert m.bond_dims() == r["bonds"], c
+            m.close()

@@ -203,3 +203,25 @@ def test_gemm_autotuner_gives_the_same_circuit(monkeypatch):
     got = circuits.observables(circuits.run_circuit(spec))
     assert abs(got["energy_per_site"] - ref["energy_per_site"]) <= 1e-10 * max(1.0, abs(ref["energy_per_site"]))
     np.testing.assert_allclose(got["populations"], ref["populations"], rtol=0, atol=1e-10)
+
+
+def test_repeated_runs_agree_to_rounding():
+    """Products whose k range is split add their partial tiles in a fixed order (no atomics), so
+    run-to-run differences come only from the tridiagonal reduction's on-chip accumulation (LDS
+    atomics of the matrix-vector products, whose order varies): the same truncating circuit,
+    run three times and four more times as a batch on four streams, must agree to 1e-13."""
+    circuits, mpdo = _gpu()
+    spec = random_spec(seed=8, n=8, d=4, p=3, chi=64, rate_lo=1e-3, rate_hi=1e-2)
+    print("[gpu] truncating N=8 p=3 chi=64, three runs and a batch of four", flush=True)
+    runs = []
+    for _ in range(3):
+        m = circuits.run_circuit(spec)
+        runs.append((circuits.observables(m), m.bond_dims()))
+        m.close()
+    for r in mpdo.run_batch([circuits.describe(spec)] * 4, n_workers=4):
+        runs.append((circuits.summarize(r["values"], spec.n, spec.d), r["bonds"]))
+    ref, bonds = runs[0]
+    for g, b in runs[1:]:
+        assert b == bonds
+        assert abs(g["energy_per_site"] - ref["energy_per_site"]) <= 1e-13
+        assert float(np.max(np.abs(g["populations"] - ref["populations"]))) <= 1e-13

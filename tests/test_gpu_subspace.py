@@ -71,3 +71,50 @@ def test_subspace_path_on_a_truncating_circuit_agrees_with_exact_split(monkeypat
     assert de <= 1e-8 and dp <= 1e-8 and dpur <= 1e-8
     assert max(m.bond_dims()) == 64
     m.close()
+
+
+def _compare_cut_logs(gpu_infos, oracle_log, chi, rel=1e-10):
+    """Per-update, gauge-invariant quantities of the cut against the oracle's log: tr(rho) and
+    xi = tr(rho^2)/tr(rho)^2 of the whole merged tensor before the cut (what PPT reads,
+    Eq. (xiformula)), the kept count (equal where chi makes the cut; elsewhere it may differ by
+    a value sitting at the 1e-14 relative cutoff), the discarded weight, the trace after PPT."""
+    assert len(gpu_infos) == len(oracle_log)
+    worst = 0.0
+    for g, o in zip(gpu_infos, oracle_log):
+        assert g["bond"] == o["bond"]
+        assert abs(g["kept"] - o["kept"]) <= (0 if o["kept"] == chi else 1), (g["bond"], g["kept"], o["kept"])
+        for k in ("trace_before", "xi_before", "trace_after"):
+            err = abs(g[k] - o[k]) / abs(o[k])
+            worst = max(worst, err)
+            assert err <= rel, (k, g["bond"], g[k], o[k])
+        assert abs(g["discarded_weight"] - o["discarded_weight"]) <= rel
+    return worst
+
+
+def test_forced_subspace_truncating_circuit_matches_oracle(monkeypatch):
+    """The subspace split, forced on (above order 100), on a circuit that cuts at chi = 64 while
+    the subspace block (64 + 256 = 320) stays below theta's rank (up to 576), so the block is
+    iterated: every update's trace, xi and discarded weight (which PPT computes from the whole
+    theta, not from the part the block captured) and the final observables must match the CPU
+    oracle (LAPACK SVD) to 1e-10."""
+    circuits, mpdo = _gpu()
+    from oracle import mpo
+    spec = config_m3(0, n=8, p=4, chi=64)
+    print("[gpu] N=8 chi=64 p=4 fp64, subspace path above order 100, against the oracle", flush=True)
+    ref = mpo.run_spec(spec)
+    o = mpo.observables(ref)
+    monkeypatch.setenv("MPDO_SUBSPACE_MIN_ORDER", "100")
+    infos = []
+    m = circuits.run_circuit(spec, infos=infos)
+    g = circuits.observables(m)
+    worst = _compare_cut_logs(infos, ref.log, spec.chi)
+    cut = [x for x in ref.log if x["discarded_weight"] > 0]
+    de = abs(g["energy_per_site"] - o["energy_per_site"])
+    print(f"[gpu] {len(cut)} cuts; worst per-update rel err {worst:.2e}; |dE/N| {de:.2e}", flush=True)
+    assert len(cut) >= 5
+    assert de <= 1e-10 * max(1.0, abs(o["energy_per_site"]))
+    np.testing.assert_allclose(g["populations"], o["populations"], rtol=0, atol=1e-10)
+    assert abs(g["p_success"] - o["p_success"]) <= 1e-10
+    assert abs(circuits.purity(m) - o["purity"]) <= 1e-10 * o["purity"]
+    assert max(abs(a - b) for a, b in zip(m.bond_dims(), ref.bond_dims())) <= 1
+    m.close()
