@@ -52,6 +52,19 @@ typedef struct mpdo_pulse_params {
 mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* params, const double* omega,
                                const double* delta, double* superop, void* hip_stream);
 
+/* As mpdo_pulse_channel, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the call makes no hipMalloc,
+ * hipFree or other allocating call.  Its device buffers are carved from one fixed scratch block
+ * of 32 MiB per device (a static device array, resident from the library's load until the
+ * process ends), which limits n_steps to 131072 for d = 4 and 484917 for d = 3; a larger
+ * n_steps returns MPDO_E_ARG with the bytes needed, before any device work.  Every call on a
+ * device shares that device's block: calls that overlap on one device (two host threads, or
+ * two streams with work in flight) race and give wrong results, so serialise them.  Inputs
+ * and outputs are as in mpdo_pulse_channel (host arrays, copied in and out on hip_stream);
+ * the call returns after the result is on the host.  Other status codes as above. */
+mpdo_status mpdo_pulse_channel_noalloc(const mpdo_pulse_params* params, const double* omega,
+                                       const double* delta, double* superop, void* hip_stream);
+
 const char* mpdo_pulse_last_error(void);
 
 #ifdef __cplusplus

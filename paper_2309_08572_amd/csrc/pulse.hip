@@ -30,10 +30,19 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "../../include/mpdo_pulse.h"
 #include "gemm.h"
+
+// Scratch of the allocation-free entry point (mpdo_pulse_channel_noalloc): one fixed block per
+// device, which every call on that device reuses (calls that overlap on one device race) and
+// which stays allocated until the process ends.  Host code never uses the name itself, only the
+// address hipGetSymbolAddress returns for the current device.  Nothing in it must start at
+// zero: every kernel and product writes all of its part before reading it.
+constexpr size_t PULSE_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[PULSE_SCRATCH_BYTES];
 
 namespace {
 
@@ -231,10 +240,32 @@ mpdo_status fail(mpdo_status st, const std::string& msg) {
     return st;
 }
 
-}  // namespace
+// Device buffers of one call: step samples (2 n), per-step drive table (6 n), the segment
+// channels (nseg) and the pairwise products (ceil(nseg / 2)), each channel ne^2 complex.
+struct PulseBufs {
+    double *samp, *tab, *out, *tmp;
+};
 
-extern "C" mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* p, const double* omega, const double* delta,
-                                          double* superop, void* hip_stream) {
+struct PulseSizes {
+    int ne, nseg;
+    size_t samp_b, tab_b, one_b;
+    size_t total() const {   // one block of scratch, every part 256-byte aligned
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        return al(samp_b) + al(tab_b) + al(one_b * nseg) + al(one_b * ((nseg + 1) / 2));
+    }
+};
+
+PulseSizes pulse_sizes(int d, int n) {
+    PulseSizes z;
+    z.ne = d * d * d * d;
+    z.nseg = std::max(1, std::min(MAX_SEG, n / SEG_MIN_STEPS));
+    z.samp_b = 2 * (size_t)n * sizeof(double);
+    z.tab_b = 6 * (size_t)n * sizeof(double);
+    z.one_b = 2 * (size_t)z.ne * z.ne * sizeof(double);
+    return z;
+}
+
+mpdo_status check_params(const mpdo_pulse_params* p, const double* omega, const double* delta, double* superop) {
     if (!p || !omega || !delta || !superop) return fail(MPDO_E_ARG, "null pointer");
     const int d = p->d, n = p->n_steps;
     if (d != 3 && d != 4) return fail(MPDO_E_ARG, "d must be 3 or 4");
@@ -247,7 +278,14 @@ extern "C" mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* p, const doub
         return fail(MPDO_E_ARG, "negative rate or branch ratio");
     if (d == 3 && p->branch[2] != 0.0) return fail(MPDO_E_ARG, "a dark branch needs d = 4");
     if (!finite_all(omega, n) || !finite_all(delta, n)) return fail(MPDO_E_ARG, "non-finite pulse sample");
+    return MPDO_OK;
+}
 
+// The channel of one pulse into superop (host), computed in the device buffers B (validated
+// parameters; the sizes of B follow pulse_sizes(d, n_steps)).
+mpdo_status pulse_run(const mpdo_pulse_params* p, const double* omega, const double* delta, double* superop,
+                      hipStream_t s, const PulseBufs& B) {
+    const int d = p->d, n = p->n_steps;
     const double tau = p->tau;
     SiteNoise z{};
     const double e0 = exp(-p->gamma_diss * p->branch[0] * tau);
@@ -262,53 +300,106 @@ extern "C" mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* p, const doub
     z.dq = exp(-g2 * tau);
     z.dh = exp(-0.25 * g2 * tau);
 
-    const int ne = d * d * d * d;
-    const int nseg = std::max(1, std::min(MAX_SEG, n / SEG_MIN_STEPS));
-    hipStream_t s = (hipStream_t)hip_stream;
-    double *dsamp = nullptr, *dtab = nullptr, *dout = nullptr, *dtmp = nullptr;
-    mpdo_status st = MPDO_OK;
-    const size_t samp_b = 2 * (size_t)n * sizeof(double), tab_b = 6 * (size_t)n * sizeof(double);
-    const size_t one_b = 2 * (size_t)ne * ne * sizeof(double);
-    if (hipMalloc(&dsamp, samp_b) != hipSuccess || hipMalloc(&dtab, tab_b) != hipSuccess ||
-        hipMalloc(&dout, one_b * nseg) != hipSuccess || hipMalloc(&dtmp, one_b * ((nseg + 1) / 2)) != hipSuccess) {
+    const PulseSizes zs = pulse_sizes(d, n);
+    const int ne = zs.ne, nseg = zs.nseg;
+    hipError_t e = hipMemcpyAsync(B.samp, omega, n * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(B.samp + n, delta, n * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pulse_drive_kernel, dim3((n + 255) / 256), dim3(256), 0, s, B.samp, B.samp + n, n, tau,
+                           B.tab);
+        if (d == 4)
+            hipLaunchKernelGGL(pulse_evolve_kernel<4>, dim3(ne, nseg), dim3(EVOLVE_THREADS), 0, s, B.tab, n, nseg,
+                               tau, p->blockade, z, B.out);
+        else
+            hipLaunchKernelGGL(pulse_evolve_kernel<3>, dim3(ne, nseg), dim3(EVOLVE_THREADS), 0, s, B.tab, n, nseg,
+                               tau, p->blockade, z, B.out);
+        e = hipGetLastError();
+    }
+    // product of the segment channels in time order: S = S_{nseg-1} ... S_1 S_0, pairwise
+    double* cur = B.out;
+    double* nxt = B.tmp;
+    int cnt = nseg;
+    const long one = (long)ne * ne;   // complex elements of one channel
+    while (e == hipSuccess && cnt > 1) {
+        const int pairs = cnt / 2;
+        e = mpdo::cgemm<double>(s, ne, ne, ne, mpdo::cd{1.0, 0.0}, mpdo::view<double>(cur + 2 * one, ne, 1),
+                                mpdo::view<double>(cur, ne, 1), mpdo::cd{0.0, 0.0}, mpdo::view<double>(nxt, ne, 1),
+                                pairs, 2 * one, 2 * one, one);
+        if (e == hipSuccess && (cnt & 1))
+            e = hipMemcpyAsync(nxt + 2 * one * pairs, cur + 2 * one * (cnt - 1), zs.one_b, hipMemcpyDeviceToDevice, s);
+        cnt = pairs + (cnt & 1);
+        std::swap(cur, nxt);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(superop, cur, zs.one_b, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(MPDO_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+    return MPDO_OK;
+}
+
+constexpr int PULSE_MAX_DEVICES = 64;
+char* g_scratch_ptr[PULSE_MAX_DEVICES] = {nullptr};   // device address of scratch, per device
+std::mutex g_scratch_mu;
+
+// The device address of this device's scratch (looked up once per device, with it current).
+mpdo_status scratch_of_device(char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(MPDO_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= PULSE_MAX_DEVICES) return fail(MPDO_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MPDO_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPDO_OK;
+}
+
+}  // namespace
+
+extern "C" mpdo_status mpdo_pulse_channel(const mpdo_pulse_params* p, const double* omega, const double* delta,
+                                          double* superop, void* hip_stream) {
+    mpdo_status st = check_params(p, omega, delta, superop);
+    if (st != MPDO_OK) return st;
+    const PulseSizes zs = pulse_sizes(p->d, p->n_steps);
+    PulseBufs B{nullptr, nullptr, nullptr, nullptr};
+    if (hipMalloc(&B.samp, zs.samp_b) != hipSuccess || hipMalloc(&B.tab, zs.tab_b) != hipSuccess ||
+        hipMalloc(&B.out, zs.one_b * zs.nseg) != hipSuccess ||
+        hipMalloc(&B.tmp, zs.one_b * ((zs.nseg + 1) / 2)) != hipSuccess) {
         st = fail(MPDO_E_NOMEM, "device allocation failed");
     } else {
-        hipError_t e = hipMemcpyAsync(dsamp, omega, n * sizeof(double), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(dsamp + n, delta, n * sizeof(double), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(pulse_drive_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dsamp, dsamp + n, n, tau,
-                               dtab);
-            if (d == 4)
-                hipLaunchKernelGGL(pulse_evolve_kernel<4>, dim3(ne, nseg), dim3(EVOLVE_THREADS), 0, s, dtab, n, nseg,
-                                   tau, p->blockade, z, dout);
-            else
-                hipLaunchKernelGGL(pulse_evolve_kernel<3>, dim3(ne, nseg), dim3(EVOLVE_THREADS), 0, s, dtab, n, nseg,
-                                   tau, p->blockade, z, dout);
-            e = hipGetLastError();
-        }
-        // product of the segment channels in time order: S = S_{nseg-1} ... S_1 S_0, pairwise
-        double* cur = dout;
-        double* nxt = dtmp;
-        int cnt = nseg;
-        const long one = (long)ne * ne;   // complex elements of one channel
-        while (e == hipSuccess && cnt > 1) {
-            const int pairs = cnt / 2;
-            e = mpdo::cgemm<double>(s, ne, ne, ne, mpdo::cd{1.0, 0.0}, mpdo::view<double>(cur + 2 * one, ne, 1),
-                                    mpdo::view<double>(cur, ne, 1), mpdo::cd{0.0, 0.0}, mpdo::view<double>(nxt, ne, 1),
-                                    pairs, 2 * one, 2 * one, one);
-            if (e == hipSuccess && (cnt & 1))
-                e = hipMemcpyAsync(nxt + 2 * one * pairs, cur + 2 * one * (cnt - 1), one_b, hipMemcpyDeviceToDevice, s);
-            cnt = pairs + (cnt & 1);
-            std::swap(cur, nxt);
-        }
-        if (e == hipSuccess) e = hipMemcpyAsync(superop, cur, one_b, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) st = fail(MPDO_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+        st = pulse_run(p, omega, delta, superop, (hipStream_t)hip_stream, B);
     }
-    if (dsamp) (void)hipFree(dsamp);
-    if (dtab) (void)hipFree(dtab);
-    if (dout) (void)hipFree(dout);
-    if (dtmp) (void)hipFree(dtmp);
+    if (B.samp) (void)hipFree(B.samp);
+    if (B.tab) (void)hipFree(B.tab);
+    if (B.out) (void)hipFree(B.out);
+    if (B.tmp) (void)hipFree(B.tmp);
+    if (st == MPDO_OK) g_err.clear();
+    return st;
+}
+
+extern "C" mpdo_status mpdo_pulse_channel_noalloc(const mpdo_pulse_params* p, const double* omega,
+                                                  const double* delta, double* superop, void* hip_stream) {
+    mpdo_status st = check_params(p, omega, delta, superop);
+    if (st != MPDO_OK) return st;
+    const PulseSizes zs = pulse_sizes(p->d, p->n_steps);
+    if (zs.total() > PULSE_SCRATCH_BYTES)
+        return fail(MPDO_E_ARG, "n_steps too large for the fixed scratch of mpdo_pulse_channel_noalloc (" +
+                                    std::to_string(zs.total()) + " bytes needed, " +
+                                    std::to_string(PULSE_SCRATCH_BYTES) + " available)");
+    char* base = nullptr;
+    st = scratch_of_device(&base);
+    if (st != MPDO_OK) return st;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    PulseBufs B;
+    B.samp = (double*)base;
+    B.tab = (double*)(base + al(zs.samp_b));
+    B.out = (double*)(base + al(zs.samp_b) + al(zs.tab_b));
+    B.tmp = (double*)(base + al(zs.samp_b) + al(zs.tab_b) + al(zs.one_b * zs.nseg));
+    st = pulse_run(p, omega, delta, superop, (hipStream_t)hip_stream, B);
     if (st == MPDO_OK) g_err.clear();
     return st;
 }

@@ -15,7 +15,7 @@ import numpy as np
 
 from . import mpdo
 
-EXPORTS = ("mpdo_pulse_channel", "mpdo_pulse_last_error")
+EXPORTS = ("mpdo_pulse_channel", "mpdo_pulse_channel_noalloc", "mpdo_pulse_last_error")
 
 
 class PulseParams(C.Structure):
@@ -29,6 +29,8 @@ def _lib():
         dp = C.POINTER(C.c_double)
         lib.mpdo_pulse_channel.argtypes = [C.POINTER(PulseParams), dp, dp, dp, C.c_void_p]
         lib.mpdo_pulse_channel.restype = C.c_int
+        lib.mpdo_pulse_channel_noalloc.argtypes = [C.POINTER(PulseParams), dp, dp, dp, C.c_void_p]
+        lib.mpdo_pulse_channel_noalloc.restype = C.c_int
         lib.mpdo_pulse_last_error.argtypes = []
         lib.mpdo_pulse_last_error.restype = C.c_char_p
         lib._pulse_bound = True
@@ -36,11 +38,12 @@ def _lib():
 
 
 def channel(omega, delta, tau: float, d: int = 4, blockade: float = 0.0, gamma_diss: float = 0.0,
-            branch=(1.0 / 16, 1.0 / 16, 7.0 / 8), gamma_deph: float = 0.0) -> np.ndarray:
+            branch=(1.0 / 16, 1.0 / 16, 7.0 / 8), gamma_deph: float = 0.0, noalloc: bool = False) -> np.ndarray:
     """The pulse's two-atom channel: (d^4 x d^4) complex, rows eta_1 d^2 + eta_2 (per-atom
     vectorised index eta = sigma d + sigma'), ready for MPDO.apply_gate.  omega/delta: values at
     the middle of each of the len(omega) steps of length tau.  The default branching ratios are
-    the paper's (1/16, 1/16, 7/8); with d = 3 the dark branch must be 0."""
+    the paper's (1/16, 1/16, 7/8); with d = 3 the dark branch must be 0.  noalloc: use the entry
+    point that allocates no device memory (fixed per-device scratch; see mpdo_pulse.h)."""
     import torch
     if not torch.cuda.is_available():
         raise RuntimeError("the pulse channel is integrated on the GPU; no CPU fallback exists")
@@ -55,8 +58,8 @@ def channel(omega, delta, tau: float, d: int = 4, blockade: float = 0.0, gamma_d
     out = np.zeros((m2, m2), dtype=np.complex128)
     lib = _lib()
     dp = C.POINTER(C.c_double)
-    st = lib.mpdo_pulse_channel(C.byref(p), om.ctypes.data_as(dp), de.ctypes.data_as(dp),
-                                out.ctypes.data_as(dp), None)
+    fn = lib.mpdo_pulse_channel_noalloc if noalloc else lib.mpdo_pulse_channel
+    st = fn(C.byref(p), om.ctypes.data_as(dp), de.ctypes.data_as(dp), out.ctypes.data_as(dp), None)
     if st != 0:
         msg = lib.mpdo_pulse_last_error()
         raise mpdo.MpdoError(st, msg.decode() if msg else "")
