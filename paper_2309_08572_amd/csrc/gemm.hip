@@ -89,13 +89,24 @@ __device__ __forceinline__ void load_cplx(const T* p, long off, int conj, T& re,
 // WM: MFMA tiles per wave along each output dimension; block tile (32 WM) x (32 WM).
 // TF: 1 if B's operand transforms (bshift, bcol) may be set; the plain kernel keeps the
 // registers they need free (the FP64 64 x 64 kernel stays within two waves per SIMD).
+// LDS row padding.  A 16x16x4 MFMA step reads A[16 rows][4 k] and B[4 k][16 columns]; the
+// first 32 lanes cover 16 rows (columns) at 2 k.  FP64 elements take two 4-byte banks and the
+// +1 padding already spreads them; for FP32 a row stride of 2 (mod 32) words puts the A reads
+// on 32 distinct banks and a stride of 16 (mod 32) does the same for B (measured: about two
+// conflict cycles per LDS instruction with +1 padding in FP32, none in FP64).
+template <typename T>
+constexpr int PAD_A = std::is_same<T, float>::value ? 2 : 1;
+
+template <typename T, int BN>
+constexpr int PAD_B = std::is_same<T, float>::value ? 16 : 1;
+
 template <typename T, int WM, int TF>
 __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
     constexpr int BM = 32 * WM, BN = 32 * WM, WQ = 16 * WM;
-    __shared__ T sAr[BM][BK + 1];
-    __shared__ T sAi[BM][BK + 1];
-    __shared__ T sBr[BK][BN + 1];
-    __shared__ T sBi[BK][BN + 1];
+    __shared__ T sAr[BM][BK + PAD_A<T>];
+    __shared__ T sAi[BM][BK + PAD_A<T>];
+    __shared__ T sBr[BK][BN + PAD_B<T, BN>];
+    __shared__ T sBi[BK][BN + PAD_B<T, BN>];
     __shared__ double sbf[BN];   // column factors of B (b_col)
 
     const int tid = threadIdx.x;
@@ -103,9 +114,18 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
     const int wave = tid >> 6;
     const int wr = wave >> 1;
     const int wc = wave & 1;
-    const int m0 = blockIdx.y * BM;
-    const int n0 = blockIdx.x * BN;
-    const int bz = blockIdx.z;
+    // Logical tile of this workgroup.  Workgroups are handed to the eight XCDs in turn
+    // (linear id w to XCD w mod 8), each XCD with its own L2; mapping the w of one XCD onto a
+    // contiguous run of tiles (x fastest, then y, then batch) lets the workgroups that share
+    // A row panels and B column panels meet in the same L2.
+    const unsigned nx = gridDim.x, ny = gridDim.y;
+    const unsigned nw = nx * ny * gridDim.z;
+    const unsigned w = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const unsigned per = nw / 8, rem = nw % 8, xcd = w % 8;
+    const unsigned t = xcd * per + (xcd < rem ? xcd : rem) + w / 8;
+    const int m0 = (int)((t / nx) % ny) * BM;
+    const int n0 = (int)(t % nx) * BN;
+    const int bz = (int)(t / (nx * ny));
     const int b = bz / g.ksplit;
     const int kc = bz - b * g.ksplit;
     const int kbeg = kc * g.kchunk;

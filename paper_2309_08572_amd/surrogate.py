@@ -427,7 +427,8 @@ def calls_to_reach(hist, target: float) -> Optional[int]:
 
 
 def experiment(task: Task, n_data: int, epochs: int, rate_sets, budget: int, runs: int = 3,
-               proposals: int = 4, seed: int = 0, widths=None, n_workers: int = 16, log=print) -> dict:
+               proposals: int = 4, seed: int = 0, widths=None, n_workers: int = 16, log=print,
+               chunk: int = 2048) -> dict:
     """Dataset -> training -> for each noise setting: reference optimum, then the simulator calls
     the plain and the guided search need to come within 1e-3 of it."""
     def say(msg):
@@ -435,7 +436,7 @@ def experiment(task: Task, n_data: int, epochs: int, rate_sets, budget: int, run
 
     t0 = time.time()
     sim = Simulator(task, n_workers)
-    X, Y, _, _ = make_dataset(sim, n_data, seed, log=log)
+    X, Y, _, _ = make_dataset(sim, n_data, seed, chunk=chunk, log=log)
     t_data = time.time() - t0
     say("dataset of %d circuits in %.1f s" % (n_data, t_data))
     widths = widths or [task.n_in, 256, 256, 256, 2]
@@ -489,12 +490,14 @@ def main():
     ap.add_argument("--rates", type=float, nargs=3, action="append",
                     help="noise setting (leak, dephasing, decay); repeat for several")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--proposals", type=int, default=4)
+    ap.add_argument("--chunk", type=int, default=2048, help="circuits per batch call while building the data")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     task = Task(n=a.n, p=a.p, chi=a.chi)
     rate_sets = a.rates or [[1e-3, 1e-3, 1e-3]]
     res = experiment(task, a.data, a.epochs, rate_sets, budget=a.budget, runs=a.runs, seed=a.seed,
-                     log=lambda m: print(m, flush=True))
+                     proposals=a.proposals, chunk=a.chunk, log=lambda m: print(m, flush=True))
     line = json.dumps(res)
     print(line)
     if a.out:
