@@ -26,14 +26,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def _cpu_baseline(spec, budget_s: float) -> dict:
-    """The CPU oracle on a bounded sample of the same circuit, extrapolated per layer."""
-    import numpy as np
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+def _oracle_sample(spec, budget_s: float):
+    """The oracle on the circuit's two-site updates in order until budget_s has passed:
+    (per-layer update times, updates done, seconds)."""
     from oracle import channels as ch
     from oracle import mpo
     ops = ch.circuit_ops(spec)
@@ -54,21 +49,68 @@ def _cpu_baseline(spec, budget_s: float) -> dict:
             m.apply_1site(site, ch.superop_1site(kraus))
         if time.time() - t0 > budget_s:
             break
-    done = sum(len(v) for v in per_layer.values())
-    total = 0.0
+    return per_layer, sum(len(v) for v in per_layer.values()), time.time() - t0
+
+
+def _extrapolate(spec, per_layer) -> float:
+    """Circuit seconds from each reached layer's mean update time (later layers as the last)."""
+    import numpy as np
     reached = sorted(per_layer)
+    total = 0.0
     for k in range(spec.p):
-        times = per_layer.get(k, per_layer[reached[-1]])
-        total += float(np.mean(times)) * (spec.n - 1)
-    return {
-        "value": (spec.p * (spec.n - 1)) / total,
+        total += float(np.mean(per_layer.get(k, per_layer[reached[-1]]))) * (spec.n - 1)
+    return total
+
+
+def _blas():
+    try:
+        from threadpoolctl import threadpool_info
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            return (f"{info[0].get('internal_api')} {info[0].get('version')}",
+                    max(int(i.get("num_threads", 1)) for i in info))
+    except Exception:
+        pass
+    return "unknown", os.cpu_count() or 1
+
+
+def _cpu_baseline(spec, budget_s: float, small_specs=()) -> dict:
+    """The CPU oracle (numpy + LAPACK SVD, FP64; the oracle as it stands) on the host: a bounded
+    sample of the benchmark circuit on all BLAS threads, the circuit time extrapolated per
+    layer (the headline record), the same sample on one thread (a third of the budget), and
+    the small circuits in small_specs timed in full."""
+    vendor, threads = _blas()
+    per_layer, done, secs = _oracle_sample(spec, budget_s)
+    rec = {
+        "value": (spec.p * (spec.n - 1)) / _extrapolate(spec, per_layer),
         "unit": "two-site updates/s",
         "cores": int(threads),
         "kind": "oracle",
+        "blas": vendor,
         "sample": (f"CPU oracle (numpy/LAPACK SVD, FP64) on the first {done} two-site updates "
-                   f"of the same circuit ({time.time() - t0:.1f} s), circuit time extrapolated "
-                   f"from each layer's mean update time (layers reached: {len(reached)})"),
+                   f"of the same circuit ({secs:.1f} s), circuit time extrapolated "
+                   f"from each layer's mean update time (layers reached: {len(per_layer)})"),
     }
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1, user_api="blas"):
+            pl1, done1, secs1 = _oracle_sample(spec, budget_s / 3.0)
+        rec["single_thread"] = {"value": (spec.p * (spec.n - 1)) / _extrapolate(spec, pl1),
+                                "unit": "two-site updates/s", "cores": 1,
+                                "sample": f"first {done1} two-site updates ({secs1:.1f} s), extrapolated per layer"}
+    except Exception as e:   # threadpoolctl missing: the record says so
+        rec["single_thread"] = {"error": str(e)}
+    full = {}
+    for name, sp in small_specs:
+        t0 = time.time()
+        from oracle import mpo
+        mpo.run_spec(sp)
+        dt = time.time() - t0
+        full[name] = {"seconds": dt, "two_site_updates": sp.n_two_site_updates(),
+                      "updates_per_s": sp.n_two_site_updates() / dt}
+    if full:
+        rec["full_circuits"] = full
+    return rec
 
 
 def _batch(count: int, workers: int) -> dict:
@@ -120,7 +162,21 @@ def _second_order(spec, reps: int) -> dict:
     return out
 
 
-def _saturated(max_warm: int, precisions) -> dict:
+def _oracle_on_state(bonds, sites, centre, bond, kraus, d, chi):
+    """The CPU oracle's two-site update of `bond` on the given chain (FP64 site tensors, canonical
+    about `centre`, no queued maps): (seconds, the oracle's cut record)."""
+    from oracle import channels as ch
+    from oracle import mpo
+    m = mpo.MPO([ch.plus_state(d)] * len(sites), chi=chi)
+    m.A = [a.copy() for a in sites]
+    m.lo = m.hi = centre
+    S2 = ch.superop_2site(kraus, d)
+    t0 = time.time()
+    info = m.apply_2site(bond, S2)
+    return time.time() - t0, info
+
+
+def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
     """The saturated steady state at chi = 512, FP32 matrix cores against FP64 on the same updates.
 
     The benchmark circuit's gate set (seed-0 angles, rates 1e-3) runs on a 20-atom chain in FP64,
@@ -165,6 +221,9 @@ def _saturated(max_warm: int, precisions) -> dict:
         a.apply_gate_kraus(i, kr)
     b = mpdo.MPDO(n, d, chi, precision=mpdo.MPDO_FP32) if "fp32" in precisions else None
     fams = ("theta", "gemm", "tri_reduce", "tri_solve", "tri_back", "eig_small", "phys", "other")
+    cpu = []   # the CPU oracle on the same saturated updates (cpu_updates of them)
+    from oracle import channels as och
+    okraus = och.gate_kraus_2site(spec.gamma[warm], spec.p_leak, d)
     acc = {"fp64": {"t": [], "prof": None, "kept": []}, "fp32": {"t": [], "prof": None, "kept": []}}
     errs_e, errs_p = [], []
 
@@ -192,12 +251,24 @@ def _saturated(max_warm: int, precisions) -> dict:
         # the update alone and the FP32 context starts from exactly the FP64 chain (an FP32
         # canonical move would itself compress the bonds it crosses to what FP32 resolves)
         a.move_centre(i + 1)
-        if b is not None:
+        ocase = None
+        if b is not None or len(cpu) < cpu_updates:
             bonds, sites, centre = a.get_state()
-            b.set_state(bonds, sites, centre)
+            if b is not None:
+                b.set_state(bonds, sites, centre)
+                timed(b, i, "fp32")
+            if len(cpu) < cpu_updates:
+                ocase = _oracle_on_state(bonds, sites, centre, i, okraus, d, chi)
             del sites
-            timed(b, i, "fp32")
-        timed(a, i, "fp64")
+        ginf = timed(a, i, "fp64")
+        if ocase is not None:
+            osec, oinf = ocase
+            cpu.append({"bond": i, "seconds": osec, "kept": oinf["kept"], "gpu_kept": ginf["kept"],
+                        "rel_err_trace_before": abs(ginf["trace_before"] - oinf["trace_before"]) / abs(oinf["trace_before"]),
+                        "rel_err_xi_before": abs(ginf["xi_before"] - oinf["xi_before"]) / abs(oinf["xi_before"]),
+                        "rel_err_trace_after": abs(ginf["trace_after"] - oinf["trace_after"]) / abs(oinf["trace_after"]),
+                        "abs_err_discarded_weight": abs(ginf["discarded_weight"] - oinf["discarded_weight"]),
+                        "oracle_gap_at_cut": oinf["gap_at_cut"], "gpu_sigma_gap_at_cut": ginf["sigma_gap_at_cut"]})
         if b is not None:
             oa, ob = circuits.observables(a), circuits.observables(b)
             errs_e.append(abs(oa["energy_per_site"] - ob["energy_per_site"]))
@@ -240,6 +311,12 @@ def _saturated(max_warm: int, precisions) -> dict:
     a.close()
     if b is not None:
         b.close()
+    if cpu:
+        vendor, threads = _blas()
+        res["cpu_oracle"] = {"updates": cpu, "seconds_per_update": float(np.mean([c["seconds"] for c in cpu])),
+                             "cores": threads, "blas": vendor,
+                             "note": "the CPU oracle (numpy/LAPACK SVD of the 8192 x 8192 theta) on the same "
+                                     "saturated updates, from the FP64 GPU chain; its cut record beside the GPU's"}
     out = {"workload": f"noisy QAOA gate set, N={n} atoms, d=4, chi_max={chi}, seed 0, rates 1e-3: FP64 layers "
                        f"until the centre bonds reach {chi} ({warm} layers), the even bonds of the next; then each "
                        f"odd-bond update with chi_l = chi_m = chi_r = {chi} run from the same state in FP64 and "
@@ -422,6 +499,8 @@ def main() -> int:
     ap.add_argument("--saturated-layers", type=int, default=8,
                     help="at most this many untimed layers before the saturated chi=512 updates are timed "
                          "(0: skip that leg)")
+    ap.add_argument("--cpu-saturated", type=int, default=0,
+                    help="also run the CPU oracle on this many of the saturated chi=512 updates (minutes each)")
     ap.add_argument("--crosstalk-layers", type=int, default=3,
                     help="layers of the crosstalk-gate leg (the first is untimed); 0 skips it")
     ap.add_argument("--second-order-reps", type=int, default=3,
@@ -532,7 +611,7 @@ def main() -> int:
     if args.pulse_steps > 0:
         out["pulse_gate"] = _pulse_gate(args.pulse_steps)
     if args.saturated_layers > 0:
-        out["saturated"] = _saturated(args.saturated_layers, run)
+        out["saturated"] = _saturated(args.saturated_layers, run, args.cpu_saturated)
     if args.second_order_reps > 0:
         try:
             out["second_order"] = _second_order(spec, args.second_order_reps)
@@ -544,7 +623,10 @@ def main() -> int:
         except Exception as e:   # a rejected gate (bond too large for chi_max) is reported, not fatal
             out["crosstalk"] = {"error": str(e)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(spec, args.cpu_baseline_seconds)
+        from workloads import config_m0, config_m1
+        out["cpu_baseline"] = _cpu_baseline(spec, args.cpu_baseline_seconds,
+                                            small_specs=(("m0_n6_d3_p1", config_m0(0)),
+                                                         ("m1_n40_d4_p2_chi128", config_m1(0))))
     print(json.dumps(out))
     return 0
 

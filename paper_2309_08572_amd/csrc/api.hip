@@ -725,7 +725,9 @@ struct Engine {
                 gemm(a, a, b, C1(), R, adj(R), C0(), V<T>(s.bG, a, 1));
                 HIPCHK((geam<T, double>(st, a, a, C1(), V<T>(s.bG, a, 1), C0(), V<double>(s.Gd, a, 1))));
             }
-            const double tau = (lev == 0) ? 1e-4 : 0.0;
+            // level 0 accepts lambda > 1e-6 lambda_max (sigma > 1e-3 sigma_max); what lies below is
+            // resolved by the residual levels with a smaller backward error
+            const double tau = (lev == 0) ? 1e-6 : 0.0;
             // one pair beyond the chi cap is asked for: when it is accepted, the cap decides the
             // cut at this level and its value is the largest discarded Schmidt value, left in
             // s.sig[chi] (the gap at the cut; ties there make the truncated state non-unique)

@@ -87,8 +87,11 @@ def test_cpu_baseline_record_on_a_small_circuit():
     pytest.importorskip("numpy")
     from workloads import config_m0
     spec = config_m0(0)
-    rec = bench._cpu_baseline(spec, 2.0)
+    rec = bench._cpu_baseline(spec, 2.0, small_specs=(("m0", spec),))
     assert rec["kind"] == "oracle" and rec["unit"] == "two-site updates/s"
     assert rec["value"] > 0.0 and rec["cores"] >= 1
     assert isinstance(rec["sample"], str) and rec["sample"]
+    assert isinstance(rec["blas"], str)
+    assert rec["single_thread"].get("cores", 1) == 1
+    assert rec["full_circuits"]["m0"]["two_site_updates"] == spec.n_two_site_updates()
     json.dumps(rec)
