@@ -499,6 +499,8 @@ def main() -> int:
     ap.add_argument("--saturated-layers", type=int, default=8,
                     help="at most this many untimed layers before the saturated chi=512 updates are timed "
                          "(0: skip that leg)")
+    ap.add_argument("--saturated-only", action="store_true",
+                    help="run only the saturated chi=512 leg and print its record (for profiling)")
     ap.add_argument("--cpu-saturated", type=int, default=0,
                     help="also run the CPU oracle on this many of the saturated chi=512 updates (minutes each)")
     ap.add_argument("--crosstalk-layers", type=int, default=3,
@@ -522,6 +524,9 @@ def main() -> int:
     updates = spec.n_two_site_updates()
     modes = {"fp64": mpdo.MPDO_FP64, "fp32": mpdo.MPDO_FP32}
     run = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
+    if args.saturated_only:
+        print(json.dumps({"saturated": _saturated(max(1, args.saturated_layers), run, args.cpu_saturated)}))
+        return 0
     results = {}
     for name in run:
         m = mpdo.MPDO(spec.n, spec.d, spec.chi, precision=modes[name])

@@ -360,6 +360,7 @@ struct Engine {
     // the rounding floor); -2 - level, the cap was met with the next value below the threshold
     // of that deflation level (s.st[1 + level], an eigenvalue bound).
     int cut_next = -1;
+    bool theta_check = false;   // sc[4..5] (||theta||^2, non-finite count) awaits the next orth_verify
 
     Engine(mpdo_ctx_s& ctx, Scratch<T>& sc) : c(ctx), s(sc), st(ctx.st) {}
 
@@ -514,11 +515,18 @@ struct Engine {
     }
     void orth_verify() {
         const bool dbg = getenv("MPDO_DEBUG_CHECKS") != nullptr;
-        if (nchk == 0) return;
+        if (nchk == 0 && !theta_check) return;
         const int m = nchk;
         nchk = 0;
-        double buf[2 * NCHK];
-        read_doubles(s.odev, 2 * m, buf);
+        double buf[2 * NCHK], th[2] = {0.0, 0.0};
+        if (theta_check) {
+            // ||theta||^2 and the non-finite count of the merged tensor (sc[4..5]) in the same copy
+            read_doubles2(s.odev, 2 * std::max(m, 1), buf, s.sc + 4, 2, th);
+            theta_check = false;
+            if (th[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
+        } else {
+            read_doubles(s.odev, 2 * m, buf);
+        }
         const double tol = std::is_same<T, double>::value ? 1e-9 : 1e-3;
         for (int k = 0; k < m; ++k) {
             const double dev = buf[2 * k] / chk_q[k] - 1.0;
@@ -934,10 +942,7 @@ struct Engine {
             gemm(q, nb, k, C1(), V<T>(s.bK, k, 1), Fb, C0(), V<T>(s.bC, nb, 1));
             // ||theta||^2 (= ||C||^2) and its non-finite count stay in sc[4..5] for PPT
             HIPCHK(sumsq<T>(st, V<T>(s.bC, nb, 1), q, nb, s.sc + 4, s.sqp, s.sqc));
-            double sums[2];
-            read_doubles(s.sc + 4, 2, sums);
-            if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
-            n2 = sums[0];
+            theta_check = true;   // its non-finite count is read with the basis checks
             kept = svd_left(V<T>(s.bC, nb, 1), q, nb, chi, s.bU2);
             if (kept <= 0) throw Fail{MPDO_E_NUMERIC, "empty spectrum"};
             if (dir > 0) {
@@ -975,10 +980,7 @@ struct Engine {
             HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
             HIPCHK(dot(st, s.lvec, s.vtmp, nL, s.sc));
             HIPCHK(sumsq<T>(st, Th, nL, nR, s.sc + 4, s.sqp, s.sqc));
-            double sums[2];
-            read_doubles(s.sc + 4, 2, sums);
-            if (sums[1] != 0.0) throw Fail{MPDO_E_NUMERIC, "non-finite entries in the merged tensor"};
-            n2 = sums[0];
+            theta_check = true;   // its non-finite count is read with the basis checks
             CView<T> Fa = dir > 0 ? Th : adj(Th);
             if (std::min(na, nb) > subspace_min_order()) {
                 // range basis by subspace iteration, then the exact split of the q x nb core
@@ -1023,8 +1025,9 @@ struct Engine {
         site_changed(i + 1);
         c.centre = dir > 0 ? i + 1 : i;
         if (info) {
-            double po[16], sg[2];
-            read_doubles(s.pout, 13, po);
+            double po[16], sg[2], nn[2];
+            read_doubles2(s.pout, 13, po, s.sc + 4, 2, nn);
+            n2 = nn[0];
             read_doubles(s.sig, 1, sg);
             double smin = 0.0;
             read_doubles(s.sig + (kept - 1), 1, &smin);

@@ -12,9 +12,8 @@
 // diagonal blocks, not a sequential tridiagonal reduction of order 768.
 //
 //   chol_shift_kernel  s from the trace of G (one workgroup; no host synchronisation)
-//   chol_diag_kernel   one wave: the 64 x 64 diagonal block factored in LDS (right-looking,
-//                      column by column) and its lower-triangular inverse by forward
-//                      substitution, one column per lane
+//   chol_diag_kernel   one workgroup: the 64 x 64 diagonal block factored in LDS
+//                      (right-looking, one barrier per column) and its lower-triangular inverse
 //   panel and trailing updates, and the block triangular solve, run on the matrix-core GEMM.
 #include <math.h>
 
@@ -46,76 +45,90 @@ __global__ __launch_bounds__(256) void chol_shift_kernel(const double* __restric
 // (ld ldl) receives the factor (zeros above the diagonal) and Li (kb x kb, ld CB) its inverse.
 // A pivot that is not positive and finite sets flag[0] = 1 and is replaced by 1 (the result is
 // then discarded by the caller).
-__global__ __launch_bounds__(64) void chol_diag_kernel(const double* __restrict__ A, long lda, int k0, int kb,
+//
+// The block lives in LDS; thread (c, h) = (t mod 64, t / 64) works on column c, rows c + h + 4 k.
+// Step j of the right-looking factorisation reads column j, final since step j - 1, and applies
+// a_rc -= a_rj conj(a_cj) / a_jj to the rows r >= c of the columns c > j, so that one barrier per
+// step suffices; the columns are scaled by 1 / sqrt(a_jj) at the end.  The inverse X = L^{-1}
+// follows the same pattern: y_c = e_c, step q subtracts L_rq y_qc / L_qq from the rows r > q,
+// and X_rc = y_rc / L_rr at the end.
+constexpr int DT = 256;   // threads of chol_diag_kernel
+__global__ __launch_bounds__(DT) void chol_diag_kernel(const double* __restrict__ A, long lda, int k0, int kb,
                                                        const double* __restrict__ shift, double* __restrict__ L,
                                                        long ldl, double* __restrict__ Li, int* __restrict__ flag) {
-    __shared__ double ar[CB][CB + 1], ai[CB][CB + 1];
-    __shared__ double xr_s[CB][CB + 1], xi_s[CB][CB + 1];
-    const int lane = threadIdx.x;
+    __shared__ double Ar[CB][CB + 1], Am[CB][CB + 1];   // the block, then its factor
+    __shared__ double Yr[CB][CB + 1], Ym[CB][CB + 1];   // the inverse
+    __shared__ double dg[CB];                           // sqrt of the pivots
+    const int t = threadIdx.x, c = t & (CB - 1), h = t >> 6;
     const double s = shift ? shift[0] : 0.0;
-    for (int idx = lane; idx < kb * kb; idx += 64) {
-        const int r = idx / kb, c = idx - (idx / kb) * kb;
-        double xr = 0.0, xi = 0.0;
-        if (r >= c) {
+    for (int r = h; r < CB; r += 4) {
+        double vr = 0.0, vi = 0.0;
+        if (r < kb && c < kb && r >= c) {
             const double* a = A + 2 * ((long)(k0 + r) * lda + (k0 + c));
-            xr = a[0];
-            xi = r == c ? 0.0 : a[1];
-            if (r == c) xr += s;
+            vr = a[0];
+            vi = r == c ? 0.0 : a[1];
         }
-        ar[r][c] = xr;
-        ai[r][c] = xi;
+        Ar[r][c] = r == c && c < kb ? vr + s : vr;
+        Am[r][c] = vi;
     }
     __syncthreads();
     for (int j = 0; j < kb; ++j) {
-        double p = ar[j][j];
+        double p = Ar[j][j];
+        if (!(p > 0.0) || !isfinite(p)) p = 1.0;
+        if (c > j && c < kb) {
+            const double rp = 1.0 / p;
+            const double yr = Ar[c][j] * rp, yi = -Am[c][j] * rp;   // conj(a_cj) / a_jj
+            for (int r = c + h; r < kb; r += 4) {
+                const double xr = Ar[r][j], xi = Am[r][j];
+                Ar[r][c] -= xr * yr - xi * yi;
+                Am[r][c] -= xr * yi + xi * yr;
+            }
+        }
+        __syncthreads();
+    }
+    // scale the columns; the factor to global memory (zero above the diagonal) and to LDS
+    if (t < CB) {
+        double p = t < kb ? Ar[t][t] : 1.0;
         if (!(p > 0.0) || !isfinite(p)) {
-            if (lane == 0) flag[0] = 1;
+            if (t < kb) flag[0] = 1;
             p = 1.0;
         }
-        const double dj = sqrt(p), rdj = 1.0 / dj;
-        __syncthreads();
-        if (lane == 0) ar[j][j] = dj;
-        for (int r = j + 1 + lane; r < kb; r += 64) {
-            ar[r][j] *= rdj;
-            ai[r][j] *= rdj;
-        }
-        __syncthreads();
-        // trailing lower part: a_rc -= l_rj conj(l_cj), j < c <= r
-        const int w = kb - j - 1;
-        for (int idx = lane; idx < w * w; idx += 64) {
-            const int r = j + 1 + idx / w, c = j + 1 + (idx - (idx / w) * w);
-            if (c > r) continue;
-            const double xr = ar[r][j], xi = ai[r][j], yr = ar[c][j], yi = ai[c][j];
-            ar[r][c] -= xr * yr + xi * yi;
-            ai[r][c] -= xi * yr - xr * yi;
-        }
-        __syncthreads();
+        dg[t] = sqrt(p);
     }
-    // the factor, zero above the diagonal
-    for (int idx = lane; idx < kb * kb; idx += 64) {
-        const int r = idx / kb, c = idx - (idx / kb) * kb;
-        double* l = L + 2 * ((long)(k0 + r) * ldl + (k0 + c));
-        l[0] = r >= c ? ar[r][c] : 0.0;
-        l[1] = r > c ? ai[r][c] : 0.0;
+    __syncthreads();
+    const double rdc = 1.0 / dg[c];
+    for (int r = h; r < CB; r += 4) {
+        const bool low = r > c && r < kb && c < kb;
+        const double lr = r == c ? dg[c] : (low ? Ar[r][c] * rdc : 0.0);
+        const double li = low ? Am[r][c] * rdc : 0.0;
+        Ar[r][c] = lr;
+        Am[r][c] = li;
+        Yr[r][c] = r == c ? 1.0 : 0.0;
+        Ym[r][c] = 0.0;
+        if (r < kb && c < kb) {
+            double* l = L + 2 * ((long)(k0 + r) * ldl + (k0 + c));
+            l[0] = lr;
+            l[1] = li;
+        }
     }
-    // inverse, column c per lane (in LDS): X[r][c] = (delta_rc - sum_{c <= q < r} L[r][q] X[q][c]) / L[r][r]
-    if (lane < kb) {
-        const int c = lane;
-        for (int r = 0; r < kb; ++r) {
-            double sr = r == c ? 1.0 : 0.0, si = 0.0;
-            for (int q = c; q < r; ++q) {
-                const double lr = ar[r][q], li = ai[r][q], yr = xr_s[q][c], yi = xi_s[q][c];
-                sr -= lr * yr - li * yi;
-                si -= lr * yi + li * yr;
+    __syncthreads();
+    for (int q = 0; q < kb; ++q) {
+        if (c <= q) {
+            const double rq = 1.0 / Ar[q][q];
+            const double yr = Yr[q][c] * rq, yi = Ym[q][c] * rq;
+            int r = q + 1 + ((h - (q + 1)) & 3);   // first row > q of this thread's slice
+            for (; r < kb; r += 4) {
+                const double lr = Ar[r][q], li = Am[r][q];
+                Yr[r][c] -= lr * yr - li * yi;
+                Ym[r][c] -= lr * yi + li * yr;
             }
-            const double rd = 1.0 / ar[r][r];
-            xr_s[r][c] = r < c ? 0.0 : sr * rd;
-            xi_s[r][c] = r < c ? 0.0 : si * rd;
         }
-        for (int r = 0; r < kb; ++r) {
-            Li[2 * ((long)r * CB + c)] = xr_s[r][c];
-            Li[2 * ((long)r * CB + c) + 1] = xi_s[r][c];
-        }
+        __syncthreads();
+    }
+    for (int r = h; r < kb; r += 4) {
+        const double rr = 1.0 / Ar[r][r];
+        Li[2 * ((long)r * CB + c)] = c < kb ? Yr[r][c] * rr : 0.0;
+        Li[2 * ((long)r * CB + c) + 1] = c < kb ? Ym[r][c] * rr : 0.0;
     }
 }
 
@@ -135,7 +148,7 @@ hipError_t cholesky_lower(hipStream_t s, double* A, long lda, int m, double shif
     for (int k0 = 0; k0 < m; k0 += CB) {
         const int kb = m - k0 < CB ? m - k0 : CB;
         double* Lik = Li + (size_t)(k0 / CB) * CB * CB * 2;
-        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, s, A, lda, k0, kb, shift_coef > 0.0 ? sh : nullptr,
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(DT), 0, s, A, lda, k0, kb, shift_coef > 0.0 ? sh : nullptr,
                            L, ldl, Lik, flag);
         const int rest = m - k0 - kb;
         if (rest <= 0) break;

@@ -117,3 +117,25 @@ def test_parallel_lambda_and_t(k):
     lt, info = P.ppt(lam, T, k)
     assert info["degenerate_sigma"]
     np.testing.assert_allclose(lt, lam[:k])
+
+
+def test_renorm_trace_option_keeps_the_trace_and_the_normalised_observables():
+    """The oracle's optional trace renormalisation (a reading: the paper leaves the trace after
+    PPT as the cut leaves it): on a heavily truncating circuit (chi 16) the plain run's trace
+    drifts, the renormalised run's final trace is 1 to rounding (every channel is trace
+    preserving, so only the cuts could change it), and the normalised observables of the two
+    runs agree (every later step is linear in rho or, like PPT and the relative cutoff,
+    equivariant under rho -> c rho)."""
+    from oracle import mpo
+    from workloads import random_spec
+    spec = random_spec(seed=8, n=8, d=4, p=3, chi=16, rate_lo=1e-3, rate_hi=1e-2)
+    a = mpo.run_spec(spec)
+    b = mpo.run_spec(spec, renorm_trace=True)
+    assert abs(a.trace() - 1.0) > 1e-3
+    assert abs(b.trace() - 1.0) < 1e-12
+    cuts = [x for x in b.log if x["discarded_weight"] > 1e-12]
+    assert len(cuts) >= 5
+    oa, ob = mpo.observables(a), mpo.observables(b)
+    assert abs(oa["energy_per_site"] - ob["energy_per_site"]) < 1e-12
+    np.testing.assert_allclose(oa["populations"], ob["populations"], rtol=0, atol=1e-12)
+    assert abs(oa["p_success"] - ob["p_success"]) < 1e-12
