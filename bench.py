@@ -177,7 +177,8 @@ def _oracle_on_state(bonds, sites, centre, bond, kraus, d, chi):
 
 
 def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
-    """The saturated steady state at chi = 512, FP32 matrix cores against FP64 on the same updates.
+    """The saturated steady state at chi = 512, FP32 and split-BF16 matrix cores against FP64 on
+    the same updates.
 
     The benchmark circuit's gate set (seed-0 angles, rates 1e-3) runs on a 20-atom chain in FP64,
     untimed, layer by layer until the three centre bonds are at 512 (at most `max_warm` layers),
@@ -185,11 +186,11 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
     its queued single-atom maps, so the state is the chain alone.  Each update of the odd bonds
     whose three bonds are all 512 (theta of 8192 x 8192, rank <= 4608) is then run twice from
     the same state, the canonical centre already on the pair (moved there untimed in FP64): by
-    the FP64 context, and by an FP32 context loaded with that state (mpdo_set_state with the
-    FP64 context's canonical centre).  Both are timed, bracketed by
+    the FP64 context, and by an FP32 and a split-BF16 context loaded with that state
+    (mpdo_set_state with the FP64 context's canonical centre).  All are timed, bracketed by
     synchronisations, with HIP events on the theta contraction (merge and gate products), the
     other products and the eigensolver families; after each, the per-site energy and the
-    populations of the two results are compared.  The per-update cost does not depend on N
+    populations of each result are compared with the FP64 one.  The per-update cost does not depend on N
     (only on the three bond dimensions and d), so the 20-atom chain stands for the saturated
     bulk of the N=100 chain."""
     import numpy as np
@@ -219,13 +220,16 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
     kr = circuits.block_kraus(spec.gamma[warm], spec.p_leak, d)
     for i in range(0, n - 1, 2):
         a.apply_gate_kraus(i, kr)
-    b = mpdo.MPDO(n, d, chi, precision=mpdo.MPDO_FP32) if "fp32" in precisions else None
+    # the other precisions, each loaded with the FP64 state before every timed update
+    others = {k: mpdo.MPDO(n, d, chi, precision=v) for k, v in
+              (("fp32", mpdo.MPDO_FP32), ("bf16x3", mpdo.MPDO_BF16X3)) if k in precisions}
     fams = ("theta", "gemm", "tri_reduce", "tri_solve", "tri_back", "eig_small", "phys", "other")
     cpu = []   # the CPU oracle on the same saturated updates (cpu_updates of them)
     from oracle import channels as och
     okraus = och.gate_kraus_2site(spec.gamma[warm], spec.p_leak, d)
-    acc = {"fp64": {"t": [], "prof": None, "kept": []}, "fp32": {"t": [], "prof": None, "kept": []}}
-    errs_e, errs_p = [], []
+    acc = {k: {"t": [], "prof": None, "kept": []} for k in ["fp64"] + list(others)}
+    errs_e = {k: [] for k in others}
+    errs_p = {k: [] for k in others}
 
     def timed(m, i, key):
         m.profile(True)
@@ -252,11 +256,11 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
         # canonical move would itself compress the bonds it crosses to what FP32 resolves)
         a.move_centre(i + 1)
         ocase = None
-        if b is not None or len(cpu) < cpu_updates:
+        if others or len(cpu) < cpu_updates:
             bonds, sites, centre = a.get_state()
-            if b is not None:
+            for key, b in others.items():
                 b.set_state(bonds, sites, centre)
-                timed(b, i, "fp32")
+                timed(b, i, key)
             if len(cpu) < cpu_updates:
                 ocase = _oracle_on_state(bonds, sites, centre, i, okraus, d, chi)
             del sites
@@ -269,17 +273,20 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
                         "rel_err_trace_after": abs(ginf["trace_after"] - oinf["trace_after"]) / abs(oinf["trace_after"]),
                         "abs_err_discarded_weight": abs(ginf["discarded_weight"] - oinf["discarded_weight"]),
                         "oracle_gap_at_cut": oinf["gap_at_cut"], "gpu_sigma_gap_at_cut": ginf["sigma_gap_at_cut"]})
-        if b is not None:
-            oa, ob = circuits.observables(a), circuits.observables(b)
-            errs_e.append(abs(oa["energy_per_site"] - ob["energy_per_site"]))
-            errs_p.append(float(np.max(np.abs(oa["populations"] - ob["populations"]))))
+        if others:
+            oa = circuits.observables(a)
+            for key, b in others.items():
+                ob = circuits.observables(b)
+                errs_e[key].append(abs(oa["energy_per_site"] - ob["energy_per_site"]))
+                errs_p[key].append(float(np.max(np.abs(oa["populations"] - ob["populations"]))))
     res = {}
-    for key in ("fp64", "fp32"):
+    for key in acc:
         t, prof = acc[key]["t"], acc[key]["prof"]
         if not t:
             continue
         tot = float(np.sum(t))
-        peak = PEAK["fp64_mfma"] if key == "fp64" else PEAK["fp32_mfma"]
+        # split-BF16: three BF16 products per real product, judged against a third of the BF16 peak
+        peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"] / 3}[key]
         fam_rec = {}
         for f in fams:
             v = prof[f]
@@ -289,7 +296,8 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
             if f in ("theta", "gemm"):
                 r["flop"] = v["flops"]
                 r["tflops"] = v["flops"] / (1e-3 * v["ms"]) / 1e12 if v["ms"] else 0.0
-                r["frac_of_peak"] = r["tflops"] / peak
+                # the gemm family mixes split-BF16 products with plain FP32 ones in bf16x3 mode
+                r["frac_of_peak"] = r["tflops"] / (peak if f == "theta" or key != "bf16x3" else PEAK["fp32_mfma"])
             fam_rec[f] = r
         th = prof["theta"]
         res[key] = {
@@ -309,7 +317,7 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
             "mfma_algorithmic_tflops_per_update_time": 2.9e12 * len(t) / tot / 1e12,
         }
     a.close()
-    if b is not None:
+    for b in others.values():
         b.close()
     if cpu:
         vendor, threads = _blas()
@@ -319,15 +327,16 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
                                      "saturated updates, from the FP64 GPU chain; its cut record beside the GPU's"}
     out = {"workload": f"noisy QAOA gate set, N={n} atoms, d=4, chi_max={chi}, seed 0, rates 1e-3: FP64 layers "
                        f"until the centre bonds reach {chi} ({warm} layers), the even bonds of the next; then each "
-                       f"odd-bond update with chi_l = chi_m = chi_r = {chi} run from the same state in FP64 and "
-                       f"in FP32 (state loaded with mpdo_set_state)",
+                       f"odd-bond update with chi_l = chi_m = chi_r = {chi} run from the same state in FP64, "
+                       f"FP32 and split-BF16 (state loaded with mpdo_set_state)",
            "untimed_layers": warm, **res}
-    if "fp64" in res and "fp32" in res:
-        out["fp32_speedup_vs_fp64"] = res["fp64"]["ms_per_update"] / res["fp32"]["ms_per_update"]
-        out["fp32_theta_speedup_vs_fp64"] = (res["fp64"]["theta_contraction"]["ms_per_update"] /
-                                             res["fp32"]["theta_contraction"]["ms_per_update"])
-        out["fp32_abs_err_energy_per_site_vs_fp64_max"] = max(errs_e)
-        out["fp32_abs_err_populations_vs_fp64_max"] = max(errs_p)
+    for key in others:
+        if "fp64" in res and key in res:
+            out[f"{key}_speedup_vs_fp64"] = res["fp64"]["ms_per_update"] / res[key]["ms_per_update"]
+            out[f"{key}_theta_speedup_vs_fp64"] = (res["fp64"]["theta_contraction"]["ms_per_update"] /
+                                                   res[key]["theta_contraction"]["ms_per_update"])
+            out[f"{key}_abs_err_energy_per_site_vs_fp64_max"] = max(errs_e[key])
+            out[f"{key}_abs_err_populations_vs_fp64_max"] = max(errs_p[key])
     return out
 
 
@@ -394,7 +403,7 @@ def _crosstalk(layers: int) -> dict:
             "max_bond": max(bonds), "trace": [tr.real, tr.imag]}
 
 
-PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp64_vector": 78.6, "hbm_gbs": 8000.0}
+PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2500.0, "fp64_vector": 78.6, "hbm_gbs": 8000.0}
 
 
 # Event pairs around a launch also time its dispatch (~10 us here), so a per-launch event
@@ -524,8 +533,11 @@ def main() -> int:
     updates = spec.n_two_site_updates()
     modes = {"fp64": mpdo.MPDO_FP64, "fp32": mpdo.MPDO_FP32}
     run = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
+    # the saturated leg also times the split-BF16 mode (it differs from FP32 only in the products
+    # with theta, which the circuit's factored updates never form)
+    sat_run = run + ["bf16x3"] if args.precision == "both" else run
     if args.saturated_only:
-        print(json.dumps({"saturated": _saturated(max(1, args.saturated_layers), run, args.cpu_saturated)}))
+        print(json.dumps({"saturated": _saturated(max(1, args.saturated_layers), sat_run, args.cpu_saturated)}))
         return 0
     results = {}
     for name in run:
@@ -616,7 +628,7 @@ def main() -> int:
     if args.pulse_steps > 0:
         out["pulse_gate"] = _pulse_gate(args.pulse_steps)
     if args.saturated_layers > 0:
-        out["saturated"] = _saturated(args.saturated_layers, run, args.cpu_saturated)
+        out["saturated"] = _saturated(args.saturated_layers, sat_run, args.cpu_saturated)
     if args.second_order_reps > 0:
         try:
             out["second_order"] = _second_order(spec, args.second_order_reps)

@@ -72,8 +72,15 @@ typedef enum {
 
 typedef enum {
     MPDO_FP64 = 0,          /* every contraction and Gram product in FP64 (MFMA f64)     */
-    MPDO_FP32 = 1           /* contractions and Gram products on FP32 MFMA with FP32
+    MPDO_FP32 = 1,          /* contractions and Gram products on FP32 MFMA with FP32
                                accumulation; eigensolve, PPT and observables in FP64     */
+    MPDO_BF16X3 = 2         /* as MPDO_FP32 (FP32 site data), but the products with the
+                               merged tensor theta (the merge, the gate, the saturated
+                               split's subspace iteration) split each FP32 operand into
+                               two BF16 terms and form three BF16 matrix-core products
+                               with FP32 accumulation: an elementary product carries a
+                               relative error below 2^-15 instead of 2^-24.  Gram
+                               products, projections and the rest stay in FP32.          */
 } mpdo_precision;
 
 typedef struct {
@@ -82,7 +89,7 @@ typedef struct {
     int chi_max;            /* bond-dimension cap, 1..1024                               */
     int precision;          /* mpdo_precision                                            */
     double cutoff_rel;      /* drop Schmidt values below cutoff_rel * largest; 0 -> 1e-14
-                               (MPDO_FP64) or 1e-6 (MPDO_FP32)                        */
+                               (MPDO_FP64) or 1e-6 (MPDO_FP32, MPDO_BF16X3)            */
     int ppt;                /* 1: Purity-Preserving Truncation (Sec. III.D); 0: plain cut */
     int renorm_trace;       /* 1: rescale the cut spectrum so tr(rho) is unchanged       */
     void* hip_stream;       /* hipStream_t to enqueue on; NULL = the null stream         */

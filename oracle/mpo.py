@@ -168,7 +168,9 @@ class MPO:
         """tr(rho^2) = <vec rho | vec rho> for Hermitian rho (vectorised 2-norm)."""
         E = np.ones((1, 1), dtype=np.complex128)
         for a in self.A:
-            E = np.einsum("ab,asc,bsd->cd", E, a.conj(), a)
+            # two pairwise contractions (optimize=True); the plain three-operand loop would
+            # cost chi^4 D2 per site
+            E = np.einsum("ab,asc,bsd->cd", E, a.conj(), a, optimize=True)
         return float(np.real(E[0, 0]))
 
     def to_dense(self) -> np.ndarray:

@@ -5,4 +5,4 @@ The compute path is libmpdo.so (HIP, gfx950), reached through ``mpdo.MPDO``; PyT
 used only for device memory and streams.  ``circuits`` drives the paper-shaped QAOA
 circuits through the library.
 """
-from .mpdo import MPDO, MPDO_FP32, MPDO_FP64, MpdoError, load_library  # noqa: F401
+from .mpdo import MPDO, MPDO_BF16X3, MPDO_FP32, MPDO_FP64, MpdoError, load_library  # noqa: F401

@@ -286,7 +286,8 @@ struct BlockGate {
 struct mpdo_ctx_s {
     mpdo_config cfg{};
     int N = 0, d = 0, D2 = 0, chi = 0;
-    bool fp32 = false;
+    bool fp32 = false;            // site data and products in FP32 (MPDO_FP32, MPDO_BF16X3)
+    bool x3 = false;              // MPDO_BF16X3: the theta products by split-BF16 matrix-core products
     double cutoff = 1e-14;
     hipStream_t st = nullptr;
     std::string err;
@@ -420,9 +421,20 @@ struct Engine {
         o.ws_bytes = s.skw_bytes;
         return o;
     }
+    // the same for products with theta (its merge, the gate, the subspace iteration's
+    // applications): split-BF16 products in MPDO_BF16X3 mode
+    GemmOpts xo() const {
+        GemmOpts o = wso();
+        o.split_bf16 = c.x3;
+        return o;
+    }
     void gemm(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_, int batch = 1, long sA = 0,
               long sB = 0, long sC = 0) {
         HIPCHK(cgemm_ex<T>(st, M, N, K, a, A, B, b, C_, wso(), ps(), batch, sA, sB, sC));
+    }
+    // a product with theta (xo())
+    void gemm_x(int M, int N, int K, cd a, CView<T> A, CView<T> B, cd b, CView<T> C_) {
+        HIPCHK(cgemm_ex<T>(st, M, N, K, a, A, B, b, C_, xo(), ps()));
     }
     // C = A (B diag(f)) for a device array f of N real factors
     void gemm_cols(int M, int N, int K, CView<T> A, CView<T> B, const double* f, CView<T> C_) {
@@ -682,7 +694,7 @@ struct Engine {
         T* Kt = s.bK2;   // orth2's coefficients (unused)
         T* Cq = s.bU2;   // Q^H theta (q x nb, ld nb)
         HIPCHK(fill_random<T>(st, V<T>(X, m, 1), nb, m, seed));
-        gemm(na, m, nb, C1(), Th, V<T>(X, m, 1), C0(), V<T>(Y, m, 1));
+        gemm_x(na, m, nb, C1(), Th, V<T>(X, m, 1), C0(), V<T>(Y, m, 1));
         int cols = m, q = 0;
         double w_old = -1.0;
         for (int it = 0;; ++it) {
@@ -691,11 +703,11 @@ struct Engine {
             if (orth_chol(Y, na, cols, Qt)) {
                 q = cols;
             } else {
-                gemm(na, cols, nb, C1(), Th, V<T>(X, cols, 1), C0(), V<T>(Y, cols, 1));
+                gemm_x(na, cols, nb, C1(), Th, V<T>(X, cols, 1), C0(), V<T>(Y, cols, 1));
                 q = orth2(V<T>(Y, cols, 1), na, cols, Qt, Kt);
             }
             if (q <= 0) return 0;
-            gemm(q, nb, na, C1(), adj(V<T>(Qt, cols, 1)), Th, C0(), V<T>(Cq, nb, 1));
+            gemm_x(q, nb, na, C1(), adj(V<T>(Qt, cols, 1)), Th, C0(), V<T>(Cq, nb, 1));
             ++sub_iters;
             if (m >= rank_bound) break;
             HIPCHK(sumsq<T>(st, V<T>(Cq, nb, 1), q, nb, s.sums, s.sqp, s.sqc));
@@ -709,7 +721,7 @@ struct Engine {
             int z = q;
             if (!orth_chol(Kt, nb, q, X)) z = orth2(adj(V<T>(Cq, nb, 1)), nb, q, X, Kt);
             if (z <= 0) return 0;
-            gemm(na, z, nb, C1(), Th, V<T>(X, q, 1), C0(), V<T>(Y, z, 1));
+            gemm_x(na, z, nb, C1(), Th, V<T>(X, q, 1), C0(), V<T>(Y, z, 1));
             cols = z;
         }
         HIPCHK((geam<T, T>(st, na, q, C1(), V<T>(Qt, cols, 1), C0(), V<T>(Qout, ldq, 1))));
@@ -959,7 +971,7 @@ struct Engine {
             ProfRename th(ps(), PF_GEMM, PF_THETA);
             ProfSink* tps = ps() ? &th : nullptr;
             HIPCHK(cgemm_ex<T>(st, nL, nR, cm, C1(), V<T>(site(i), cm, 1), V<T>(site(i + 1), nR, 1), C0(),
-                               V<T>(s.bT1, nR, 1), wso(), tps));
+                               V<T>(s.bT1, nR, 1), xo(), tps));
             if (bg) {
                 // theta[l][eta eta'][r] as cl blocks of m2 x cr: block (alpha, beta) = rows
                 // l in [lo, lo + ln) of alpha, columns r in [ro, ro + rn) of beta
@@ -968,13 +980,13 @@ struct Engine {
                         if (bg->ln[a] <= 0 || bg->rn[b] <= 0) continue;
                         const long off = 2 * ((long)bg->lo[a] * m2 * cr + (long)bg->ro[b]);
                         HIPCHK(cgemm_ex<T>(st, m2, bg->rn[b], m2, C1(), V<T>((T*)bg->G[4 * a + b], m2, 1),
-                                           V<T>(s.bT1 + off, cr, 1), C0(), V<T>(s.bA + off, cr, 1), wso(), tps,
+                                           V<T>(s.bT1 + off, cr, 1), C0(), V<T>(s.bA + off, cr, 1), xo(), tps,
                                            bg->ln[a], 0, (long)m2 * cr, (long)m2 * cr));
                     }
             } else {
                 load_superop();
                 HIPCHK(cgemm_ex<T>(st, m2, cr, m2, C1(), V<T>((T*)c.SdevT, m2, 1), V<T>(s.bT1, cr, 1), C0(),
-                                   V<T>(s.bA, cr, 1), wso(), tps, cl, 0, (long)m2 * cr, (long)m2 * cr));
+                                   V<T>(s.bA, cr, 1), xo(), tps, cl, 0, (long)m2 * cr, (long)m2 * cr));
             }
             CView<T> Th = V<T>(s.bA, nR, 1);
             HIPCHK(gemv_left<T>(st, trans(Th), nR, nL, s.rvec, s.vtmp));   // theta rvec
@@ -1154,7 +1166,7 @@ bool all_finite(const double* p, size_t n) {
 size_t workspace_for(const mpdo_config& cfg) {
     const int D2 = cfg.d * cfg.d;
     const int nmax = cfg.chi_max * D2;
-    const bool f32 = cfg.precision == MPDO_FP32;
+    const bool f32 = cfg.precision != MPDO_FP64;
     const size_t tsz = f32 ? sizeof(float) : sizeof(double);
     size_t b = 0;
     const size_t site = (size_t)cfg.chi_max * D2 * cfg.chi_max * 2 * tsz + 256;
@@ -1768,7 +1780,8 @@ mpdo_status mpdo_create(const mpdo_config* cfg, mpdo_ctx* out) {
     }
     *out = nullptr;
     if (cfg->n_sites < 2 || cfg->d < 2 || cfg->d > 4 || cfg->chi_max < 1 || cfg->chi_max > 1024 ||
-        (cfg->precision != MPDO_FP64 && cfg->precision != MPDO_FP32) || cfg->cutoff_rel < 0.0 ||
+        (cfg->precision != MPDO_FP64 && cfg->precision != MPDO_FP32 && cfg->precision != MPDO_BF16X3) ||
+        cfg->cutoff_rel < 0.0 ||
         !(cfg->cutoff_rel < 1.0)) {
         g_create_err = "config out of range";
         return MPDO_E_ARG;
@@ -1779,7 +1792,8 @@ mpdo_status mpdo_create(const mpdo_config* cfg, mpdo_ctx* out) {
     c->d = cfg->d;
     c->D2 = cfg->d * cfg->d;
     c->chi = cfg->chi_max;
-    c->fp32 = cfg->precision == MPDO_FP32;
+    c->fp32 = cfg->precision != MPDO_FP64;
+    c->x3 = cfg->precision == MPDO_BF16X3;
     // default relative cutoff: the rounding floor of the working precision's products
     c->cutoff = cfg->cutoff_rel > 0.0 ? cfg->cutoff_rel : (c->fp32 ? 1e-6 : 1e-14);
     c->st = (hipStream_t)cfg->hip_stream;

@@ -28,6 +28,11 @@ struct GemmOpts {
     // order in which workgroups run.
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // FP32 products only: each operand split into two BF16 terms and the product formed from
+    // three BF16 matrix-core products with FP32 accumulation (relative error of an elementary
+    // product below 2^-15 instead of 2^-24; the FP32 accumulation is unchanged).  Ignored for
+    // FP64 and with operand transforms.
+    bool split_bf16 = false;
 };
 
 // cgemm with operand transforms.  C must not alias A or B.

@@ -1,4 +1,4 @@
-// Complex GEMM on CDNA4 matrix cores (gfx950), FP64 and FP32.
+// Complex GEMM on CDNA4 matrix cores (gfx950), FP64, FP32 and FP32 data by split-BF16 products.
 //
 //   C = alpha * op(A) * op(B) + beta * C
 //
@@ -270,6 +270,207 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<T> g) {
             }
 }
 
+// ------------------------------------------------------------ split-BF16 products of FP32 data
+// Each FP32 operand x is written as hi + lo with hi = bf16(x) and lo = bf16(x - hi) (x - hi is
+// exact in FP32; both roundings to nearest even, by the packed hardware conversion), so
+// x - hi - lo is below 2^-18 |x|.  A real product a b is then a_hi b_hi + a_hi b_lo + a_lo b_hi
+// (the dropped a_lo b_lo is below 2^-18 |a b|), three BF16 matrix-core products with FP32
+// accumulation: 16x16x32 MFMAs, one k-step of 32 per tile.  The complex product takes the
+// four real products of the FP32 kernel, twelve MFMAs per 16x16 output tile and k-step (the
+// negated imaginary part of A by a sign-bit flip, which is exact).
+//
+// A k-step costs a wave 12 x 16 cycles of matrix core per 16x16 tile, a sixth of the FP32
+// kernel's, so the operand traffic and the conversion must be spread over more output: the
+// workgroup tile is 128 x 128 (each wave 64 x 64, 4 x 4 MFMA tiles, accumulators in AGPRs),
+// i.e. 3072 matrix-core cycles per SIMD and k-step against 32 KB of operands per workgroup.
+// Every thread loads 16 complex values of A and 16 of B per k-step at offsets fixed for the
+// whole product (one 64-bit base per operand and a constant stride between its 16 values), so
+// the next k-step's loads cost one add.  LDS holds hi and lo planes of the real and imaginary
+// parts, k contiguous (rows of 40 BF16, 16-byte aligned), so a lane reads the eight k values
+// of its row (column) with one 16-byte load; the 16 lanes of a row group then touch 64
+// distinct banks.  The same lane-to-k assignment is used for A and B, so the sum over k pairs
+// matching terms whatever order the instruction adds them.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef unsigned short v8us __attribute__((ext_vector_type(8)));
+constexpr int XK = 32;    // k-step of the split-BF16 kernel
+constexpr int XPAD = 8;   // LDS row padding in BF16 elements (rows stay 16-byte aligned)
+constexpr int XT = 128;   // workgroup tile (rows of A, columns of B)
+constexpr int XL = (XT * XK) / 256;   // complex values of each operand per thread and k-step
+
+// (hi, lo) of x packed as two BF16 (hi in the low half)
+__device__ __forceinline__ unsigned split_bf16(float x) {
+    const __bf16 h = (__bf16)x;
+    const v2bf p = {h, (__bf16)(x - (float)h)};
+    return __builtin_bit_cast(unsigned, p);
+}
+
+__device__ __forceinline__ v4f mfma_bf16(v8us a, v8us b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0,
+                                                   0);
+}
+
+// Per-thread load pattern of one operand tile (XT rows (A) or columns (B) by XK k): value j
+// (0 <= j < XL) sits at row r0 + j dr and k k0 + j dk of the tile; `fast` says whether k is
+// the contiguous dimension of the view (then 32 consecutive threads read 32 consecutive k of
+// a row), else rows are (then 128 consecutive threads read 128 consecutive rows).
+struct XPat {
+    int r0, dr, k0, dk;
+};
+__device__ __forceinline__ XPat xpat(int tid, bool kfast) {
+    return kfast ? XPat{tid / XK, 256 / XK, tid % XK, 0} : XPat{tid % XT, 0, tid / XT, 256 / XT};
+}
+
+__global__ __launch_bounds__(256) void cgemm_x3_kernel(GemmArgs<float> g) {
+    constexpr int WM = 4, WQ = 16 * WM;
+    // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo; [row of A or column of B][k]
+    __shared__ __attribute__((aligned(16))) unsigned short sA[4][XT][XK + XPAD];
+    __shared__ __attribute__((aligned(16))) unsigned short sB[4][XT][XK + XPAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1;
+    const int wc = wave & 1;
+    // the XCD-aware tile order of cgemm_kernel
+    const unsigned nx = gridDim.x, ny = gridDim.y;
+    const unsigned nw = nx * ny * gridDim.z;
+    const unsigned w = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const unsigned per = nw / 8, rem = nw % 8, xcd = w % 8;
+    const unsigned t = xcd * per + (xcd < rem ? xcd : rem) + w / 8;
+    const int m0 = (int)((t / nx) % ny) * XT;
+    const int n0 = (int)(t % nx) * XT;
+    const int bz = (int)(t / (nx * ny));
+    const int b = bz / g.ksplit;
+    const int kc = bz - b * g.ksplit;
+    const int kbeg = kc * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+
+    // A value (m, k) at A.p + 2 (m rs + k cs); B value (k, n) at B.p + 2 (k rs + n cs)
+    const XPat pa = xpat(tid, g.A.cs == 1), pb = xpat(tid, g.B.rs == 1);
+    const float* Ab = g.A.p + 2 * ((long)b * g.sA + (long)(m0 + pa.r0) * g.A.rs + (long)pa.k0 * g.A.cs);
+    const long Aj = 2 * ((long)pa.dr * g.A.rs + (long)pa.dk * g.A.cs), Ak = 2 * (long)g.A.cs;
+    const float* Bb = g.B.p + 2 * ((long)b * g.sB + (long)(n0 + pb.r0) * g.B.cs + (long)pb.k0 * g.B.rs);
+    const long Bj = 2 * ((long)pb.dr * g.B.cs + (long)pb.dk * g.B.rs), Bk = 2 * (long)g.B.rs;
+    const float sa = g.A.conj ? -1.0f : 1.0f, sb = g.B.conj ? -1.0f : 1.0f;
+    float* Cp = g.C.p + 2 * (long)b * g.sC;
+
+    v4f cr[WM][WM], ci[WM][WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j) {
+            cr[i][j] = (v4f){0, 0, 0, 0};
+            ci[i][j] = (v4f){0, 0, 0, 0};
+        }
+
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+
+    float2 va[XL], vb[XL];
+    auto fetch = [&](int k0) {
+        const float* ap = Ab + (long)k0 * Ak;
+        const float* bp = Bb + (long)k0 * Bk;
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            va[j] = make_float2(0.0f, 0.0f);
+            if (m0 + pa.r0 + j * pa.dr < g.M && k0 + pa.k0 + j * pa.dk < kend)
+                va[j] = *(const float2*)(ap + j * Aj);
+        }
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            vb[j] = make_float2(0.0f, 0.0f);
+            if (n0 + pb.r0 + j * pb.dr < g.N && k0 + pb.k0 + j * pb.dk < kend)
+                vb[j] = *(const float2*)(bp + j * Bj);
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += XK) {
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            const int r = pa.r0 + j * pa.dr, k = pa.k0 + j * pa.dk;
+            const unsigned re = split_bf16(va[j].x), im = split_bf16(sa * va[j].y);
+            sA[0][r][k] = (unsigned short)re;
+            sA[1][r][k] = (unsigned short)(re >> 16);
+            sA[2][r][k] = (unsigned short)im;
+            sA[3][r][k] = (unsigned short)(im >> 16);
+        }
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            const int r = pb.r0 + j * pb.dr, k = pb.k0 + j * pb.dk;
+            const unsigned re = split_bf16(vb[j].x), im = split_bf16(sb * vb[j].y);
+            sB[0][r][k] = (unsigned short)re;
+            sB[1][r][k] = (unsigned short)(re >> 16);
+            sB[2][r][k] = (unsigned short)im;
+            sB[3][r][k] = (unsigned short)(im >> 16);
+        }
+        __syncthreads();
+        if (k0 + XK < kend) fetch(k0 + XK);
+        v8us bb[WM][4];
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bb[j][q] = *(const v8us*)&sB[q][wc * WQ + j * 16 + li][8 * lk];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            v8us a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = *(const v8us*)&sA[q][wr * WQ + i * 16 + li][8 * lk];
+            const v8us nih = a[2] ^ (unsigned short)0x8000, nil = a[3] ^ (unsigned short)0x8000;
+#pragma unroll
+            for (int j = 0; j < WM; ++j) {
+                // the small terms first
+                cr[i][j] = mfma_bf16(a[1], bb[j][0], cr[i][j]);
+                cr[i][j] = mfma_bf16(a[0], bb[j][1], cr[i][j]);
+                cr[i][j] = mfma_bf16(nil, bb[j][2], cr[i][j]);
+                cr[i][j] = mfma_bf16(nih, bb[j][3], cr[i][j]);
+                cr[i][j] = mfma_bf16(a[0], bb[j][0], cr[i][j]);
+                cr[i][j] = mfma_bf16(nih, bb[j][2], cr[i][j]);
+                ci[i][j] = mfma_bf16(a[1], bb[j][2], ci[i][j]);
+                ci[i][j] = mfma_bf16(a[0], bb[j][3], ci[i][j]);
+                ci[i][j] = mfma_bf16(a[3], bb[j][0], ci[i][j]);
+                ci[i][j] = mfma_bf16(a[2], bb[j][1], ci[i][j]);
+                ci[i][j] = mfma_bf16(a[0], bb[j][2], ci[i][j]);
+                ci[i][j] = mfma_bf16(a[2], bb[j][0], ci[i][j]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // epilogue as in cgemm_kernel (FP32 accumulator layout: rows 4 (lane / 16) + r)
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wr * WQ + i * 16 + 4 * lk + r;
+                const int gn = n0 + wc * WQ + j * 16 + li;
+                if (gm >= g.M || gn >= g.N) continue;
+                const double xr = (double)cr[i][j][r], xi = (double)ci[i][j][r];
+                const double vr = g.ar * xr - g.ai * xi;
+                const double vi = g.ar * xi + g.ai * xr;
+                if (g.part) {
+                    float* pp = g.part + 2 * (((long)kc * g.batch + b) * g.M * (long)g.N + (long)gm * g.N + gn);
+                    pp[0] = (float)vr;
+                    pp[1] = (float)vi;
+                } else {
+                    const long off = 2 * ((long)gm * g.C.rs + (long)gn * g.C.cs);
+                    double or_ = 0.0, oi = 0.0;
+                    if (g.br != 0.0 || g.bi != 0.0) {
+                        const double cr0 = (double)Cp[off];
+                        const double ci0 = g.C.conj ? -(double)Cp[off + 1] : (double)Cp[off + 1];
+                        or_ = g.br * cr0 - g.bi * ci0;
+                        oi = g.br * ci0 + g.bi * cr0;
+                    }
+                    const double wr_ = vr + or_;
+                    const double wi_ = vi + oi;
+                    Cp[off] = (float)wr_;
+                    Cp[off + 1] = (float)(g.C.conj ? -wi_ : wi_);
+                }
+            }
+}
+
 // C = beta C + sum over the ks k-chunks of the partial products, added in chunk order (FP64
 // sums), one thread per output element of every batch.
 template <typename T>
@@ -324,11 +525,13 @@ int chunk_of(int K, int ks) { return (((K + ks - 1) / ks + BK - 1) / BK) * BK; }
 // and the memory-side cache, counted at a quarter weight (it mostly overlaps the matrix work;
 // it decides between plans of equal matrix time).  A split adds its partial tiles, written and
 // read back by the reduce launch (~4 TB/s), and ~5 us of fixed cost; every launch ~2 us.
-double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p) {
+// The split-BF16 kernel (x3) spends 12 MFMAs of 16 cycles per 16x16 tile and k-step of 32.
+// Launch plan: block tile (32 wm)^2.
+double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p, bool x3 = false) {
     const double tsz = fp64 ? 8.0 : 4.0;
     const double W = (double)tiles_of(M, N, batch, p.wm) * p.ks;
     const int chunk = p.ks > 1 ? chunk_of(K, p.ks) : K;
-    const double cyc = (fp64 ? 64.0 : 32.0) * p.wm * p.wm * chunk;
+    const double cyc = (x3 ? 6.0 : fp64 ? 64.0 : 32.0) * p.wm * p.wm * chunk;
     const double mfma_us = std::ceil(W / 256.0) * cyc / 2400.0;
     const double bytes = W * chunk * 64.0 * p.wm * 2.0 * tsz;
     const double part_us = p.ks > 1 ? 2.0 * W * 1024.0 * p.wm * p.wm * 2.0 * tsz / 4e6 : 0.0;
@@ -337,16 +540,18 @@ double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p) {
 
 // wm_max = 1 restricts the plan to 32 x 32 tiles (the kernel with operand transforms needs
 // more registers than two waves per SIMD allow at 64 x 64)
-Plan plan_of(int M, int N, int K, int batch, bool fp64, int wm_max = 2, int ks_max = 64) {
+// x3: the split-BF16 kernel (128 x 128 tile, wm = 4)
+Plan plan_of(int M, int N, int K, int batch, bool fp64, int wm_max = 2, int ks_max = 64, bool x3 = false) {
+    if (x3) wm_max = 4;   // the split-BF16 kernel has only the 128 x 128 tile
     Plan best{wm_max, 1};
-    double best_t = plan_cost(M, N, K, batch, fp64, best);
-    for (int wm = wm_max; wm >= 1; --wm)
+    double best_t = plan_cost(M, N, K, batch, fp64, best, x3);
+    for (int wm = wm_max; wm >= (x3 ? 4 : 1); --wm)
         for (int ks = 1; ks <= ks_max; ks *= 2) {
             if (ks > 1 && K < 2 * BK) break;
             const int k_eff = ks > 1 ? (K + chunk_of(K, ks) - 1) / chunk_of(K, ks) : 1;
             if (ks > 1 && k_eff < 2) continue;
             const Plan p{wm, k_eff};
-            const double t = plan_cost(M, N, K, batch, fp64, p);
+            const double t = plan_cost(M, N, K, batch, fp64, p, x3);
             if (t < 0.97 * best_t) {
                 best = p;
                 best_t = t;
@@ -396,10 +601,16 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
         }
     }
     const int bt = 32 * plan.wm;
-    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, batch * g.ksplit);
+    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, batch * g.ksplit);   // plan.wm = 4: the split-BF16 tile
     if (prof) prof->begin(s, PF_GEMM);
     const bool tf = g.bshift || g.bcol;
-    if (plan.wm == 2) {
+    bool x3 = false;
+    if constexpr (std::is_same<T, float>::value) {
+        x3 = opt.split_bf16 && !tf && plan.wm == 4;
+        if (x3) hipLaunchKernelGGL(cgemm_x3_kernel, grid, dim3(256), 0, s, g);
+    }
+    if (x3) {
+    } else if (plan.wm == 2) {
         if (tf)
             hipLaunchKernelGGL((cgemm_kernel<T, 2, 1>), grid, dim3(256), 0, s, g);
         else
@@ -517,8 +728,9 @@ hipError_t cgemm_ex(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CV
     // the largest k split whose partials fit the workspace
     int ks_max = 1;
     while (ks_max < 64 && opt.ws && split_bytes<T>(M, N, batch, 2 * ks_max) <= opt.ws_bytes) ks_max *= 2;
-    Plan plan = plan_of(M, N, k, batch, std::is_same<T, double>::value, plain ? 2 : 1, ks_max);
-    if (plain && autotune_on() && beta.re == 0.0 && beta.im == 0.0 && K >= 128)
+    const bool x3 = std::is_same<T, float>::value && opt.split_bf16 && plain;
+    Plan plan = plan_of(M, N, k, batch, std::is_same<T, double>::value, plain ? 2 : 1, ks_max, x3);
+    if (plain && !x3 && autotune_on() && beta.re == 0.0 && beta.im == 0.0 && K >= 128)
         plan = tune_plan<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, opt, ks_max);
     return cgemm_launch<T>(s, M, N, k, alpha, A, B, beta, C, batch, sA, sB, sC, plan, prof, opt);
 }

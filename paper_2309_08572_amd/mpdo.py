@@ -16,6 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpdo.so
 
 MPDO_FP64 = 0
 MPDO_FP32 = 1
+MPDO_BF16X3 = 2
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_NUMERIC",
           6: "E_UNSUPPORTED"}
