@@ -498,7 +498,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n", type=int, default=100)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "both"], default="both")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3", "both"], default="both")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-circuits", type=int, default=32,
@@ -531,7 +531,7 @@ def main() -> int:
 
     spec = config_m3(args.seed, n=args.n)
     updates = spec.n_two_site_updates()
-    modes = {"fp64": mpdo.MPDO_FP64, "fp32": mpdo.MPDO_FP32}
+    modes = {"fp64": mpdo.MPDO_FP64, "fp32": mpdo.MPDO_FP32, "bf16x3": mpdo.MPDO_BF16X3}
     run = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
     # the saturated leg also times the split-BF16 mode (it differs from FP32 only in the products
     # with theta, which the circuit's factored updates never form)

@@ -334,6 +334,21 @@ mpdo_status mpdo_profile_read(mpdo_ctx ctx, double* out, int n_families);
 /* Block until all work of the context has finished. */
 mpdo_status mpdo_synchronize(mpdo_ctx ctx);
 
+/* C = alpha op(A) op(B) + beta C on the library's matrix-core product kernels: every
+ * contraction of the update (the merge and gate of Sec. III.A, Fig. 2(c); the Gram products
+ * and rebuilds that replace the SVD) runs through them, and tests check them element by
+ * element here.  precision: a value of mpdo_precision; FP32 and BF16X3 round the operands to
+ * FP32 first.  A, B, C: host complex128 (interleaved re, im), row-major.  op_a = 0: A is M x K
+ * and op(A) = A; 1: A is K x M and op(A) = A^T; 2: A is K x M and op(A) = A^H.  op_b the same
+ * with B K x N (op 0) or N x K (1, 2).  C is M x N, read when beta != 0 and overwritten.
+ * alpha, beta: complex scalars (2 doubles).  split_k = 1 lends the product a workspace for
+ * k-split partial sums (added in a fixed order), 0 runs k unsplit.  Synchronous on the null
+ * stream of the current device; allocates and frees its device copies.  E_ARG for a negative
+ * size, a null pointer, an unknown op or precision, or an operand above 2^28 elements;
+ * E_NOMEM / E_DEVICE for a failed allocation or HIP call (message: mpdo_last_error(NULL)). */
+mpdo_status mpdo_cgemm(int precision, int M, int N, int K, const double* alpha, const double* A, int op_a,
+                       const double* B, int op_b, const double* beta, double* C, int split_k);
+
 /* Message of the last failed call on ctx (or of mpdo_create when ctx is NULL). */
 const char* mpdo_last_error(mpdo_ctx ctx);
 

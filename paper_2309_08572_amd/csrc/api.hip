@@ -1770,6 +1770,48 @@ static void expect2_impl(mpdo_ctx c, int n_terms, const int* first, const int* l
     }
 }
 
+// The product kernels on host operands (mpdo_cgemm): device copies in T, one cgemm_ex on the
+// null stream, the result back in complex128.
+template <typename T>
+void run_cgemm(bool x3, int M, int N, int K, const double* alpha, const double* A, int op_a, const double* B,
+               int op_b, const double* beta, double* C, int split_k) {
+    struct Buf {
+        void* p = nullptr;
+        ~Buf() {
+            if (p) (void)hipFree(p);
+        }
+    } dA, dB, dC, ws;
+    auto up = [](Buf& d, const double* h, long n) {
+        std::vector<T> t((size_t)2 * n);
+        for (long i = 0; i < 2 * n; ++i) t[i] = (T)h[i];
+        if (hipMalloc(&d.p, sizeof(T) * (size_t)std::max(2 * n, 2L)) != hipSuccess)
+            throw Fail{MPDO_E_NOMEM, "device allocation failed"};
+        if (n > 0 && hipMemcpy(d.p, t.data(), sizeof(T) * 2 * n, hipMemcpyHostToDevice) != hipSuccess)
+            throw Fail{MPDO_E_DEVICE, "copy to the device failed"};
+    };
+    up(dA, A, (long)M * K);
+    up(dB, B, (long)K * N);
+    up(dC, C, (long)M * N);
+    // op 0: stored as op(X) row-major; 1: stored transposed; 2: stored transposed, conjugated
+    const CView<T> va = op_a == 0 ? view<T>((T*)dA.p, K, 1) : view<T>((T*)dA.p, 1, M, op_a == 2);
+    const CView<T> vb = op_b == 0 ? view<T>((T*)dB.p, N, 1) : view<T>((T*)dB.p, 1, K, op_b == 2);
+    GemmOpts o;
+    o.split_bf16 = x3;
+    if (split_k) {
+        o.ws_bytes = std::min((size_t)64 * M * N * 2 * sizeof(T), (size_t)256 << 20);
+        if (hipMalloc(&ws.p, o.ws_bytes) != hipSuccess) throw Fail{MPDO_E_NOMEM, "device allocation failed"};
+        o.ws = ws.p;
+    }
+    if (cgemm_ex<T>(0, M, N, K, cd{alpha[0], alpha[1]}, va, vb, cd{beta[0], beta[1]}, view<T>((T*)dC.p, N, 1), o) !=
+            hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        throw Fail{MPDO_E_DEVICE, "product kernel failed"};
+    std::vector<T> t((size_t)2 * M * N);
+    if (M * (long)N > 0 && hipMemcpy(t.data(), dC.p, sizeof(T) * t.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        throw Fail{MPDO_E_DEVICE, "copy to the host failed"};
+    for (size_t i = 0; i < t.size(); ++i) C[i] = (double)t[i];
+}
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -2332,6 +2374,25 @@ mpdo_status mpdo_profile_read(mpdo_ctx c, double* out, int n_families) {
     const int nf = std::min(n_families, (int)PF_COUNT);
     for (int f = 0; f < nf; ++f)
         for (int q = 0; q < 4; ++q) out[4 * f + q] = c->prof_acc[4 * f + q];
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_cgemm(int precision, int M, int N, int K, const double* alpha, const double* A, int op_a,
+                       const double* B, int op_b, const double* beta, double* C, int split_k) {
+    if (M < 0 || N < 0 || K < 0 || !alpha || !beta || (M * (long)N > 0 && !C) || (M * (long)K > 0 && !A) ||
+        (K * (long)N > 0 && !B) || op_a < 0 || op_a > 2 || op_b < 0 || op_b > 2 ||
+        (precision != MPDO_FP64 && precision != MPDO_FP32 && precision != MPDO_BF16X3) ||
+        (long)M * K > (1L << 28) || (long)K * N > (1L << 28) || (long)M * N > (1L << 28)) {
+        g_create_err = "bad product arguments";
+        return MPDO_E_ARG;
+    }
+    try {
+        if (precision == MPDO_FP64) run_cgemm<double>(false, M, N, K, alpha, A, op_a, B, op_b, beta, C, split_k);
+        else run_cgemm<float>(precision == MPDO_BF16X3, M, N, K, alpha, A, op_a, B, op_b, beta, C, split_k);
+    } catch (const Fail& f) {
+        g_create_err = f.msg;
+        return f.st;
+    }
     return MPDO_OK;
 }
 

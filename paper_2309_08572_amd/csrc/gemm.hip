@@ -20,6 +20,7 @@
 // workgroup needs 64 WM^2 cycles per unit of k on its compute unit: the small products of an
 // update (outputs of a few 64 x 64 tiles) are bound by how many compute units they reach.
 // The launcher picks the tile size and the k split from that cost (plan_of).
+#include <stdio.h>
 #include <stdlib.h>
 
 #include <algorithm>
@@ -471,6 +472,146 @@ __global__ __launch_bounds__(256) void cgemm_x3_kernel(GemmArgs<float> g) {
             }
 }
 
+// FP32 products of large outputs: the 128 x 128 workgroup tile and the load pattern of the
+// split-BF16 kernel, with the FP32 16x16x4 MFMA (four real products per complex k-step).  A
+// k-tile of 32 then costs each SIMD 16 tiles x 8 steps x 4 MFMAs x 32 cycles of matrix core,
+// against 32 KB of operands per workgroup and one LDS staging, which the 64 x 64 kernel pays
+// for a quarter of the work.  LDS planes [row of A or column of B][k] with rows of 34 floats:
+// the 32 lanes that a 16x16x4 read serves at once (16 rows at 2 k) land on 32 distinct banks.
+constexpr int FPAD = 2;
+__global__ __launch_bounds__(256) void cgemm_f32_big_kernel(GemmArgs<float> g) {
+    constexpr int WM = 4, WQ = 16 * WM;
+    __shared__ float sAr[XT][XK + FPAD], sAi[XT][XK + FPAD];
+    __shared__ float sBr[XT][XK + FPAD], sBi[XT][XK + FPAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1;
+    const int wc = wave & 1;
+    const unsigned nx = gridDim.x, ny = gridDim.y;
+    const unsigned nw = nx * ny * gridDim.z;
+    const unsigned w = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const unsigned per = nw / 8, rem = nw % 8, xcd = w % 8;
+    const unsigned t = xcd * per + (xcd < rem ? xcd : rem) + w / 8;
+    const int m0 = (int)((t / nx) % ny) * XT;
+    const int n0 = (int)(t % nx) * XT;
+    const int bz = (int)(t / (nx * ny));
+    const int b = bz / g.ksplit;
+    const int kc = bz - b * g.ksplit;
+    const int kbeg = kc * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+
+    const XPat pa = xpat(tid, g.A.cs == 1), pb = xpat(tid, g.B.rs == 1);
+    const float* Ab = g.A.p + 2 * ((long)b * g.sA + (long)(m0 + pa.r0) * g.A.rs + (long)pa.k0 * g.A.cs);
+    const long Aj = 2 * ((long)pa.dr * g.A.rs + (long)pa.dk * g.A.cs), Ak = 2 * (long)g.A.cs;
+    const float* Bb = g.B.p + 2 * ((long)b * g.sB + (long)(n0 + pb.r0) * g.B.cs + (long)pb.k0 * g.B.rs);
+    const long Bj = 2 * ((long)pb.dr * g.B.cs + (long)pb.dk * g.B.rs), Bk = 2 * (long)g.B.rs;
+    const float sa = g.A.conj ? -1.0f : 1.0f, sb = g.B.conj ? -1.0f : 1.0f;
+    float* Cp = g.C.p + 2 * (long)b * g.sC;
+
+    v4f cr[WM][WM], ci[WM][WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j) {
+            cr[i][j] = (v4f){0, 0, 0, 0};
+            ci[i][j] = (v4f){0, 0, 0, 0};
+        }
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+
+    float2 va[XL], vb[XL];
+    auto fetch = [&](int k0) {
+        const float* ap = Ab + (long)k0 * Ak;
+        const float* bp = Bb + (long)k0 * Bk;
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            va[j] = make_float2(0.0f, 0.0f);
+            if (m0 + pa.r0 + j * pa.dr < g.M && k0 + pa.k0 + j * pa.dk < kend)
+                va[j] = *(const float2*)(ap + j * Aj);
+        }
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            vb[j] = make_float2(0.0f, 0.0f);
+            if (n0 + pb.r0 + j * pb.dr < g.N && k0 + pb.k0 + j * pb.dk < kend)
+                vb[j] = *(const float2*)(bp + j * Bj);
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += XK) {
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            const int r = pa.r0 + j * pa.dr, k = pa.k0 + j * pa.dk;
+            sAr[r][k] = va[j].x;
+            sAi[r][k] = sa * va[j].y;
+        }
+#pragma unroll
+        for (int j = 0; j < XL; ++j) {
+            const int r = pb.r0 + j * pb.dr, k = pb.k0 + j * pb.dk;
+            sBr[r][k] = vb[j].x;
+            sBi[r][k] = sb * vb[j].y;
+        }
+        __syncthreads();
+        if (k0 + XK < kend) fetch(k0 + XK);
+#pragma unroll 2
+        for (int kk = 0; kk < XK; kk += 4) {
+            float br[WM], bi[WM];
+#pragma unroll
+            for (int j = 0; j < WM; ++j) {
+                br[j] = sBr[wc * WQ + j * 16 + li][kk + lk];
+                bi[j] = sBi[wc * WQ + j * 16 + li][kk + lk];
+            }
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                const float ar = sAr[wr * WQ + i * 16 + li][kk + lk];
+                const float ai = sAi[wr * WQ + i * 16 + li][kk + lk];
+                const float nai = -ai;
+#pragma unroll
+                for (int j = 0; j < WM; ++j) {
+                    cr[i][j] = mfma16(ar, br[j], cr[i][j]);
+                    cr[i][j] = mfma16(nai, bi[j], cr[i][j]);
+                    ci[i][j] = mfma16(ar, bi[j], ci[i][j]);
+                    ci[i][j] = mfma16(ai, br[j], ci[i][j]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wr * WQ + i * 16 + 4 * lk + r;
+                const int gn = n0 + wc * WQ + j * 16 + li;
+                if (gm >= g.M || gn >= g.N) continue;
+                const double xr = (double)cr[i][j][r], xi = (double)ci[i][j][r];
+                const double vr = g.ar * xr - g.ai * xi;
+                const double vi = g.ar * xi + g.ai * xr;
+                if (g.part) {
+                    float* pp = g.part + 2 * (((long)kc * g.batch + b) * g.M * (long)g.N + (long)gm * g.N + gn);
+                    pp[0] = (float)vr;
+                    pp[1] = (float)vi;
+                } else {
+                    const long off = 2 * ((long)gm * g.C.rs + (long)gn * g.C.cs);
+                    double or_ = 0.0, oi = 0.0;
+                    if (g.br != 0.0 || g.bi != 0.0) {
+                        const double cr0 = (double)Cp[off];
+                        const double ci0 = g.C.conj ? -(double)Cp[off + 1] : (double)Cp[off + 1];
+                        or_ = g.br * cr0 - g.bi * ci0;
+                        oi = g.br * ci0 + g.bi * cr0;
+                    }
+                    const double wr_ = vr + or_;
+                    const double wi_ = vi + oi;
+                    Cp[off] = (float)wr_;
+                    Cp[off + 1] = (float)(g.C.conj ? -wi_ : wi_);
+                }
+            }
+}
+
 // C = beta C + sum over the ks k-chunks of the partial products, added in chunk order (FP64
 // sums), one thread per output element of every batch.
 template <typename T>
@@ -543,9 +684,10 @@ double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p, bool x3 = fa
 // x3: the split-BF16 kernel (128 x 128 tile, wm = 4)
 Plan plan_of(int M, int N, int K, int batch, bool fp64, int wm_max = 2, int ks_max = 64, bool x3 = false) {
     if (x3) wm_max = 4;   // the split-BF16 kernel has only the 128 x 128 tile
+    else if (!fp64 && wm_max == 2) wm_max = 4;   // plain FP32 products may take it too
     Plan best{wm_max, 1};
     double best_t = plan_cost(M, N, K, batch, fp64, best, x3);
-    for (int wm = wm_max; wm >= (x3 ? 4 : 1); --wm)
+    for (int wm = wm_max; wm >= (x3 ? 4 : 1); wm /= 2)   // tiles of 128, 64, 32
         for (int ks = 1; ks <= ks_max; ks *= 2) {
             if (ks > 1 && K < 2 * BK) break;
             const int k_eff = ks > 1 ? (K + chunk_of(K, ks) - 1) / chunk_of(K, ks) : 1;
@@ -601,15 +743,20 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
         }
     }
     const int bt = 32 * plan.wm;
-    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, batch * g.ksplit);   // plan.wm = 4: the split-BF16 tile
+    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, batch * g.ksplit);   // plan.wm = 4: the 128 x 128 tile
+    if (getenv("MPDO_DEBUG_GEMM"))
+        fprintf(stderr, "[mpdo gemm] %s M %d N %d K %d batch %d tile %d ksplit %d chunk %d%s\n",
+                sizeof(T) == 8 ? "f64" : (opt.split_bf16 ? "bf16x3" : "f32"), M, N, K, batch, bt, g.ksplit, g.kchunk,
+                g.bshift || g.bcol ? " transforms" : "");
     if (prof) prof->begin(s, PF_GEMM);
     const bool tf = g.bshift || g.bcol;
-    bool x3 = false;
+    bool big = false;   // the 128 x 128 kernels (plan.wm = 4: FP32, plain operands)
     if constexpr (std::is_same<T, float>::value) {
-        x3 = opt.split_bf16 && !tf && plan.wm == 4;
-        if (x3) hipLaunchKernelGGL(cgemm_x3_kernel, grid, dim3(256), 0, s, g);
+        big = !tf && plan.wm == 4;
+        if (big && opt.split_bf16) hipLaunchKernelGGL(cgemm_x3_kernel, grid, dim3(256), 0, s, g);
+        else if (big) hipLaunchKernelGGL(cgemm_f32_big_kernel, grid, dim3(256), 0, s, g);
     }
-    if (x3) {
+    if (big) {
     } else if (plan.wm == 2) {
         if (tf)
             hipLaunchKernelGGL((cgemm_kernel<T, 2, 1>), grid, dim3(256), 0, s, g);

@@ -27,6 +27,7 @@ EXPORTS = (
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_expect2", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_set_state", "mpdo_canonical_centre", "mpdo_move_centre", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
     "mpdo_profile_enable", "mpdo_profile_enable_mask", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
+    "mpdo_cgemm",
 )
 
 PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other",
@@ -118,6 +119,7 @@ def load_library() -> C.CDLL:
     lib.mpdo_batch_workspace_bytes.restype = C.c_size_t
     lib.mpdo_run_batch.argtypes = [C.POINTER(Circuit), C.c_int, C.c_int, C.c_void_p, C.c_size_t]
     lib.mpdo_profile_read.argtypes = [ctx, dp, C.c_int]
+    lib.mpdo_cgemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_int, dp, dp, C.c_int]
     for name in EXPORTS:
         if name not in ("mpdo_workspace_bytes", "mpdo_last_error", "mpdo_version",
                         "mpdo_batch_workspace_bytes"):
@@ -307,6 +309,29 @@ class MPDO:
 
     def synchronize(self):
         self._check(self.lib.mpdo_synchronize(self.ctx))
+
+
+def cgemm(precision: int, A, B, op_a: int = 0, op_b: int = 0, alpha=1.0, beta=0.0, C0=None,
+          split_k: bool = False, device: int = 0) -> np.ndarray:
+    """alpha op(A) op(B) + beta C0 through the library's matrix-core product kernels
+    (mpdo_cgemm); op 0: as stored, 1: transpose, 2: conjugate transpose."""
+    import torch
+    lib = load_library()
+    torch.cuda.set_device(device)
+    A, B = _cplx(A), _cplx(B)
+    M = A.shape[0] if op_a == 0 else A.shape[1]
+    K = A.shape[1] if op_a == 0 else A.shape[0]
+    N = B.shape[1] if op_b == 0 else B.shape[0]
+    if (B.shape[0] if op_b == 0 else B.shape[1]) != K:
+        raise ValueError("inner dimensions differ")
+    Cm = np.zeros((M, N), dtype=np.complex128) if C0 is None else _cplx(C0).copy()
+    al = np.array([complex(alpha).real, complex(alpha).imag])
+    be = np.array([complex(beta).real, complex(beta).imag])
+    st = lib.mpdo_cgemm(int(precision), M, N, K, _dptr(al), _dptr(A), int(op_a), _dptr(B), int(op_b), _dptr(be),
+                        _dptr(Cm), int(split_k))
+    if st != 0:
+        raise MpdoError(st, lib.mpdo_last_error(None).decode())
+    return Cm
 
 
 def run_batch(descs, n_workers: int = 8, device: int = 0):
