@@ -49,3 +49,53 @@ def test_saturated_chain_keeps_the_ppt_invariants():
     assert np.all(np.isfinite(g["populations"]))
     assert abs(np.sum(g["populations"], axis=1) - 1.0).max() <= 1e-10   # normalised by the trace
     m.close()
+
+
+def test_saturating_chain_matches_stored_oracle():
+    """N=12, d=4, p=6, chi_max=512 (the benchmark's gate set; the centre bonds reach 512 and the
+    larger updates form theta of up to 8192 x 8192 and split it by subspace iteration) against
+    the CPU oracle's LAPACK-SVD run of the same circuit, stored by
+    tests/golden/make_m3_oracle.py sat: every one of the 66 updates' cut record and the final
+    observables.
+
+    Bars.  The oracle's cuts discard at most 1.2e-13 of the weight per update and the gaps at
+    the chi = 512 cuts are ~1e-12 of the largest Schmidt value, so the two truncated states can
+    differ only in directions of that weight; the subspace iteration stops when the captured
+    weight changes by less than 1e-10 of itself.  Trace and xi before each cut: 1e-9 relative;
+    kept counts: equal where the chi cap decides (512), within 2 where the 1e-14 cutoff does;
+    final per-site energy, populations, success probability, purity, trace: 1e-9."""
+    import json
+    import os
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08572_amd import circuits
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "qaoa_n12_p6_chi512_seed0_oracle.json")) as f:
+        o = json.load(f)
+    print("[gpu] N=12 chi=512 p=6 fp64 against the stored oracle", flush=True)
+    infos = []
+    m = circuits.run_circuit(config_m3(0, n=12, p=6), infos=infos)
+    assert len(infos) == len(o["log"])
+    worst_t = worst_x = 0.0
+    for x, r in zip(infos, o["log"]):
+        assert x["bond"] == r["bond"]
+        worst_t = max(worst_t, abs(x["trace_before"] - r["trace_before"]) / abs(r["trace_before"]))
+        worst_x = max(worst_x, abs(x["xi_before"] - r["xi_before"]) / abs(r["xi_before"]))
+        if r["kept"] >= 512:
+            assert x["kept"] == 512, (x, r)
+        else:
+            assert abs(x["kept"] - r["kept"]) <= 2, (x, r)
+        assert x["ppt_feasible"] == r["ppt_feasible"]
+    g = circuits.observables(m)
+    de = abs(g["energy_per_site"] - o["energy_per_site"])
+    dp = float(np.max(np.abs(g["populations"] - np.array(o["populations"]))))
+    dpur = abs(circuits.purity(m) - o["purity"])
+    print(f"[gpu] max rel trace/xi before cuts {worst_t:.2e} {worst_x:.2e}; |dE/N| {de:.2e}, max |d pop| "
+          f"{dp:.2e}, |d purity| {dpur:.2e}", flush=True)
+    assert worst_t <= 1e-9 and worst_x <= 1e-9
+    assert de <= 1e-9 and dp <= 1e-9 and dpur <= 1e-9
+    assert abs(g["p_success"] - o["p_success"]) <= 1e-9
+    assert abs(g["trace"] - complex(*o["trace"])) <= 1e-9
+    assert m.bond_dims() == o["bond_dims"]
+    m.close()
