@@ -12,8 +12,8 @@
 // diagonal blocks, not a sequential tridiagonal reduction of order 768.
 //
 //   chol_shift_kernel  s from the trace of G (one workgroup; no host synchronisation)
-//   chol_diag_kernel   one workgroup: the 64 x 64 diagonal block factored in LDS
-//                      (right-looking, one barrier per column) and its lower-triangular inverse
+//   chol_diag_kernel   one workgroup of 1024 threads: the 64 x 64 diagonal block factored in
+//                      LDS (right-looking, one barrier per column) and its lower-triangular inverse
 //   panel and trailing updates, and the block triangular solve, run on the matrix-core GEMM.
 #include <math.h>
 
@@ -46,30 +46,35 @@ __global__ __launch_bounds__(256) void chol_shift_kernel(const double* __restric
 // A pivot that is not positive and finite sets flag[0] = 1 and is replaced by 1 (the result is
 // then discarded by the caller).
 //
-// The block lives in LDS; thread (c, h) = (t mod 64, t / 64) works on column c, rows c + h + 4 k.
-// Step j of the right-looking factorisation reads column j, final since step j - 1, and applies
-// a_rc -= a_rj conj(a_cj) / a_jj to the rows r >= c of the columns c > j, so that one barrier per
-// step suffices; the columns are scaled by 1 / sqrt(a_jj) at the end.  The inverse X = L^{-1}
-// follows the same pattern: y_c = e_c, step q subtracts L_rq y_qc / L_qq from the rows r > q,
-// and X_rc = y_rc / L_rr at the end.
-constexpr int DT = 256;   // threads of chol_diag_kernel
+// The block lives in LDS; thread (c, h) = (t mod 64, t / 64) works on column c, rows
+// c + h + 16 k (16 row slices, so a step's longest row list is 4).  Step j of the right-looking
+// factorisation reads column j, final since step j - 1, and applies a_rc -= a_rj conj(a_cj) /
+// a_jj to the rows r >= c of the columns c > j, so that one barrier per step suffices; the
+// columns are scaled by 1 / sqrt(a_jj) at the end.  The block is stored by columns (64 doubles
+// apart): the 64 lanes of a wave then read column j at consecutive addresses and update
+// a_{c+h+16k, c} on distinct banks.  The inverse X = L^{-1} follows the same pattern: y_c =
+// e_c, step q subtracts L_rq y_qc / L_qq from the rows r > q (row slice h of every column;
+// the lanes of a wave read the same L_rq and update a row of Y stored by rows), and X_rc =
+// y_rc / L_rr at the end.
+constexpr int DT = 1024;            // threads of chol_diag_kernel
+constexpr int DS = DT / CB;         // row slices
 __global__ __launch_bounds__(DT) void chol_diag_kernel(const double* __restrict__ A, long lda, int k0, int kb,
                                                        const double* __restrict__ shift, double* __restrict__ L,
                                                        long ldl, double* __restrict__ Li, int* __restrict__ flag) {
-    __shared__ double Ar[CB][CB + 1], Am[CB][CB + 1];   // the block, then its factor
-    __shared__ double Yr[CB][CB + 1], Ym[CB][CB + 1];   // the inverse
+    __shared__ double Ar[CB][CB], Am[CB][CB];           // [column][row]: the block, then its factor
+    __shared__ double Yr[CB][CB + 1], Ym[CB][CB + 1];   // [row][column]: the inverse
     __shared__ double dg[CB];                           // sqrt of the pivots
-    const int t = threadIdx.x, c = t & (CB - 1), h = t >> 6;
+    const int t = threadIdx.x, c = t & (CB - 1), h = t / CB;
     const double s = shift ? shift[0] : 0.0;
-    for (int r = h; r < CB; r += 4) {
+    for (int r = h; r < CB; r += DS) {
         double vr = 0.0, vi = 0.0;
         if (r < kb && c < kb && r >= c) {
             const double* a = A + 2 * ((long)(k0 + r) * lda + (k0 + c));
             vr = a[0];
             vi = r == c ? 0.0 : a[1];
         }
-        Ar[r][c] = r == c && c < kb ? vr + s : vr;
-        Am[r][c] = vi;
+        Ar[c][r] = r == c && c < kb ? vr + s : vr;
+        Am[c][r] = vi;
     }
     __syncthreads();
     for (int j = 0; j < kb; ++j) {
@@ -77,11 +82,11 @@ __global__ __launch_bounds__(DT) void chol_diag_kernel(const double* __restrict_
         if (!(p > 0.0) || !isfinite(p)) p = 1.0;
         if (c > j && c < kb) {
             const double rp = 1.0 / p;
-            const double yr = Ar[c][j] * rp, yi = -Am[c][j] * rp;   // conj(a_cj) / a_jj
-            for (int r = c + h; r < kb; r += 4) {
-                const double xr = Ar[r][j], xi = Am[r][j];
-                Ar[r][c] -= xr * yr - xi * yi;
-                Am[r][c] -= xr * yi + xi * yr;
+            const double yr = Ar[j][c] * rp, yi = -Am[j][c] * rp;   // conj(a_cj) / a_jj
+            for (int r = c + h; r < kb; r += DS) {
+                const double xr = Ar[j][r], xi = Am[j][r];
+                Ar[c][r] -= xr * yr - xi * yi;
+                Am[c][r] -= xr * yi + xi * yr;
             }
         }
         __syncthreads();
@@ -97,12 +102,12 @@ __global__ __launch_bounds__(DT) void chol_diag_kernel(const double* __restrict_
     }
     __syncthreads();
     const double rdc = 1.0 / dg[c];
-    for (int r = h; r < CB; r += 4) {
+    for (int r = h; r < CB; r += DS) {
         const bool low = r > c && r < kb && c < kb;
-        const double lr = r == c ? dg[c] : (low ? Ar[r][c] * rdc : 0.0);
-        const double li = low ? Am[r][c] * rdc : 0.0;
-        Ar[r][c] = lr;
-        Am[r][c] = li;
+        const double lr = r == c ? dg[c] : (low ? Ar[c][r] * rdc : 0.0);
+        const double li = low ? Am[c][r] * rdc : 0.0;
+        Ar[c][r] = lr;
+        Am[c][r] = li;
         Yr[r][c] = r == c ? 1.0 : 0.0;
         Ym[r][c] = 0.0;
         if (r < kb && c < kb) {
@@ -116,16 +121,15 @@ __global__ __launch_bounds__(DT) void chol_diag_kernel(const double* __restrict_
         if (c <= q) {
             const double rq = 1.0 / Ar[q][q];
             const double yr = Yr[q][c] * rq, yi = Ym[q][c] * rq;
-            int r = q + 1 + ((h - (q + 1)) & 3);   // first row > q of this thread's slice
-            for (; r < kb; r += 4) {
-                const double lr = Ar[r][q], li = Am[r][q];
+            for (int r = q + 1 + ((h - (q + 1)) & (DS - 1)); r < kb; r += DS) {   // rows > q of slice h
+                const double lr = Ar[q][r], li = Am[q][r];
                 Yr[r][c] -= lr * yr - li * yi;
                 Ym[r][c] -= lr * yi + li * yr;
             }
         }
         __syncthreads();
     }
-    for (int r = h; r < kb; r += 4) {
+    for (int r = h; r < kb; r += DS) {
         const double rr = 1.0 / Ar[r][r];
         Li[2 * ((long)r * CB + c)] = c < kb ? Yr[r][c] * rr : 0.0;
         Li[2 * ((long)r * CB + c) + 1] = c < kb ? Ym[r][c] * rr : 0.0;
