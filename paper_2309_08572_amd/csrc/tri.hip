@@ -188,8 +188,9 @@ __device__ __forceinline__ double pivot_rcp(double q) {
 // tiles stored in full); a group of 8 lanes owns RS tiles, lane k row k of each (8 complex
 // values, slot q holding column q ^ k of the tile): RS_REG tiles in registers, the rest in
 // LDS, so no matrix element leaves the chip until the reflectors are written.  v and w live in LDS at absolute indices with zeros over
-// the reduced part, so the arithmetic needs no masks.  Per column: Hermitian matvec (row sums
-// in registers, column sums and row totals by LDS f64 atomics), rank-2 update in place.
+// the reduced part, so the arithmetic needs no masks.  Per column one pass over the tiles:
+// the previous column's rank-2 update in place, then the Hermitian matvec with the updated
+// values (row sums in registers, column sums and row totals by LDS f64 atomics).
 constexpr int RB = 512;        // threads: 2 waves per SIMD leave 256 registers per lane
 constexpr int RNW = RB / 64;
 constexpr int RT = 8;
@@ -203,12 +204,14 @@ static_assert((RMAX / RT) * (RMAX / RT + 1) / 2 <= RG * RS, "tiles of the larges
 struct RedLds {
     double tr[RS_LDS][RT][RB];   // LDS tiles, [slot][column][lane]
     double ti[RS_LDS][RT][RB];
-    double vabs[2 * RMAX];       // column j below the diagonal (absolute rows)
-    double v[2 * RMAX];          // Householder vector (absolute rows, zero outside the block)
+    double vabs[2 * RMAX];       // column j below the diagonal, all earlier updates applied (absolute rows)
+    double raw[2 * RMAX];        // column j + 1 as the tiles hold it during step j (update j not applied)
+    double v[2][2 * RMAX];       // Householder vectors of columns j and j - 1 (by parity; absolute
+                                 // rows, zero outside the block)
     double pabs[2 * RMAX];       // A22 v, accumulated by the tiles' atomics (cleared after use)
-    double wv[2 * RMAX];         // w of the rank-2 update
+    double wv[2 * RMAX];         // w of the last rank-2 update
     double red[2 * RNW];         // per-wave partials of v^H A22 v (written before the matvec barrier)
-    double red2[2 * RNW];        // per-wave partials of the next column's norm (before the update barrier)
+    double red2[2 * RNW];        // per-wave partials of the next column's norm
 };
 
 // Per-wave partial of a workgroup sum into red[w]; after the next barrier collect() returns the
@@ -336,6 +339,76 @@ __device__ __forceinline__ void tile_update(TileRow& x, int I, int J, int k, con
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// The previous column's update A -= vp wp^H + wp vp^H on this lane's tile row, and then, when
+// mv, p += A v over the updated tile exactly as tile_matvec does: one pass over the tile per
+// column instead of an update pass and a product pass.
+template <class TileRow>
+__device__ __forceinline__ void tile_update_matvec(TileRow& x, int I, int J, int k, const double* vp,
+                                                   const double* wp, const double* v, double* pabs, double& vav,
+                                                   bool mv) {
+    __builtin_amdgcn_sched_barrier(0);
+    const int r = RT * I + k;
+    const double pr = vp[2 * r], pi = vp[2 * r + 1], qr = wp[2 * r], qi = wp[2 * r + 1];
+    const double vrr = v[2 * r], vri = v[2 * r + 1];
+    double rr = 0.0, ri = 0.0;
+    double ar[RT], ai[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int c = RT * J + (q ^ k);
+        const double pcr = vp[2 * c], pci = vp[2 * c + 1], qcr = wp[2 * c], qci = wp[2 * c + 1];
+        const double hr = x.re(q) - (pr * qcr + pi * qci + qr * pcr + qi * pci);
+        const double hi = x.im(q) - (pi * qcr - pr * qci + qi * pcr - qr * pci);
+        x.set(q, hr, hi);
+        const double vcr = v[2 * c], vci = v[2 * c + 1];
+        rr += hr * vcr - hi * vci;
+        ri += hr * vci + hi * vcr;
+        ar[q] = hr * vrr + hi * vri;   // conj(A_rc) v_r
+        ai[q] = hr * vri - hi * vrr;
+    }
+    if (mv) {
+        if (I != J) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ar[q] += dpp_mov<0x141>(ar[7 - q]);
+                ai[q] += dpp_mov<0x141>(ai[7 - q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                ar[q] += dpp_mov<0x4E>(ar[q + 2]);
+                ai[q] += dpp_mov<0x4E>(ai[q + 2]);
+            }
+            ar[0] += dpp_mov<0xB1>(ar[1]);
+            ai[0] += dpp_mov<0xB1>(ai[1]);
+            const int c = RT * J + k;
+            atomicAdd(&pabs[2 * c], ar[0]);
+            atomicAdd(&pabs[2 * c + 1], ai[0]);
+            vav += v[2 * c] * ar[0] + v[2 * c + 1] * ai[0];
+        }
+        atomicAdd(&pabs[2 * r], rr);
+        atomicAdd(&pabs[2 * r + 1], ri);
+        vav += vrr * rr + vri * ri;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// column col (rows col.. of this lane's tile row) -> raw, unchanged
+template <class TileRow>
+__device__ __forceinline__ void tile_extract_raw(const TileRow& x, int I, int J, int col, int k, int n, double* raw) {
+    if (I < 0 || J != col / RT) return;
+    const int r = RT * I + k, jq = (col - RT * (col / RT)) ^ k;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int q = 0; q < RT; ++q)
+        if (q == jq) {
+            a = x.re(q);
+            b = x.im(q);
+        }
+    if (r >= col && r < n) {
+        raw[2 * r] = a;
+        raw[2 * r + 1] = b;
+    }
+}
+
 // a lane's row of one tile: in registers, or in LDS ([column][lane] planes)
 struct RegRow {
     double (&r)[RT];
@@ -421,7 +494,9 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
     }
     for (int i = tid; i < 2 * RMAX; i += RB) {
         L.vabs[i] = 0.0;
-        L.v[i] = 0.0;
+        L.raw[i] = 0.0;
+        L.v[0][i] = 0.0;
+        L.v[1][i] = 0.0;
         L.pabs[i] = 0.0;
         L.wv[i] = 0.0;
     }
@@ -442,10 +517,13 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
         __syncthreads();
     }
 
-    // Four barriers per column: after v (in LDS), after the matvec (p = A22 v and v^H A22 v
-    // complete), after w, after the update (which also extracts column j + 1 and its norm).
-    // p^H v = conj(tau) v^H A22 v, so w = tau p - (|tau|^2 / 2)(v^H A22 v) v needs no
-    // reduction of its own.
+    // Three barriers per column.  Step j: (1) every thread forms column j's reflector from the
+    // corrected column in vabs and its norm; v_j goes to LDS.  (2) One pass over the tiles applies
+    // column j - 1's rank-2 update (held back from step j - 1) and accumulates p = A22 v_j and
+    // v_j^H A22 v_j with the updated values; the tiles' column j + 1 is copied to raw.  (3) w_j =
+    // tau p - (|tau|^2 / 2)(v^H A22 v) v, and column j + 1 corrected for update j (O(n): each
+    // thread recomputes w_{j+1}), with its norm.  p^H v = conj(tau) v^H A22 v, so w needs no
+    // reduction of its own.  The last update is never applied to the tiles (nothing reads them).
     for (int j = 0; j < n - 1; ++j) {
         // Tile coordinates are laundered each column so that the compiler recomputes the
         // LDS column addresses instead of keeping 40 of them live across the loop.
@@ -479,68 +557,78 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
             }
         }
         const bool reflect = tr_ != 0.0 || ti_ != 0.0;   // the same in every thread
+        double* vc = L.v[j & 1];
+        const double* vp = L.v[(j & 1) ^ 1];
         // v (absolute rows: 1 at j + 1, (sr + i si) x below, 0 elsewhere) and reflector row j
         for (int i = tid; i < RMAX; i += RB) {
             double vr, vi;
             hh_entry(L.vabs, i, j, n, sr, si, vr, vi);
-            L.v[2 * i] = vr;
-            L.v[2 * i + 1] = vi;
+            vc[2 * i] = vr;
+            vc[2 * i + 1] = vi;
             if (i > j && i < n) {
                 refl[2 * ((long)j * n + (i - j - 1))] = vr;
                 refl[2 * ((long)j * n + (i - j - 1)) + 1] = vi;
             }
         }
         __syncthreads();
-        // p = A22 v (tau applied below) and this thread's share of v^H A22 v
+        // update j - 1, then p = A22 v_j (tau applied below) and this thread's share of v^H A22 v;
+        // column j + 1 of the updated tiles -> raw
         double vav = 0.0;
-        if (reflect) {
 #pragma unroll
-            for (int s = 0; s < RS_REG; ++s)
-                if (tile_live(tI[s], tJ[s], j)) {
-                    RegRow x{ar[s], ai[s]};
-                    tile_matvec(x, tI[s], tJ[s], k, L.v, L.pabs, vav);
-                }
+        for (int s = 0; s < RS_REG; ++s) {
+            RegRow x{ar[s], ai[s]};
+            if (tile_live(tI[s], tJ[s], j - 1)) tile_update_matvec(x, tI[s], tJ[s], k, vp, L.wv, vc, L.pabs, vav, reflect);
+            tile_extract_raw(x, tI[s], tJ[s], j + 1, k, n, L.raw);
+        }
 #pragma unroll
-            for (int s = 0; s < RS_LDS; ++s)
-                if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j)) {
-                    LdsRow x{L.tr[s], L.ti[s], tid};
-                    tile_matvec(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.pabs, vav);
-                }
+        for (int s = 0; s < RS_LDS; ++s) {
+            LdsRow x{L.tr[s], L.ti[s], tid};
+            if (tile_live(tI[RS_REG + s], tJ[RS_REG + s], j - 1))
+                tile_update_matvec(x, tI[RS_REG + s], tJ[RS_REG + s], k, vp, L.wv, vc, L.pabs, vav, reflect);
+            tile_extract_raw(x, tI[RS_REG + s], tJ[RS_REG + s], j + 1, k, n, L.raw);
         }
         publish(vav, L.red);
         __syncthreads();
-        // w = tau p - (|tau|^2 / 2)(v^H A22 v) v; clear p
+        // w = tau p - (|tau|^2 / 2)(v^H A22 v) v; clear p; column j + 1 with update j applied
+        // (a_i -= v_i conj(w_{j+1}) + w_i conj(v_{j+1})) -> vabs, dg[j + 1], its norm below the
+        // subdiagonal -> red2
+        double x2n = 0.0;
         {
             const double h = 0.5 * (tr_ * tr_ + ti_ * ti_) * collect<RNW>(L.red);
+            const int j1 = j + 1;
+            double w1r = 0.0, w1i = 0.0;
+            if (reflect) {
+                const double p1r = L.pabs[2 * j1], p1i = L.pabs[2 * j1 + 1];
+                w1r = tr_ * p1r - ti_ * p1i - h * vc[2 * j1];
+                w1i = tr_ * p1i + ti_ * p1r - h * vc[2 * j1 + 1];
+            }
+            const double v1r = vc[2 * j1], v1i = vc[2 * j1 + 1];
             for (int i = tid; i < RMAX; i += RB) {
                 double wr = 0.0, wi = 0.0;
+                const double vr = vc[2 * i], vi = vc[2 * i + 1];
                 if (reflect && i > j && i < n) {
                     const double pr0 = L.pabs[2 * i], pi0 = L.pabs[2 * i + 1];
-                    wr = tr_ * pr0 - ti_ * pi0 - h * L.v[2 * i];
-                    wi = tr_ * pi0 + ti_ * pr0 - h * L.v[2 * i + 1];
+                    wr = tr_ * pr0 - ti_ * pi0 - h * vr;
+                    wi = tr_ * pi0 + ti_ * pr0 - h * vi;
                 }
                 L.wv[2 * i] = wr;
                 L.wv[2 * i + 1] = wi;
                 L.pabs[2 * i] = 0.0;
                 L.pabs[2 * i + 1] = 0.0;
+                if (i >= j1 && i < n) {
+                    // v_i conj(w1) + w_i conj(v1)
+                    const double cr = vr * w1r + vi * w1i + wr * v1r + wi * v1i;
+                    const double ci = vi * w1r - vr * w1i + wi * v1r - wr * v1i;
+                    const double ar_ = L.raw[2 * i] - cr, ai_ = L.raw[2 * i + 1] - ci;
+                    if (i == j1) {
+                        dg[j1] = ar_;
+                    } else {
+                        L.vabs[2 * i] = ar_;
+                        L.vabs[2 * i + 1] = ai_;
+                        if (i > j1 + 1) x2n += ar_ * ar_ + ai_ * ai_;
+                    }
+                }
             }
-        }
-        __syncthreads();
-        // A22 -= v w^H + w v^H (entries outside the trailing block see v = w = 0); then column
-        // j + 1 below the diagonal -> vabs, dg[j + 1], and its norm below the subdiagonal
-        double x2n = 0.0;
-#pragma unroll
-        for (int s = 0; s < RS_REG; ++s) {
-            RegRow x{ar[s], ai[s]};
-            if (reflect && tile_live(tI[s], tJ[s], j)) tile_update(x, tI[s], tJ[s], k, L.v, L.wv);
-            tile_extract(x, tI[s], tJ[s], j + 1, k, n, L.vabs, dg, x2n);
-        }
-#pragma unroll
-        for (int s = 0; s < RS_LDS; ++s) {
-            LdsRow x{L.tr[s], L.ti[s], tid};
-            if (reflect && tile_live(tI[RS_REG + s], tJ[RS_REG + s], j))
-                tile_update(x, tI[RS_REG + s], tJ[RS_REG + s], k, L.v, L.wv);
-            tile_extract(x, tI[RS_REG + s], tJ[RS_REG + s], j + 1, k, n, L.vabs, dg, x2n);
         }
         publish(x2n, L.red2);
         __syncthreads();
