@@ -230,3 +230,61 @@ def renyi2_mutual_information(m: MPDO, a, b) -> float:
     a, b = set(a), set(b)
     v = m.expect2([_block_term(m, a), _block_term(m, b), _block_term(m, a | b)]).real
     return float(-math.log(v[0]) - math.log(v[1]) + math.log(v[2]))
+
+
+# ------------------------------------------------------------ the pulse-level QAOA iteration
+def _qubit_unitary(u2, d: int) -> np.ndarray:
+    u = np.eye(d, dtype=np.complex128)
+    u[:2, :2] = u2
+    return u
+
+
+def _site_superop(u: np.ndarray) -> np.ndarray:
+    """vec(u rho u^+) with the per-atom vectorised index sigma d + sigma'."""
+    return np.kron(u, u.conj())
+
+
+def cz_phase(S: np.ndarray, d: int) -> float:
+    """The single-qubit Z phase of a two-atom CZ channel S (mpdo_apply_gate's layout):
+    arg(u_01 / u_00) read off S's action on |01><00| (a CZ pulse returns the qubit states to
+    themselves up to these phases)."""
+    D2 = d * d
+    src = (0 * d + 0) * D2 + (1 * d + 0)     # |0><0| (x) |1><0|
+    return float(np.angle(S[src, src]))
+
+
+def pulse_qaoa_ops(cz: np.ndarray, alphas, betas, b: float, d: int, phase: float):
+    """The QAOA iteration of Sec. IV from a two-atom CZ channel (Eqs. (HZ_block_representation),
+    (HZ_representation)): per layer, on every bond exp(i alpha Z_i Z_j) = CNOT (I (x)
+    exp(i alpha Z_j)) CNOT with CNOT = (I (x) Had) CZ (I (x) Had), the CZ's single-qubit Z
+    phase `phase` (cz_phase of the noise-free pulse) undone on both atoms; then exp(i b alpha Z)
+    and exp(i beta X) on every atom (single-atom gates on {0, 1}, noise free).  Returns
+    [(block superoperator, [zfield, mixer])] per layer (superoperators in mpdo_apply_gate's
+    layout; the mixer and field as unitaries)."""
+    corr = _site_superop(_qubit_unitary(np.diag([1.0, np.exp(-1j * phase)]), d))
+    czc = np.kron(corr, corr) @ cz
+    had = _site_superop(_qubit_unitary(np.array([[1.0, 1.0], [1.0, -1.0]]) / math.sqrt(2.0), d))
+    eye = np.eye(d * d, dtype=np.complex128)
+    h2 = np.kron(eye, had)
+    layers = []
+    for a, bt in zip(alphas, betas):
+        rz = np.kron(eye, _site_superop(_qubit_unitary(np.diag([np.exp(1j * a), np.exp(-1j * a)]), d)))
+        blk = h2 @ czc @ h2 @ rz @ h2 @ czc @ h2
+        zf = _qubit_unitary(np.diag([np.exp(1j * b * a), np.exp(-1j * b * a)]), d)
+        mx = _qubit_unitary(np.array([[math.cos(bt), 1j * math.sin(bt)], [1j * math.sin(bt), math.cos(bt)]]), d)
+        layers.append((blk, [zf, mx]))
+    return layers
+
+
+def run_pulse_qaoa(n: int, d: int, chi: int, layers, precision: int = MPDO_FP64) -> MPDO:
+    """|+>^N through the layers of pulse_qaoa_ops: bonds left to right, then the single-atom
+    gates on every atom (queued, they enter the next block)."""
+    m = MPDO(n, d, chi, precision=precision)
+    m.init_product_state([plus_rho(d)] * n)
+    for blk, singles in layers:
+        for i in range(n - 1):
+            m.apply_gate(i, blk)
+        for j in range(n):
+            for u in singles:
+                m.apply_channel(j, [u])
+    return m
