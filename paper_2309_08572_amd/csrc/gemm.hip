@@ -311,15 +311,17 @@ __device__ __forceinline__ v4f mfma_bf16(v8us a, v8us b, v4f c) {
                                                    0);
 }
 
-// Per-thread load pattern of one operand tile (XT rows (A) or columns (B) by XK k): value j
-// (0 <= j < XL) sits at row r0 + j dr and k k0 + j dk of the tile; `fast` says whether k is
-// the contiguous dimension of the view (then 32 consecutive threads read 32 consecutive k of
-// a row), else rows are (then 128 consecutive threads read 128 consecutive rows).
+// Per-thread load pattern of one operand tile (TILE rows (A) or columns (B) by XK k): value j
+// (0 <= j < TILE XK / 256) sits at row r0 + j dr and k k0 + j dk of the tile; `kfast` says
+// whether k is the contiguous dimension of the view (then 32 consecutive threads read 32
+// consecutive k of a row), else rows are (then TILE consecutive threads read TILE consecutive
+// rows).
 struct XPat {
     int r0, dr, k0, dk;
 };
+template <int TILE = XT>
 __device__ __forceinline__ XPat xpat(int tid, bool kfast) {
-    return kfast ? XPat{tid / XK, 256 / XK, tid % XK, 0} : XPat{tid % XT, 0, tid / XT, 256 / XT};
+    return kfast ? XPat{tid / XK, 256 / XK, tid % XK, 0} : XPat{tid % TILE, 0, tid / TILE, 256 / TILE};
 }
 
 __global__ __launch_bounds__(256) void cgemm_x3_kernel(GemmArgs<float> g) {
@@ -612,6 +614,146 @@ __global__ __launch_bounds__(256) void cgemm_f32_big_kernel(GemmArgs<float> g) {
             }
 }
 
+// FP64 products of large outputs: 128 x 64 workgroup tiles (each wave 64 x 32: 4 x 2 MFMA
+// 16x16x4 FP64 tiles, whose accumulators fill 128 AGPRs; a square 64 x 64 wave tile would
+// need all 256), the load pattern of the FP32 kernel above.  A k-tile of 32 then costs each
+// SIMD 8 tiles x 8 steps x 4 MFMAs x 64 cycles, twice the 64 x 64 kernel's, against 1.5 times
+// its operands.  LDS rows of 33 doubles.
+constexpr int DM = 128, DN = 64;
+__global__ __launch_bounds__(256) void cgemm_f64_big_kernel(GemmArgs<double> g) {
+    constexpr int TM = 4, TN = 2, WQM = 16 * TM, WQN = 16 * TN;
+    constexpr int LA = DM * XK / 256, LB = DN * XK / 256;
+    __shared__ double sAr[DM][XK + 1], sAi[DM][XK + 1];
+    __shared__ double sBr[DN][XK + 1], sBi[DN][XK + 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1;
+    const int wc = wave & 1;
+    const unsigned nx = gridDim.x, ny = gridDim.y;
+    const unsigned nw = nx * ny * gridDim.z;
+    const unsigned w = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const unsigned per = nw / 8, rem = nw % 8, xcd = w % 8;
+    const unsigned t = xcd * per + (xcd < rem ? xcd : rem) + w / 8;
+    const int m0 = (int)((t / nx) % ny) * DM;
+    const int n0 = (int)(t % nx) * DN;
+    const int bz = (int)(t / (nx * ny));
+    const int b = bz / g.ksplit;
+    const int kc = bz - b * g.ksplit;
+    const int kbeg = kc * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+
+    const XPat pa = xpat<DM>(tid, g.A.cs == 1), pb = xpat<DN>(tid, g.B.rs == 1);
+    const double* Ab = g.A.p + 2 * ((long)b * g.sA + (long)(m0 + pa.r0) * g.A.rs + (long)pa.k0 * g.A.cs);
+    const long Aj = 2 * ((long)pa.dr * g.A.rs + (long)pa.dk * g.A.cs), Ak = 2 * (long)g.A.cs;
+    const double* Bb = g.B.p + 2 * ((long)b * g.sB + (long)(n0 + pb.r0) * g.B.cs + (long)pb.k0 * g.B.rs);
+    const long Bj = 2 * ((long)pb.dr * g.B.cs + (long)pb.dk * g.B.rs), Bk = 2 * (long)g.B.rs;
+    const double sa = g.A.conj ? -1.0 : 1.0, sb = g.B.conj ? -1.0 : 1.0;
+    double* Cp = g.C.p + 2 * (long)b * g.sC;
+
+    v4d cr[TM][TN], ci[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            cr[i][j] = (v4d){0, 0, 0, 0};
+            ci[i][j] = (v4d){0, 0, 0, 0};
+        }
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+
+    double2 va[LA], vb[LB];
+    auto fetch = [&](int k0) {
+        const double* ap = Ab + (long)k0 * Ak;
+        const double* bp = Bb + (long)k0 * Bk;
+#pragma unroll
+        for (int j = 0; j < LA; ++j) {
+            va[j] = make_double2(0.0, 0.0);
+            if (m0 + pa.r0 + j * pa.dr < g.M && k0 + pa.k0 + j * pa.dk < kend)
+                va[j] = *(const double2*)(ap + j * Aj);
+        }
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            vb[j] = make_double2(0.0, 0.0);
+            if (n0 + pb.r0 + j * pb.dr < g.N && k0 + pb.k0 + j * pb.dk < kend)
+                vb[j] = *(const double2*)(bp + j * Bj);
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += XK) {
+#pragma unroll
+        for (int j = 0; j < LA; ++j) {
+            const int r = pa.r0 + j * pa.dr, k = pa.k0 + j * pa.dk;
+            sAr[r][k] = va[j].x;
+            sAi[r][k] = sa * va[j].y;
+        }
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            const int r = pb.r0 + j * pb.dr, k = pb.k0 + j * pb.dk;
+            sBr[r][k] = vb[j].x;
+            sBi[r][k] = sb * vb[j].y;
+        }
+        __syncthreads();
+        if (k0 + XK < kend) fetch(k0 + XK);
+#pragma unroll 2
+        for (int kk = 0; kk < XK; kk += 4) {
+            double br[TN], bi[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                br[j] = sBr[wc * WQN + j * 16 + li][kk + lk];
+                bi[j] = sBi[wc * WQN + j * 16 + li][kk + lk];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const double ar = sAr[wr * WQM + i * 16 + li][kk + lk];
+                const double ai = sAi[wr * WQM + i * 16 + li][kk + lk];
+                const double nai = -ai;
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    cr[i][j] = mfma16(ar, br[j], cr[i][j]);
+                    cr[i][j] = mfma16(nai, bi[j], cr[i][j]);
+                    ci[i][j] = mfma16(ar, bi[j], ci[i][j]);
+                    ci[i][j] = mfma16(ai, br[j], ci[i][j]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wr * WQM + i * 16 + acc_row(0.0, lk, r);
+                const int gn = n0 + wc * WQN + j * 16 + li;
+                if (gm >= g.M || gn >= g.N) continue;
+                const double xr = cr[i][j][r], xi = ci[i][j][r];
+                const double vr = g.ar * xr - g.ai * xi;
+                const double vi = g.ar * xi + g.ai * xr;
+                if (g.part) {
+                    double* pp = g.part + 2 * (((long)kc * g.batch + b) * g.M * (long)g.N + (long)gm * g.N + gn);
+                    pp[0] = vr;
+                    pp[1] = vi;
+                } else {
+                    const long off = 2 * ((long)gm * g.C.rs + (long)gn * g.C.cs);
+                    double or_ = 0.0, oi = 0.0;
+                    if (g.br != 0.0 || g.bi != 0.0) {
+                        const double cr0 = Cp[off];
+                        const double ci0 = g.C.conj ? -Cp[off + 1] : Cp[off + 1];
+                        or_ = g.br * cr0 - g.bi * ci0;
+                        oi = g.br * ci0 + g.bi * cr0;
+                    }
+                    const double wr_ = vr + or_;
+                    const double wi_ = vi + oi;
+                    Cp[off] = wr_;
+                    Cp[off + 1] = g.C.conj ? -wi_ : wi_;
+                }
+            }
+}
+
 // C = beta C + sum over the ks k-chunks of the partial products, added in chunk order (FP64
 // sums), one thread per output element of every batch.
 template <typename T>
@@ -646,14 +788,22 @@ size_t split_bytes(int M, int N, int batch, int ks) {
     return (size_t)ks * batch * (size_t)M * N * 2 * sizeof(T);
 }
 
-// Launch plan: block tile (32 wm)^2 with wm = 2 or 1, and the k range split ks ways.
+// Launch plan: block tile wm = 4 (128 x 128; FP64 128 x 64), 2 (64 x 64) or 1 (32 x 32), and the
+// k range split ks ways.
 struct Plan {
     int wm, ks;
 };
 
-int tiles_of(int M, int N, int batch, int wm) {
-    const int bt = 32 * wm;
-    return ((M + bt - 1) / bt) * ((N + bt - 1) / bt) * batch;
+// Workgroup tile of a plan: (32 wm) x (32 wm), except FP64 wm = 4: 128 x 64.
+void tile_dims(bool fp64, int wm, int& bm, int& bn) {
+    bm = 32 * wm;
+    bn = (fp64 && wm == 4) ? 64 : 32 * wm;
+}
+
+int tiles_of(int M, int N, int batch, int wm, bool fp64 = false) {
+    int bm, bn;
+    tile_dims(fp64, wm, bm, bn);
+    return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch;
 }
 
 // k extent of one chunk when the k range is split about ks ways (a multiple of BK)
@@ -670,12 +820,15 @@ int chunk_of(int K, int ks) { return (((K + ks - 1) / ks + BK - 1) / BK) * BK; }
 // Launch plan: block tile (32 wm)^2.
 double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p, bool x3 = false) {
     const double tsz = fp64 ? 8.0 : 4.0;
-    const double W = (double)tiles_of(M, N, batch, p.wm) * p.ks;
+    int bm, bn;
+    tile_dims(fp64, p.wm, bm, bn);
+    const double W = (double)tiles_of(M, N, batch, p.wm, fp64) * p.ks;
     const int chunk = p.ks > 1 ? chunk_of(K, p.ks) : K;
-    const double cyc = (x3 ? 6.0 : fp64 ? 64.0 : 32.0) * p.wm * p.wm * chunk;
+    // per unit of k a 16x16 tile costs 64 (FP64), 32 (FP32) or 6 (split-BF16) cycles
+    const double cyc = (x3 ? 6.0 : fp64 ? 64.0 : 32.0) * (bm / 32) * (bn / 32) * chunk;
     const double mfma_us = std::ceil(W / 256.0) * cyc / 2400.0;
-    const double bytes = W * chunk * 64.0 * p.wm * 2.0 * tsz;
-    const double part_us = p.ks > 1 ? 2.0 * W * 1024.0 * p.wm * p.wm * 2.0 * tsz / 4e6 : 0.0;
+    const double bytes = W * chunk * (double)(bm + bn) * 2.0 * tsz;
+    const double part_us = p.ks > 1 ? 2.0 * W * (double)bm * bn * 2.0 * tsz / 4e6 : 0.0;
     return mfma_us + 0.25 * bytes / 16e6 + part_us + 2.0 + (p.ks > 1 ? 5.0 : 0.0);
 }
 
@@ -684,7 +837,7 @@ double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p, bool x3 = fa
 // x3: the split-BF16 kernel (128 x 128 tile, wm = 4)
 Plan plan_of(int M, int N, int K, int batch, bool fp64, int wm_max = 2, int ks_max = 64, bool x3 = false) {
     if (x3) wm_max = 4;   // the split-BF16 kernel has only the 128 x 128 tile
-    else if (!fp64 && wm_max == 2) wm_max = 4;   // plain FP32 products may take it too
+    else if (wm_max == 2) wm_max = 4;   // plain products may take the large tile too
     Plan best{wm_max, 1};
     double best_t = plan_cost(M, N, K, batch, fp64, best, x3);
     for (int wm = wm_max; wm >= (x3 ? 4 : 1); wm /= 2)   // tiles of 128, 64, 32
@@ -742,19 +895,23 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
             g.part = (T*)opt.ws;
         }
     }
-    const int bt = 32 * plan.wm;
-    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, batch * g.ksplit);   // plan.wm = 4: the 128 x 128 tile
+    int bm, bn;
+    tile_dims(std::is_same<T, double>::value, plan.wm, bm, bn);
+    dim3 grid((N + bn - 1) / bn, (M + bm - 1) / bm, batch * g.ksplit);   // plan.wm = 4: the large tile
     if (getenv("MPDO_DEBUG_GEMM"))
-        fprintf(stderr, "[mpdo gemm] %s M %d N %d K %d batch %d tile %d ksplit %d chunk %d%s\n",
-                sizeof(T) == 8 ? "f64" : (opt.split_bf16 ? "bf16x3" : "f32"), M, N, K, batch, bt, g.ksplit, g.kchunk,
+        fprintf(stderr, "[mpdo gemm] %s M %d N %d K %d batch %d tile %dx%d ksplit %d chunk %d%s\n",
+                sizeof(T) == 8 ? "f64" : (opt.split_bf16 ? "bf16x3" : "f32"), M, N, K, batch, bm, bn, g.ksplit, g.kchunk,
                 g.bshift || g.bcol ? " transforms" : "");
     if (prof) prof->begin(s, PF_GEMM);
     const bool tf = g.bshift || g.bcol;
-    bool big = false;   // the 128 x 128 kernels (plan.wm = 4: FP32, plain operands)
+    bool big = false;   // the large-tile kernels (plan.wm = 4, plain operands)
     if constexpr (std::is_same<T, float>::value) {
         big = !tf && plan.wm == 4;
         if (big && opt.split_bf16) hipLaunchKernelGGL(cgemm_x3_kernel, grid, dim3(256), 0, s, g);
         else if (big) hipLaunchKernelGGL(cgemm_f32_big_kernel, grid, dim3(256), 0, s, g);
+    } else {
+        big = !tf && plan.wm == 4;
+        if (big) hipLaunchKernelGGL(cgemm_f64_big_kernel, grid, dim3(256), 0, s, g);
     }
     if (big) {
     } else if (plan.wm == 2) {

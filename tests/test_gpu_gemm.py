@@ -1,6 +1,7 @@
 """Element-wise parity of the matrix-core product kernels (mpdo_cgemm) with numpy's complex128
 matrix product: every contraction of the update runs through them (FP64 and FP32 MFMA on 32 x 32,
-64 x 64 and 128 x 128 workgroup tiles, the split-BF16 kernel, k-split partial sums).
+64 x 64 and 128 x 128 (FP64: 128 x 64) workgroup tiles, the split-BF16 kernel, k-split partial
+sums).
 
 Bars, per element, from the arithmetic: with |X| the matrix of absolute values and
 P = |alpha| |op(A)| |op(B)| + |beta| |C0|,
@@ -56,6 +57,7 @@ CASES = [
     (768, 77, 8192, 0, 2, 1.0, 0.0, True),
     (768, 768, 8192, 0, 2, 1.0, 0.0, False),
     (2048, 2048, 4096, 0, 0, 1.0, 0.0, False),
+    (2100, 1000, 130, 2, 2, 1.0 + 1.0j, 0.5, True),
 ]
 
 
