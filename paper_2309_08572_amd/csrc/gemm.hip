@@ -984,11 +984,11 @@ Plan tune_plan(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A, CView<T
         if (it != g_tune.end()) return it->second;
     }
     const Plan h = plan_of(M, N, K, batch, fp64, 2, ks_max);
-    Plan cands[16];
+    Plan cands[24];
     int nc = 0;
     cands[nc++] = h;
-    for (int wm = 2; wm >= 1; --wm)
-        for (int ks = 1; ks <= ks_max && nc < 16; ks *= 2) {
+    for (int wm = 4; wm >= 1; wm /= 2)
+        for (int ks = 1; ks <= ks_max && nc < 24; ks *= 2) {
             if (ks > 1 && ks > K / 64) break;
             if (!(wm == h.wm && ks == h.ks)) cands[nc++] = Plan{wm, ks};
         }
