@@ -123,7 +123,8 @@ __device__ __forceinline__ void block_maxmin(double& a, double& b, double* red) 
 // (ROWS_PER_WAVE rows at a time).
 constexpr int RW = 256;                 // threads of the multi-workgroup reduction kernels
 constexpr int RWV = RW / 64;
-constexpr int ROWS_PER_WAVE = 4;
+constexpr int ROWS_PER_WAVE = 1;
+constexpr int COL_CHUNK = 12;           // columns per lane whose loads tri_col_kernel issues together
 constexpr int MAX_RGROUPS = 256;
 
 int reduce_groups(int m) {
@@ -767,31 +768,48 @@ __global__ __launch_bounds__(RW) void tri_col_kernel(double* __restrict__ H, int
         double ar[ROWS_PER_WAVE], ai[ROWS_PER_WAVE];
 #pragma unroll
         for (int q = 0; q < ROWS_PER_WAVE; ++q) ar[q] = ai[q] = 0.0;
-        for (int c = lane; c < m; c += 64) {
-            const double vcr = v[2 * c], vci = v[2 * c + 1];
-            double pvr = 0.0, pvi = 0.0, pwr = 0.0, pwi = 0.0;
-            if (upd) {
-                pvr = vp[2 * (c + 1)];
-                pvi = vp[2 * (c + 1) + 1];
-                pwr = wp[2 * (c + 1)];
-                pwi = wp[2 * (c + 1) + 1];
+        // columns in chunks of COL_CHUNK per lane: the chunk's loads are all issued before its
+        // stores (written in that order, so they cannot be reordered), so a chunk waits for
+        // one memory latency rather than one per column
+        for (int cb = 0; cb < m; cb += 64 * COL_CHUNK) {
+            double2 x[COL_CHUNK][ROWS_PER_WAVE];
+#pragma unroll
+            for (int t = 0; t < COL_CHUNK; ++t) {
+                const int c = cb + 64 * t + lane;
+#pragma unroll
+                for (int q = 0; q < ROWS_PER_WAVE; ++q) {
+                    const int r = r0 + q;
+                    x[t][q] = make_double2(0.0, 0.0);
+                    if (r < m && c < m) x[t][q] = *(const double2*)(H + 2 * (base + (long)r * ld + c));
+                }
             }
 #pragma unroll
-            for (int q = 0; q < ROWS_PER_WAVE; ++q) {
-                const int r = r0 + q;
-                if (r < m) {
-                    double* h = H + 2 * (base + (long)r * ld + c);
-                    double hr = h[0], hi = h[1];
-                    if (upd) {
-                        const double vr = vp[2 * (r + 1)], vi = vp[2 * (r + 1) + 1];
-                        const double wr = wp[2 * (r + 1)], wi = wp[2 * (r + 1) + 1];
-                        hr -= vr * pwr + vi * pwi + wr * pvr + wi * pvi;
-                        hi -= vi * pwr - vr * pwi + wi * pvr - wr * pvi;
-                        h[0] = hr;
-                        h[1] = hi;
+            for (int t = 0; t < COL_CHUNK; ++t) {
+                const int c = cb + 64 * t + lane;
+                if (c >= m) continue;
+                const double vcr = v[2 * c], vci = v[2 * c + 1];
+                double pvr = 0.0, pvi = 0.0, pwr = 0.0, pwi = 0.0;
+                if (upd) {
+                    pvr = vp[2 * (c + 1)];
+                    pvi = vp[2 * (c + 1) + 1];
+                    pwr = wp[2 * (c + 1)];
+                    pwi = wp[2 * (c + 1) + 1];
+                }
+#pragma unroll
+                for (int q = 0; q < ROWS_PER_WAVE; ++q) {
+                    const int r = r0 + q;
+                    if (r < m) {
+                        double hr = x[t][q].x, hi = x[t][q].y;
+                        if (upd) {
+                            const double vr = vp[2 * (r + 1)], vi = vp[2 * (r + 1) + 1];
+                            const double wr = wp[2 * (r + 1)], wi = wp[2 * (r + 1) + 1];
+                            hr -= vr * pwr + vi * pwi + wr * pvr + wi * pvi;
+                            hi -= vi * pwr - vr * pwi + wi * pvr - wr * pvi;
+                            *(double2*)(H + 2 * (base + (long)r * ld + c)) = make_double2(hr, hi);
+                        }
+                        ar[q] += hr * vcr - hi * vci;
+                        ai[q] += hr * vci + hi * vcr;
                     }
-                    ar[q] += hr * vcr - hi * vci;
-                    ai[q] += hr * vci + hi * vcr;
                 }
             }
         }
