@@ -13,7 +13,8 @@
 //
 //   chol_shift_kernel  s from the trace of G (one workgroup; no host synchronisation)
 //   chol_diag_kernel   one workgroup of 1024 threads: the 64 x 64 diagonal block factored in
-//                      LDS (right-looking, one barrier per column) and its lower-triangular inverse
+//                      LDS by 16-column panels (a panel in one wave's registers, then a rank-16
+//                      update) and its lower-triangular inverse by 16 x 16 blocks
 //   panel and trailing updates, and the block triangular solve, run on the matrix-core GEMM.
 #include <math.h>
 
@@ -46,25 +47,34 @@ __global__ __launch_bounds__(256) void chol_shift_kernel(const double* __restric
 // A pivot that is not positive and finite sets flag[0] = 1 and is replaced by 1 (the result is
 // then discarded by the caller).
 //
-// The block lives in LDS; thread (c, h) = (t mod 64, t / 64) works on column c, rows
-// c + h + 16 k (16 row slices, so a step's longest row list is 4).  Step j of the right-looking
-// factorisation reads column j, final since step j - 1, and applies a_rc -= a_rj conj(a_cj) /
-// a_jj to the rows r >= c of the columns c > j, so that one barrier per step suffices; the
-// columns are scaled by 1 / sqrt(a_jj) at the end.  The block is stored by columns (64 doubles
-// apart): the 64 lanes of a wave then read column j at consecutive addresses and update
-// a_{c+h+16k, c} on distinct banks.  The inverse X = L^{-1} follows the same pattern: y_c =
-// e_c, step q subtracts L_rq y_qc / L_qq from the rows r > q (row slice h of every column;
-// the lanes of a wave read the same L_rq and update a row of Y stored by rows), and X_rc =
-// y_rc / L_rr at the end.
-constexpr int DT = 1024;            // threads of chol_diag_kernel
-constexpr int DS = DT / CB;         // row slices
+// The block lives in LDS, stored by columns; it is factored in panels of PW = 16 columns.
+// Panel p (columns j0 = 16 p ..): one wave holds rows 0..63 of the panel in registers (lane r,
+// row r) and factors it right-looking, column by column, with the pivot and the multipliers
+// taken from other lanes by shuffles, so the 16 steps need no barrier; then every thread applies
+// the panel's rank-16 update to the trailing columns (rows r >= c), one barrier.  Columns past
+// kb are the identity.  The inverse X = L^{-1} is formed by 16 x 16 blocks: four waves invert
+// the diagonal blocks by forward substitution in registers (lane c, column c of the block), then
+// block rows I = 1, 2, 3 in turn: T_IJ = sum_{J <= K < I} L_IK X_KJ and X_IJ = -X_II T_IJ for
+// all J < I at once.  A pivot that is not positive and finite sets flag[0] = 1 and is replaced
+// by 1.
+constexpr int DT = 1024;             // threads of chol_diag_kernel
+constexpr int DS = DT / CB;         // row slices of the trailing update
+constexpr int PW = 8;               // panel width
+// x of lane `lane` (the same lane in every active lane of the wave), by two scalar reads
+__device__ __forceinline__ double lane_val(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 __global__ __launch_bounds__(DT) void chol_diag_kernel(const double* __restrict__ A, long lda, int k0, int kb,
                                                        const double* __restrict__ shift, double* __restrict__ L,
                                                        long ldl, double* __restrict__ Li, int* __restrict__ flag) {
     __shared__ double Ar[CB][CB], Am[CB][CB];           // [column][row]: the block, then its factor
     __shared__ double Yr[CB][CB + 1], Ym[CB][CB + 1];   // [row][column]: the inverse
-    __shared__ double dg[CB];                           // sqrt of the pivots
-    const int t = threadIdx.x, c = t & (CB - 1), h = t / CB;
+    __shared__ double Tr[CB / PW - 1][PW][PW + 1], Tm[CB / PW - 1][PW][PW + 1];
+    const int t = threadIdx.x, c = t & (CB - 1), h = t / CB, lane = t & 63, wv = t >> 6;
     const double s = shift ? shift[0] : 0.0;
     for (int r = h; r < CB; r += DS) {
         double vr = 0.0, vi = 0.0;
@@ -75,64 +85,136 @@ __global__ __launch_bounds__(DT) void chol_diag_kernel(const double* __restrict_
         }
         Ar[c][r] = r == c && c < kb ? vr + s : vr;
         Am[c][r] = vi;
+        Yr[r][c] = 0.0;
+        Ym[r][c] = 0.0;
     }
     __syncthreads();
-    for (int j = 0; j < kb; ++j) {
-        double p = Ar[j][j];
-        if (!(p > 0.0) || !isfinite(p)) p = 1.0;
-        if (c > j && c < kb) {
-            const double rp = 1.0 / p;
-            const double yr = Ar[j][c] * rp, yi = -Am[j][c] * rp;   // conj(a_cj) / a_jj
+    for (int j0 = 0; j0 < CB; j0 += PW) {
+        if (wv == 0) {
+            const int r = lane;
+            double ar[PW], ai[PW];
+#pragma unroll
+            for (int k = 0; k < PW; ++k) {
+                ar[k] = Ar[j0 + k][r];
+                ai[k] = Am[j0 + k][r];
+            }
+#pragma unroll
+            for (int jj = 0; jj < PW; ++jj) {
+                const int j = j0 + jj;
+                double lr, li;
+                if (j < kb) {
+                    double p = lane_val(ar[jj], j);   // a_jj
+                    if (!(p > 0.0) || !isfinite(p)) {
+                        if (r == 0) flag[0] = 1;
+                        p = 1.0;
+                    }
+                    const double d = sqrt(p), rd = 1.0 / d;
+                    lr = r > j ? ar[jj] * rd : (r == j ? d : 0.0);
+                    li = r > j ? ai[jj] * rd : 0.0;
+                } else {
+                    lr = r == j ? 1.0 : 0.0;
+                    li = 0.0;
+                }
+                ar[jj] = lr;
+                ai[jj] = li;
+#pragma unroll
+                for (int kk = jj + 1; kk < PW; ++kk) {
+                    const double cr = lane_val(lr, j0 + kk), ci = lane_val(li, j0 + kk);   // l_{j0+kk, j}
+                    ar[kk] -= lr * cr + li * ci;   // a_{r, j0+kk} -= l_rj conj(l_{j0+kk, j})
+                    ai[kk] -= li * cr - lr * ci;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < PW; ++k) {
+                const bool low = r >= j0 + k;
+                Ar[j0 + k][r] = low ? ar[k] : 0.0;
+                Am[j0 + k][r] = low ? ai[k] : 0.0;
+            }
+        }
+        __syncthreads();
+        // rank-PW update of the trailing columns c >= j0 + PW, rows r >= c
+        if (c >= j0 + PW && c < kb) {
+            double lcr[PW], lci[PW];
+#pragma unroll
+            for (int k = 0; k < PW; ++k) {
+                lcr[k] = Ar[j0 + k][c];
+                lci[k] = -Am[j0 + k][c];   // conj(l_{c, j0+k})
+            }
             for (int r = c + h; r < kb; r += DS) {
-                const double xr = Ar[j][r], xi = Am[j][r];
-                Ar[c][r] -= xr * yr - xi * yi;
-                Am[c][r] -= xr * yi + xi * yr;
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int k = 0; k < PW; ++k) {
+                    const double xr = Ar[j0 + k][r], xi = Am[j0 + k][r];
+                    sr += xr * lcr[k] - xi * lci[k];
+                    si += xr * lci[k] + xi * lcr[k];
+                }
+                Ar[c][r] -= sr;
+                Am[c][r] -= si;
             }
         }
         __syncthreads();
     }
-    // scale the columns; the factor to global memory (zero above the diagonal) and to LDS
-    if (t < CB) {
-        double p = t < kb ? Ar[t][t] : 1.0;
-        if (!(p > 0.0) || !isfinite(p)) {
-            if (t < kb) flag[0] = 1;
-            p = 1.0;
-        }
-        dg[t] = sqrt(p);
-    }
-    __syncthreads();
-    const double rdc = 1.0 / dg[c];
-    for (int r = h; r < CB; r += DS) {
-        const bool low = r > c && r < kb && c < kb;
-        const double lr = r == c ? dg[c] : (low ? Ar[c][r] * rdc : 0.0);
-        const double li = low ? Am[c][r] * rdc : 0.0;
-        Ar[c][r] = lr;
-        Am[c][r] = li;
-        Yr[r][c] = r == c ? 1.0 : 0.0;
-        Ym[r][c] = 0.0;
-        if (r < kb && c < kb) {
+    // the factor to global memory (zeros above the diagonal)
+    for (int r = h; r < kb; r += DS)
+        if (c < kb) {
             double* l = L + 2 * ((long)(k0 + r) * ldl + (k0 + c));
-            l[0] = lr;
-            l[1] = li;
+            l[0] = Ar[c][r];
+            l[1] = Am[c][r];
+        }
+    // inverse: diagonal blocks, one wave each (lanes 0..15: the block's columns)
+    // (each lane reads back only the entries of its own column it has written)
+    if (wv < CB / PW && lane < PW) {
+        const int b0 = PW * wv, cc = lane;
+        for (int rr = 0; rr < PW; ++rr) {
+            const int row = b0 + rr;
+            double sr = rr == cc ? 1.0 : 0.0, si = 0.0;
+            for (int k = cc; k < rr; ++k) {
+                const double lr = Ar[b0 + k][row], li = Am[b0 + k][row];   // l_{row, b0+k}
+                const double yr = Yr[b0 + k][b0 + cc], yi = Ym[b0 + k][b0 + cc];
+                sr -= lr * yr - li * yi;
+                si -= lr * yi + li * yr;
+            }
+            const double rd = 1.0 / Ar[row][row];
+            Yr[row][b0 + cc] = rr < cc ? 0.0 : sr * rd;
+            Ym[row][b0 + cc] = rr < cc ? 0.0 : si * rd;
         }
     }
     __syncthreads();
-    for (int q = 0; q < kb; ++q) {
-        if (c <= q) {
-            const double rq = 1.0 / Ar[q][q];
-            const double yr = Yr[q][c] * rq, yi = Ym[q][c] * rq;
-            for (int r = q + 1 + ((h - (q + 1)) & (DS - 1)); r < kb; r += DS) {   // rows > q of slice h
-                const double lr = Ar[q][r], li = Am[q][r];
-                Yr[r][c] -= lr * yr - li * yi;
-                Ym[r][c] -= lr * yi + li * yr;
+    // block rows I = 1..3: T_IJ = sum_K L_IK X_KJ, then X_IJ = -X_II T_IJ (J < I)
+    for (int I = 1; I < CB / PW; ++I) {
+        if (t < I * PW * PW) {
+            const int J = t / (PW * PW), rr = (t / PW) % PW, cc = t % PW;
+            const int row = PW * I + rr, col = PW * J + cc;
+            double sr = 0.0, si = 0.0;
+            for (int k = PW * J; k < PW * I; ++k) {
+                const double lr = Ar[k][row], li = Am[k][row];   // l_{row, k}
+                const double yr = Yr[k][col], yi = Ym[k][col];
+                sr += lr * yr - li * yi;
+                si += lr * yi + li * yr;
             }
+            Tr[J][rr][cc] = sr;
+            Tm[J][rr][cc] = si;
+        }
+        __syncthreads();
+        if (t < I * PW * PW) {
+            const int J = t / (PW * PW), rr = (t / PW) % PW, cc = t % PW;
+            const int row = PW * I + rr;
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int k = 0; k < PW; ++k) {
+                const double xr = Yr[row][PW * I + k], xi = Ym[row][PW * I + k];
+                const double tr = Tr[J][k][cc], ti = Tm[J][k][cc];
+                sr += xr * tr - xi * ti;
+                si += xr * ti + xi * tr;
+            }
+            Yr[row][PW * J + cc] = -sr;
+            Ym[row][PW * J + cc] = -si;
         }
         __syncthreads();
     }
     for (int r = h; r < kb; r += DS) {
-        const double rr = 1.0 / Ar[r][r];
-        Li[2 * ((long)r * CB + c)] = c < kb ? Yr[r][c] * rr : 0.0;
-        Li[2 * ((long)r * CB + c) + 1] = c < kb ? Ym[r][c] * rr : 0.0;
+        Li[2 * ((long)r * CB + c)] = c < kb ? Yr[r][c] : 0.0;
+        Li[2 * ((long)r * CB + c) + 1] = c < kb ? Ym[r][c] : 0.0;
     }
 }
 
