@@ -290,7 +290,8 @@ typedef struct {
 size_t mpdo_batch_workspace_bytes(const mpdo_circuit* circuits, int n_circuits);
 
 /* Run n_circuits circuits on n_workers host threads, each with its own HIP stream and
- * context (default stream priority), taking circuits from a shared queue; the kernels of
+ * context (default stream priority), taking circuits from a shared queue ordered by bond cap
+ * and then by estimated cost (two-site updates x chi_max^3), largest first; the kernels of
  * different circuits overlap on the GPU.  device_workspace: NULL (the library allocates
  * n_workers * mpdo_batch_workspace_bytes with hipMalloc) or a caller buffer of at least
  * that size.  Per-circuit failures are reported in circuits[i].status; the call returns

@@ -1,13 +1,16 @@
 // Batched execution of independent circuits: a native worker pool over the C ABI.
 //
 // Each worker thread owns one HIP stream and a slice of the device workspace; it takes
-// circuits from a shared atomic counter, builds a context for the circuit on its stream,
+// circuits from a shared atomic counter over a list ordered by estimated cost, largest first
+// (bond cap, then the number of two-site updates; so circuits of one bond cap run together and
+// the long ones do not start last), builds a context for the circuit on its stream,
 // applies the circuit's Kraus maps in order (two-site updates with PPT, queued single-atom
 // maps), evaluates the observables and records them.  Circuits share no state, so the
 // latency-bound kernels of different circuits (Jacobi rounds, small GEMMs) fill the GPU
 // together.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <string.h>
@@ -40,6 +43,15 @@ mpdo_config config_of(const mpdo_circuit& c, void* stream) {
     cfg.renorm_trace = 0;
     cfg.hip_stream = stream;
     return cfg;
+}
+
+// Relative cost of a circuit: two-site updates times the cube of its bond cap (an update's
+// products and eigenproblems grow with the third power of the bond dimension).
+double cost_of(const mpdo_circuit& c) {
+    long two = 0;
+    for (int k = 0; k < c.n_ops; ++k) two += c.op_kind[k] == 0;
+    const double chi = (double)c.chi_max;
+    return (double)two * chi * chi * chi;
 }
 
 mpdo_status run_one(mpdo_circuit& c, hipStream_t stream, char* ws, size_t ws_bytes) {
@@ -100,6 +112,16 @@ mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers
     }
     int device = 0;
     (void)hipGetDevice(&device);
+    std::vector<int> order(n_circuits);
+    std::vector<double> cost(n_circuits);
+    for (int i = 0; i < n_circuits; ++i) {
+        order[i] = i;
+        cost[i] = cost_of(circuits[i]);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (circuits[a].chi_max != circuits[b].chi_max) return circuits[a].chi_max > circuits[b].chi_max;
+        return cost[a] > cost[b];
+    });
     std::atomic<int> next(0);
     std::vector<std::thread> pool;
     for (int w = 0; w < n_workers; ++w) {
@@ -109,8 +131,9 @@ mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers
             if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
             char* ws = base + per * (size_t)w;
             for (;;) {
-                const int i = next.fetch_add(1);
-                if (i >= n_circuits) break;
+                const int q = next.fetch_add(1);
+                if (q >= n_circuits) break;
+                const int i = order[q];
                 const auto t0 = std::chrono::steady_clock::now();
                 circuits[i].status = stream ? run_one(circuits[i], stream, ws, per) : MPDO_E_DEVICE;
                 const auto t1 = std::chrono::steady_clock::now();
