@@ -556,6 +556,13 @@ struct Engine {
         }
     }
 
+    // Newton-Schulz steps after each range refinement.  A step maps a deviation E = X^H X - I to
+    // about -3/4 E^2, and the refined columns start within ~1e-3 of orthonormal (about
+    // eps lambda_max / lambda_j), so two steps reach the basis check's bar; the two-site update
+    // takes two (an even count also leaves the result in place), and three, or four when an
+    // update is recomputed after a failed check, elsewhere.
+    int ns_iters = 3;
+
     // Newton-Schulz: make the n x q columns of Q (view, dense storage in buffer with ld) orthonormal,
     // X <- X (3/2 I - 1/2 X^H X), alternating between Q and the scratch bW (ld q)
     void ns_orth(T* Q, long ldq, int n, int q, int iters) {
@@ -603,7 +610,7 @@ struct Engine {
                 gemm(q, acc, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(Qn, cc, 1), C0(), V<T>(s.bG, acc, 1));
                 gemm(n, acc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Qn, cc, 1));
             }
-            ns_orth(Qn, cc, n, acc, 3);
+            ns_orth(Qn, cc, n, acc, ns_iters);
             orth_check("orth2", Qn, cc, n, acc, lev, cc);
             gemm(acc, cc, n, C1(), adj(V<T>(Qn, cc, 1)), F, C0(), V<T>(Kb + 2 * (long)q * cc, cc, 1));
             q += acc;
@@ -769,7 +776,7 @@ struct Engine {
                 gemm(kacc, acc, a, C1(), adj(V<T>(Ub, ldu, 1)), V<T>(Vn, ldu, 1), C0(), V<T>(s.bG, acc, 1));
                 gemm(a, acc, kacc, Cr(-1.0), V<T>(Ub, ldu, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Vn, ldu, 1));
             }
-            ns_orth(Vn, ldu, a, acc, 3);
+            ns_orth(Vn, ldu, a, acc, ns_iters);
             orth_check("split", Vn, ldu, a, acc, lev, a);
             kacc += acc;
             if (kacc >= chi || kacc >= a || lev == 2) break;
@@ -1399,9 +1406,11 @@ void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n
         try {
             if (c->fp32) {
                 Engine<float> E(*c, c->sf);
+                E.ns_iters = attempt ? 4 : 2;
                 E.update(i, gf.X ? &gf : nullptr, chi, info);
             } else {
                 Engine<double> E(*c, c->sd);
+                E.ns_iters = attempt ? 4 : 2;
                 E.update(i, gf.X ? &gf : nullptr, chi, info);
             }
             if (info) info->retried = attempt;
