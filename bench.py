@@ -223,7 +223,7 @@ def _saturated(max_warm: int, precisions, cpu_updates: int = 0) -> dict:
     # the other precisions, each loaded with the FP64 state before every timed update
     others = {k: mpdo.MPDO(n, d, chi, precision=v) for k, v in
               (("fp32", mpdo.MPDO_FP32), ("bf16x3", mpdo.MPDO_BF16X3)) if k in precisions}
-    fams = ("theta", "gemm", "tri_reduce", "tri_solve", "tri_back", "eig_small", "phys", "other")
+    fams = ("theta", "gemm", "tri_reduce", "tri_solve", "tri_back", "eig_small", "pchol", "phys", "other")
     cpu = []   # the CPU oracle on the same saturated updates (cpu_updates of them)
     from oracle import channels as och
     okraus = och.gate_kraus_2site(spec.gamma[warm], spec.p_leak, d)
@@ -460,7 +460,7 @@ def roofline_of(prof: dict, fam: str, fp64: bool) -> dict:
         ach = flop / avg_s / 1e12 if avg_s > 0 else 0.0
         rf = {"bound": "alu", "achieved": ach, "peak": PEAK["fp64_vector"], "unit": "TFLOP/s"}
     rf["frac"] = rf["achieved"] / rf["peak"]
-    if fam in ("tri_reduce", "eig_small"):
+    if fam in ("tri_reduce", "eig_small", "pchol"):
         # one workgroup on one of the 256 compute units: its own FP64 ceiling is peak / 256
         rf["workgroups"] = 1
         rf["frac_of_one_cu"] = rf["achieved"] / (rf["peak"] / 256.0)

@@ -313,7 +313,9 @@ enum {
     MPDO_PROF_TRI_BACK = 9,    /* back-transformation of the accepted eigenvectors             */
     MPDO_PROF_THETA = 10,      /* the theta contraction: the merge and gate products that form
                                   theta explicitly (GEMM kernel, timed apart from family 0)    */
-    MPDO_PROF_FAMILIES = 11
+    MPDO_PROF_PCHOL = 11,      /* pivoted Cholesky of a Gram matrix for a range basis (one
+                                  workgroup)                                                   */
+    MPDO_PROF_FAMILIES = 12
 };
 
 /* Measurement switch (instrumentation, not part of the method): with enable = 1 the

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libmpdo.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "batch.hip", "gemm.hip", "eig.hip", "tri.hip", "chol.hip", "kernels.hip", "mlp.hip", "pulse.hip"]
+SOURCES = ["api.hip", "batch.hip", "gemm.hip", "eig.hip", "tri.hip", "chol.hip", "pchol.hip", "kernels.hip", "mlp.hip", "pulse.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

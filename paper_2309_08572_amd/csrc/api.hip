@@ -29,6 +29,7 @@
 #include "common.h"
 #include "chol.h"
 #include "eig.h"
+#include "pchol.h"
 #include "tri.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -124,6 +125,7 @@ struct Scratch {
     void* skw;           // partial tiles of k-split products (GemmOpts::ws)
     size_t skw_bytes;
     double* cholw;       // Cholesky QR: shift and diagonal-block inverses (order <= CHOL_MAX)
+    double* pcw;         // pivoted-Cholesky range bases: Cholesky columns and pivot-block inverse
 
     // k-split workspace: eight n_max^2 complex outputs, capped at 128 MiB
     static size_t split_ws_bytes(int nmax) {
@@ -140,6 +142,7 @@ struct Scratch {
         b += eigh_work_bytes(nmax) + 256;
         b += split_ws_bytes(nmax) + 256;
         b += chol_work_doubles(CHOL_MAX) * sizeof(double) + 256;
+        b += pchol_work_doubles(nmax) * sizeof(double) + 256;
         return b;
     }
     void carve(Arena& a, int n) {
@@ -184,6 +187,7 @@ struct Scratch {
         skw_bytes = split_ws_bytes(n);
         skw = (void*)a.take<char>(skw_bytes);
         cholw = a.take<double>(chol_work_doubles(CHOL_MAX));
+        pcw = a.take<double>(pchol_work_doubles(n));
     }
 };
 
@@ -222,6 +226,14 @@ struct EventProf : public ProfSink {
         (void)hipEventRecord(b, s);
         recs.push_back(Rec{cur, b, fam, flop, bytes});
         cur = nullptr;
+    }
+    void amend(int fam, double flop, double bytes) override {
+        for (auto r = recs.rbegin(); r != recs.rend(); ++r)
+            if (r->fam == fam) {
+                r->flop = flop;
+                r->bytes = bytes;
+                return;
+            }
     }
     // families x (launches, ms, flop, bytes); returns events to the pool
     void collect(double* acc) {
@@ -562,6 +574,9 @@ struct Engine {
     // takes two (an even count also leaves the result in place), and three, or four when an
     // update is recomputed after a failed check, elsewhere.
     int ns_iters = 3;
+    // Range bases by pivoted Cholesky (orth2).  On for the first computation of a two-site
+    // update; a recomputation after a failed basis check takes the Gram eigendecomposition.
+    bool orth_pchol = false;
 
     // Newton-Schulz: make the n x q columns of Q (view, dense storage in buffer with ld) orthonormal,
     // X <- X (3/2 I - 1/2 X^H X), alternating between Q and the scratch bW (ld q)
@@ -586,7 +601,10 @@ struct Engine {
     // Orthonormal basis of range(F) for the n x cc view F, up to three Gram levels: level 0
     // takes the well-conditioned directions (lambda > 1e-10 lambda_max in FP64, 1e-5 in FP32),
     // each further level the residual F - Q Q^H F down to the cutoff or the residual's rounding
-    // floor, so that F = Q K holds to rounding.
+    // floor, so that F = Q K holds to rounding.  With orth_pchol (orders <= PCHOL_MAX) a level
+    // takes the columns of a pivoted Cholesky factorisation of its Gram instead of accepted
+    // eigenvectors: the same contract (F = Q K to rounding, Q orthonormal, checked), at the
+    // cost of the accepted pivots instead of a tridiagonal reduction of order cc.
     // Q: n x q written to Qb (ld cc); K = Q^H F: q x cc written to Kb (ld cc).  Uses bT1.
     int orth2(CView<T> F, int n, int cc, T* Qb, T* Kb) {
         const double e = eps();
@@ -598,14 +616,37 @@ struct Engine {
         double floor2 = 0.0, fro2 = 0.0;
         CView<T> R = F;
         int q = 0;
-        for (int lev = 0; lev < 3; ++lev) {
+        const bool f64 = std::is_same<T, double>::value;
+        const bool pc = orth_pchol && cc <= PCHOL_MAX;
+        // FP32 pivots stop at 1e-5 of a level's trace (the Cholesky QR error grows as eps32 / rel),
+        // so it takes a fourth level to reach the depth three eigen levels reach
+        const int nlev = pc && !f64 ? 4 : 3;
+        for (int lev = 0; lev < nlev; ++lev) {
             gram_cols(R, n, cc);
-            const int acc = lev == 0 ? eig_cut(cc, 0, 0.0, noise_of(cc), tau0, qmax, nullptr, s.inv)
-                                     : eig_cut(cc, lev, floor2, 4096.0 * e, 0.0, qmax - q, nullptr, s.inv);
+            int acc;
+            if (pc) {
+                // pivots while the Schur-complement diagonal exceeds rel * trace: the chosen
+                // columns' squared condition number stays near 1/rel, so the Cholesky QR basis
+                // starts within ~1e-5 (FP64) or ~1e-3 (FP32) of orthonormal.  FP64: 1e-10 at
+                // level 0, 1e-12 on the residual levels, which reach the rounding floor in three
+                // levels; FP32: 1e-5 (level 0: at least the Gram's rounding noise)
+                const double rel = lev == 0 ? std::max(tau0, noise_of(cc)) : (f64 ? 1e-12 : tau0);
+                HIPCHK(pchol_basis<T>(st, s.Gd, cc, cc, lev, lev == 0 ? 0.0 : floor2, rel, lev == 0 ? qmax : qmax - q,
+                                      s.st, s.cnt, s.pcw, s.bVT, cc, ps()));
+                acc = read_int(s.cnt);
+                if (ps()) ps()->amend(PF_PCHOL, pchol_flop(cc, acc), pchol_bytes(cc, acc));
+            } else {
+                acc = lev == 0 ? eig_cut(cc, 0, 0.0, noise_of(cc), tau0, qmax, nullptr, s.inv)
+                               : eig_cut(cc, lev, floor2, 4096.0 * e, 0.0, qmax - q, nullptr, s.inv);
+            }
             if (acc <= 0) break;
-            // new columns R W diag(lambda^-1/2), made orthogonal to the earlier ones
+            // new columns R W (pivoted Cholesky: W = P L11^{-H}; eigenvectors: W diag(lambda^-1/2)),
+            // made orthogonal to the earlier ones
             T* Qn = Qb + 2 * q;
-            gemm_cols(n, acc, cc, R, V<T>(s.bVT, cc, 1), s.inv, V<T>(Qn, cc, 1));
+            if (pc)
+                gemm(n, acc, cc, C1(), R, V<T>(s.bVT, cc, 1), C0(), V<T>(Qn, cc, 1));
+            else
+                gemm_cols(n, acc, cc, R, V<T>(s.bVT, cc, 1), s.inv, V<T>(Qn, cc, 1));
             if (q > 0) {
                 gemm(q, acc, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(Qn, cc, 1), C0(), V<T>(s.bG, acc, 1));
                 gemm(n, acc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bG, acc, 1), C1(), V<T>(Qn, cc, 1));
@@ -614,7 +655,7 @@ struct Engine {
             orth_check("orth2", Qn, cc, n, acc, lev, cc);
             gemm(acc, cc, n, C1(), adj(V<T>(Qn, cc, 1)), F, C0(), V<T>(Kb + 2 * (long)q * cc, cc, 1));
             q += acc;
-            if (q >= qmax || lev == 2) break;
+            if (q >= qmax || lev == nlev - 1) break;
             // residual F - Q K, projected out of range(Q) a second time (its rounding inside
             // range(Q), ~eps sqrt(q) ||F||, would otherwise return as deep-level directions that
             // the projection of the new columns leaves short and nearly dependent); stop once
@@ -1385,6 +1426,12 @@ size_t folded_map(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, in
     return c->fcache.size() - 1;
 }
 
+// MPDO_ORTH_EIG=1 builds every range basis from Gram eigenvectors (no pivoted Cholesky).
+static bool use_pchol() {
+    const char* v = getenv("MPDO_ORTH_EIG");
+    return !(v && atoi(v) != 0);
+}
+
 template <typename T>
 void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n_kraus, int chi,
                mpdo_trunc_info* info) {
@@ -1407,10 +1454,12 @@ void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n
             if (c->fp32) {
                 Engine<float> E(*c, c->sf);
                 E.ns_iters = attempt ? 4 : 2;
+                E.orth_pchol = attempt == 0 && use_pchol();
                 E.update(i, gf.X ? &gf : nullptr, chi, info);
             } else {
                 Engine<double> E(*c, c->sd);
                 E.ns_iters = attempt ? 4 : 2;
+                E.orth_pchol = attempt == 0 && use_pchol();
                 E.update(i, gf.X ? &gf : nullptr, chi, info);
             }
             if (info) info->retried = attempt;

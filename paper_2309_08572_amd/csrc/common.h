@@ -54,12 +54,14 @@ struct cd {
 // Kernel families timed by the profiling sink.
 enum ProfFamily { PF_GEMM = 0, PF_EIG_PAIR = 1, PF_EIG_ROT = 2, PF_EIG_SMALL = 3, PF_PHYS = 4,
                   PF_TRANSFER = 5, PF_OTHER = 6, PF_TRI_REDUCE = 7, PF_TRI_SOLVE = 8, PF_TRI_BACK = 9,
-                  PF_THETA = 10, PF_COUNT = 11 };
+                  PF_THETA = 10, PF_PCHOL = 11, PF_COUNT = 12 };
 
 // Receives begin/end marks around kernel launches when measurement is on (else null).
 struct ProfSink {
     virtual void begin(hipStream_t s, int family) = 0;
     virtual void end(hipStream_t s, int family, double flop, double bytes) = 0;
+    // replaces the work of the last launch recorded for family (once the host knows it)
+    virtual void amend(int family, double flop, double bytes) {}
     virtual ~ProfSink() {}
 };
 
@@ -72,6 +74,9 @@ struct ProfRename : public ProfSink {
     void begin(hipStream_t s, int family) override { to->begin(s, family == from_fam ? to_fam : family); }
     void end(hipStream_t s, int family, double flop, double bytes) override {
         to->end(s, family == from_fam ? to_fam : family, flop, bytes);
+    }
+    void amend(int family, double flop, double bytes) override {
+        to->amend(family == from_fam ? to_fam : family, flop, bytes);
     }
 };
 

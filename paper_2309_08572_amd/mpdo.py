@@ -31,7 +31,7 @@ EXPORTS = (
 )
 
 PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other",
-                 "tri_reduce", "tri_solve", "tri_back", "theta")
+                 "tri_reduce", "tri_solve", "tri_back", "theta", "pchol")
 
 
 class Config(C.Structure):
