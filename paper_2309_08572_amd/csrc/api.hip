@@ -664,6 +664,14 @@ struct Engine {
             gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(Kb, cc, 1), C1(), V<T>(s.bT1, cc, 1));
             gemm(q, cc, n, C1(), adj(V<T>(Qb, cc, 1)), V<T>(s.bT1, cc, 1), C0(), V<T>(s.bW, cc, 1));
             gemm(n, cc, q, Cr(-1.0), V<T>(Qb, cc, 1), V<T>(s.bW, cc, 1), C1(), V<T>(s.bT1, cc, 1));
+            if (pc) {
+                // no read here: the next level's pivots are tested against the floor
+                // 64 eps^2 ||F||_F^2 on the device (level 0 left trace(G) = ||F||_F^2 in st[0]
+                // and st[4]), and a residual below it gives no pivot
+                floor2 = 64.0 * e * e;
+                R = V<T>(s.bT1, cc, 1);
+                continue;
+            }
             HIPCHK(sumsq<T>(st, V<T>(s.bT1, cc, 1), n, cc, s.sums, s.sqp, s.sqc));
             double sums[2], st5[5];
             read_doubles2(s.sums, 2, sums, s.st, 5, st5);
