@@ -1475,7 +1475,8 @@ void do_update(mpdo_ctx c, int i, int kind, const double* in, size_t n_in, int n
             return;
         } catch (const Fail& f) {
             if (!f.retry || attempt > 0) throw;
-            if (getenv("MPDO_DEBUG_CHECKS")) fprintf(stderr, "[mpdo] recomputing update %d: %s\n", i, f.msg.c_str());
+            if (getenv("MPDO_DEBUG_CHECKS") || getenv("MPDO_DEBUG_FAILURES"))
+                fprintf(stderr, "[mpdo] recomputing update %d: %s\n", i, f.msg.c_str());
         }
     }
 }

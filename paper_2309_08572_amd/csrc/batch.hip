@@ -10,6 +10,9 @@
 // together.
 #include <hip/hip_runtime.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -61,7 +64,8 @@ mpdo_status run_one(mpdo_circuit& c, hipStream_t stream, char* ws, size_t ws_byt
     if (st != MPDO_OK) return st;
     st = mpdo_bind_workspace(ctx, ws, ws_bytes);
     if (st == MPDO_OK) st = mpdo_init_product_state(ctx, c.rho0);
-    for (int k = 0; st == MPDO_OK && k < c.n_ops; ++k) {
+    int k = 0;
+    for (; st == MPDO_OK && k < c.n_ops; ++k) {
         const int set = c.op_set[k];
         const double* K = c.kraus + 2 * c.set_offset[set];
         if (c.op_kind[k] == 0)
@@ -69,6 +73,10 @@ mpdo_status run_one(mpdo_circuit& c, hipStream_t stream, char* ws, size_t ws_byt
         else
             st = mpdo_apply_channel(ctx, c.op_site[k], c.set_count[set], K);
     }
+    // MPDO_DEBUG_FAILURES=1: the message of a failed circuit (the context and its message end here)
+    if (st != MPDO_OK && getenv("MPDO_DEBUG_FAILURES"))
+        fprintf(stderr, "[mpdo batch] circuit failed at op %d of %d (site %d): status %d: %s\n", k - 1, c.n_ops,
+                k > 0 ? c.op_site[k - 1] : -1, (int)st, mpdo_last_error(ctx));
     if (st == MPDO_OK && c.n_terms > 0)
         st = mpdo_expect(ctx, c.n_terms, c.term_first, c.term_len, c.term_ops, 1, c.out);
     if (st == MPDO_OK && c.out_trace) st = mpdo_trace(ctx, c.out_trace);

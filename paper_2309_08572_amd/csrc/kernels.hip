@@ -229,19 +229,20 @@ __global__ void sumsq_kernel(CView<T> X, int M, int N, double* __restrict__ out,
         }
         __syncthreads();
     }
+    // The blocks of a launch run on different XCDs, whose L2 caches are not coherent with each
+    // other: the partials, the arrival count and its reset all go through device-scope atomic
+    // accesses, and the arrival orders them (release by every block, acquire by the last).
     if (threadIdx.x == 0) {
-        part_g[2 * blockIdx.x] = part[0];
-        part_g[2 * blockIdx.x + 1] = pbad[0];
-        __threadfence();
-        last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+        __hip_atomic_store(&part_g[2 * blockIdx.x], part[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&part_g[2 * blockIdx.x + 1], pbad[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
-        a += part_g[2 * i];
-        b += part_g[2 * i + 1];
+        a += __hip_atomic_load(&part_g[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b += __hip_atomic_load(&part_g[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     part[threadIdx.x] = a;
     pbad[threadIdx.x] = b;
@@ -256,7 +257,7 @@ __global__ void sumsq_kernel(CView<T> X, int M, int N, double* __restrict__ out,
     if (threadIdx.x == 0) {
         out[0] = part[0];
         out[1] = pbad[0];
-        *cnt = 0u;
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

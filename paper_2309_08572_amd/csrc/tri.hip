@@ -560,6 +560,12 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
         const bool reflect = tr_ != 0.0 || ti_ != 0.0;   // the same in every thread
         double* vc = L.v[j & 1];
         const double* vp = L.v[(j & 1) ^ 1];
+        // p at row j (read by every thread in step j - 1 after its product) is cleared here, a
+        // barrier after those reads and before this step's product accumulates into p
+        if (tid == 0) {
+            L.pabs[2 * j] = 0.0;
+            L.pabs[2 * j + 1] = 0.0;
+        }
         // v (absolute rows: 1 at j + 1, (sr + i si) x below, 0 elsewhere) and reflector row j
         for (int i = tid; i < RMAX; i += RB) {
             double vr, vi;
@@ -614,8 +620,12 @@ __global__ __launch_bounds__(RB) void tri_reduce_reg_kernel(const double* __rest
                 }
                 L.wv[2 * i] = wr;
                 L.wv[2 * i + 1] = wi;
-                L.pabs[2 * i] = 0.0;
-                L.pabs[2 * i + 1] = 0.0;
+                // p is cleared for the next product, except at row j + 1: every thread read
+                // that entry above, and a later wave may not have yet (the next step clears it)
+                if (i != j1) {
+                    L.pabs[2 * i] = 0.0;
+                    L.pabs[2 * i + 1] = 0.0;
+                }
                 if (i >= j1 && i < n) {
                     // v_i conj(w1) + w_i conj(v1)
                     const double cr = vr * w1r + vi * w1i + wr * v1r + wi * v1i;
