@@ -419,9 +419,9 @@ MIN_LAUNCH_US = 50.0
 TRAFFIC = {
     # the timed family is the on-chip reduction of the core splits (orders 33..192; the range
     # bases take the pivoted Cholesky, the gate factorisations are cached after the warm-up):
-    # 486 dispatches, FETCH_SIZE 73.93 KiB, WRITE_SIZE 54.04 KiB
-    "tri_reduce": {"source": "paper_2309_08572_amd/csrc/tri.hip", "sha256_16": "3860c7b61abc2307",
-                   "bytes_per_launch": 206731.0},
+    # 486 dispatches, FETCH_SIZE 73.96 KiB, WRITE_SIZE 54.04 KiB
+    "tri_reduce": {"source": "paper_2309_08572_amd/csrc/tri.hip", "sha256_16": "72a41ec2d3e706d8",
+                   "bytes_per_launch": 206784.0},
     # all pivoted-Cholesky launches of the FP64 command (2486 dispatches over the three order
     # classes): FETCH_SIZE 29.47 KiB, WRITE_SIZE 41.72 KiB per dispatch
     "pchol": {"source": "paper_2309_08572_amd/csrc/pchol.hip", "sha256_16": "fb8cff16ca15d597",

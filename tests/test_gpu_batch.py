@@ -81,3 +81,33 @@ def test_batch_of_m2_circuits_matches_oracle_and_single_runs():
             np.testing.assert_allclose(s["populations"], g["populations"], rtol=0, atol=1e-10)
             assert m.bond_dims() == r["bonds"], c
             m.close()
+
+
+def test_batch_on_sixteen_streams_reproduces_single_runs():
+    """96 truncating circuits (N=16, d=4, chi=64, p=3, rates log-uniform in [1e-4, 1e-2]) on 16
+    worker streams, whose kernels share compute units, against the same circuits run one at a
+    time.  The tridiagonal reduction once cleared an entry of p that other waves of its
+    workgroup still had to read; alone on a compute unit the waves read it in time, next to
+    other streams' kernels some did not, and the batch returned wrong bases (caught by the
+    basis check, then recomputed) or failed circuits.  Every circuit must succeed and match
+    its single run to 1e-10 on the per-site energy and the populations (the eigensolver's LDS
+    sums are not bitwise reproducible, so equality is to rounding)."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08572_amd import circuits, mpdo
+    specs = [random_spec(seed=100 + s, n=16, d=4, p=3, chi=64) for s in range(96)]
+    print("[gpu] batch of 96 truncating circuits on 16 streams", flush=True)
+    res = mpdo.run_batch([circuits.describe(s) for s in specs], n_workers=16)
+    worst = 0.0
+    for spec, r in zip(specs, res):
+        assert r["status"] == 0, spec
+        g = circuits.summarize(r["values"], spec.n, spec.d)
+        m = circuits.run_circuit(spec)
+        o = circuits.observables(m)
+        m.close()
+        de = abs(g["energy_per_site"] - o["energy_per_site"])
+        dp = float(np.max(np.abs(g["populations"] - o["populations"])))
+        worst = max(worst, de, dp)
+        assert de <= 1e-10 and dp <= 1e-10, (spec.seed, de, dp)
+    print(f"[gpu] largest difference batch vs single {worst:.2e}", flush=True)
