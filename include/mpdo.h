@@ -301,7 +301,8 @@ mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers
 
 /* Kernel families reported by mpdo_profile_read, in this order. */
 enum {
-    MPDO_PROF_GEMM = 0,        /* complex matrix-core GEMM (theta, Gram, projections, rebuild) */
+    MPDO_PROF_GEMM = 0,        /* complex matrix-core GEMM (theta, Gram, projections, rebuild);
+                                  timed by the kernel's own start and end stamps            */
     MPDO_PROF_EIG_PAIR = 1,    /* Jacobi: 32 x 32 pair eigenproblems in LDS                    */
     MPDO_PROF_EIG_ROTATE = 2,  /* Jacobi: pair rotations applied to block rows and columns     */
     MPDO_PROF_EIG_SMALL = 3,   /* Jacobi: whole matrix of order <= 64 in one workgroup         */
@@ -315,12 +316,17 @@ enum {
                                   theta explicitly (GEMM kernel, timed apart from family 0)    */
     MPDO_PROF_PCHOL = 11,      /* pivoted Cholesky of a Gram matrix for a range basis (one
                                   workgroup)                                                   */
-    MPDO_PROF_FAMILIES = 12
+    MPDO_PROF_SPLIT_SUM = 12,  /* the k-split GEMMs' partial sums, added in chunk order (own
+                                  start and end stamps like family 0)                          */
+    MPDO_PROF_FAMILIES = 13
 };
 
 /* Measurement switch (instrumentation, not part of the method): with enable = 1 the
  * context records a HIP event pair around every launch of the families above on its
- * stream and clears earlier totals; enable = 0 stops recording (totals are kept). */
+ * stream and clears earlier totals; enable = 0 stops recording (totals are kept).  For the
+ * GEMM families (0, 10, 12) the pair is attached to the kernel itself (hipExtLaunchKernelGGL),
+ * so their milliseconds are kernel execution time; for the others a pair brackets the
+ * family's launches and also holds their dispatch. */
 mpdo_status mpdo_profile_enable(mpdo_ctx ctx, int enable);
 
 /* As mpdo_profile_enable(ctx, 1), recording only the families whose bit (1u << f) is set in
@@ -328,6 +334,14 @@ mpdo_status mpdo_profile_enable(mpdo_ctx ctx, int enable);
  * one family's kernels leaves the rest of the stream as it runs unmeasured.  family_mask = 0
  * stops recording. */
 mpdo_status mpdo_profile_enable_mask(mpdo_ctx ctx, unsigned family_mask);
+
+/* Sampling of the stamped families (0, 10, 12) while recording: only every stride-th launch
+ * of each is stamped and counted (the first of each family since this call), so a measurement
+ * of the many short product kernels costs the stream little; the totals then hold the sampled
+ * launches, whose average stands for the family's.  stride = 1 stamps every launch (the
+ * default of each mpdo_profile_enable / _mask call).  E_ARG for stride < 1; no effect while
+ * nothing is recorded. */
+mpdo_status mpdo_profile_stride(mpdo_ctx ctx, int stride);
 
 /* Totals since the last mpdo_profile_enable(ctx, 1): out[4 f + 0..3] = launches,
  * milliseconds, algorithmic flop and algorithmic bytes of family f, for f < n_families.

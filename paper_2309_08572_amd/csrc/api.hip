@@ -203,6 +203,8 @@ struct EventProf : public ProfSink {
     hipEvent_t cur = nullptr;
     int cur_fam = -1;
     unsigned mask = ~0u;   // families recorded (bit f)
+    unsigned stride = 1;   // stamped kernels: one launch in `stride` of each family recorded
+    unsigned long seen[PF_COUNT] = {0};
     hipEvent_t get() {
         if (!pool.empty()) {
             hipEvent_t e = pool.back();
@@ -226,6 +228,19 @@ struct EventProf : public ProfSink {
         (void)hipEventRecord(b, s);
         recs.push_back(Rec{cur, b, fam, flop, bytes});
         cur = nullptr;
+    }
+    bool kernel_events(int fam, hipEvent_t* a, hipEvent_t* b) override {
+        if (!((mask >> fam) & 1u)) return false;
+        if (seen[fam]++ % stride != 0) return false;
+        *a = get();
+        *b = get();
+        if (*a && *b) return true;
+        if (*a) pool.push_back(*a);
+        if (*b) pool.push_back(*b);
+        return false;
+    }
+    void kernel_done(int fam, hipEvent_t a, hipEvent_t b, double flop, double bytes) override {
+        recs.push_back(Rec{a, b, fam, flop, bytes});
     }
     void amend(int fam, double flop, double bytes) override {
         for (auto r = recs.rbegin(); r != recs.rend(); ++r)
@@ -2431,6 +2446,16 @@ mpdo_status mpdo_profile_enable_mask(mpdo_ctx c, unsigned family_mask) {
         p->mask = family_mask;
         c->prof.reset(p);
         for (double& x : c->prof_acc) x = 0.0;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_profile_stride(mpdo_ctx c, int stride) {
+    if (!c || stride < 1) return MPDO_E_ARG;
+    if (c->prof) {
+        EventProf* p = static_cast<EventProf*>(c->prof.get());
+        p->stride = (unsigned)stride;
+        for (auto& x : p->seen) x = 0;
     }
     return MPDO_OK;
 }

@@ -54,7 +54,7 @@ struct cd {
 // Kernel families timed by the profiling sink.
 enum ProfFamily { PF_GEMM = 0, PF_EIG_PAIR = 1, PF_EIG_ROT = 2, PF_EIG_SMALL = 3, PF_PHYS = 4,
                   PF_TRANSFER = 5, PF_OTHER = 6, PF_TRI_REDUCE = 7, PF_TRI_SOLVE = 8, PF_TRI_BACK = 9,
-                  PF_THETA = 10, PF_PCHOL = 11, PF_COUNT = 12 };
+                  PF_THETA = 10, PF_PCHOL = 11, PF_SPLIT_SUM = 12, PF_COUNT = 13 };
 
 // Receives begin/end marks around kernel launches when measurement is on (else null).
 struct ProfSink {
@@ -62,6 +62,11 @@ struct ProfSink {
     virtual void end(hipStream_t s, int family, double flop, double bytes) = 0;
     // replaces the work of the last launch recorded for family (once the host knows it)
     virtual void amend(int family, double flop, double bytes) {}
+    // An event pair for one kernel that the caller launches with hipExtLaunchKernelGGL, which
+    // stamps the kernel's own start and end (no dispatch time in between); false when the
+    // family is not recorded.  kernel_done records the pair with the launch's work.
+    virtual bool kernel_events(int family, hipEvent_t* a, hipEvent_t* b) { return false; }
+    virtual void kernel_done(int family, hipEvent_t a, hipEvent_t b, double flop, double bytes) {}
     virtual ~ProfSink() {}
 };
 
@@ -77,6 +82,12 @@ struct ProfRename : public ProfSink {
     }
     void amend(int family, double flop, double bytes) override {
         to->amend(family == from_fam ? to_fam : family, flop, bytes);
+    }
+    bool kernel_events(int family, hipEvent_t* a, hipEvent_t* b) override {
+        return to->kernel_events(family == from_fam ? to_fam : family, a, b);
+    }
+    void kernel_done(int family, hipEvent_t a, hipEvent_t b, double flop, double bytes) override {
+        to->kernel_done(family == from_fam ? to_fam : family, a, b, flop, bytes);
     }
 };
 

@@ -23,6 +23,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -902,41 +904,61 @@ hipError_t cgemm_launch(hipStream_t s, int M, int N, int K, cd alpha, CView<T> A
         fprintf(stderr, "[mpdo gemm] %s M %d N %d K %d batch %d tile %dx%d ksplit %d chunk %d%s\n",
                 sizeof(T) == 8 ? "f64" : (opt.split_bf16 ? "bf16x3" : "f32"), M, N, K, batch, bm, bn, g.ksplit, g.kchunk,
                 g.bshift || g.bcol ? " transforms" : "");
-    if (prof) prof->begin(s, PF_GEMM);
+    // With a profiling sink the kernel is launched with an event pair attached to it
+    // (hipExtLaunchKernelGGL stamps the kernel's own start and end), so the recorded time is
+    // kernel execution alone, as for the k-split sums that follow.
+    hipEvent_t ka = nullptr, kb = nullptr;
+    const bool timed = prof && prof->kernel_events(PF_GEMM, &ka, &kb);
+#define MPDO_GEMM_GO(K)                                                                 \
+    do {                                                                                \
+        if (timed)                                                                      \
+            hipExtLaunchKernelGGL(K, grid, dim3(256), 0, s, ka, kb, 0u, g);              \
+        else                                                                            \
+            hipLaunchKernelGGL(K, grid, dim3(256), 0, s, g);                            \
+    } while (0)
     const bool tf = g.bshift || g.bcol;
     bool big = false;   // the large-tile kernels (plan.wm = 4, plain operands)
     if constexpr (std::is_same<T, float>::value) {
         big = !tf && plan.wm == 4;
-        if (big && opt.split_bf16) hipLaunchKernelGGL(cgemm_x3_kernel, grid, dim3(256), 0, s, g);
-        else if (big) hipLaunchKernelGGL(cgemm_f32_big_kernel, grid, dim3(256), 0, s, g);
+        if (big && opt.split_bf16) MPDO_GEMM_GO(cgemm_x3_kernel);
+        else if (big) MPDO_GEMM_GO(cgemm_f32_big_kernel);
     } else {
         big = !tf && plan.wm == 4;
-        if (big) hipLaunchKernelGGL(cgemm_f64_big_kernel, grid, dim3(256), 0, s, g);
+        if (big) MPDO_GEMM_GO(cgemm_f64_big_kernel);
     }
     if (big) {
     } else if (plan.wm == 2) {
         if (tf)
-            hipLaunchKernelGGL((cgemm_kernel<T, 2, 1>), grid, dim3(256), 0, s, g);
+            MPDO_GEMM_GO((cgemm_kernel<T, 2, 1>));
         else
-            hipLaunchKernelGGL((cgemm_kernel<T, 2, 0>), grid, dim3(256), 0, s, g);
+            MPDO_GEMM_GO((cgemm_kernel<T, 2, 0>));
     } else {
         if (tf)
-            hipLaunchKernelGGL((cgemm_kernel<T, 1, 1>), grid, dim3(256), 0, s, g);
+            MPDO_GEMM_GO((cgemm_kernel<T, 1, 1>));
         else
-            hipLaunchKernelGGL((cgemm_kernel<T, 1, 0>), grid, dim3(256), 0, s, g);
+            MPDO_GEMM_GO((cgemm_kernel<T, 1, 0>));
     }
+#undef MPDO_GEMM_GO
+    // algorithmic: 8 flop per complex multiply-add; A, B read and C written once (and read
+    // when beta != 0)
+    const double flop = 8.0 * M * (double)N * K * batch;
+    const double bytes = 2.0 * sizeof(T) * batch *
+                         ((double)M * K + (double)K * N + (double)M * N * ((beta.re != 0 || beta.im != 0) ? 2 : 1));
+    if (timed) prof->kernel_done(PF_GEMM, ka, kb, flop, bytes);
     if (g.part) {
         const long tot = (long)M * N * batch;
-        hipLaunchKernelGGL(csplit_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g.part,
-                           g.ksplit, batch, M, N, C, sC, beta.re, beta.im);
-    }
-    if (prof) {
-        // algorithmic: 8 flop per complex multiply-add; A, B read and C written once (and read
-        // when beta != 0)
-        const double flop = 8.0 * M * (double)N * K * batch;
-        const double bytes = 2.0 * sizeof(T) * batch *
-                             ((double)M * K + (double)K * N + (double)M * N * ((beta.re != 0 || beta.im != 0) ? 2 : 1));
-        prof->end(s, PF_GEMM, flop, bytes);
+        const dim3 rg((unsigned)((tot + 255) / 256));
+        hipEvent_t ra = nullptr, rb = nullptr;
+        if (prof && prof->kernel_events(PF_SPLIT_SUM, &ra, &rb)) {
+            hipExtLaunchKernelGGL(csplit_reduce_kernel<T>, rg, dim3(256), 0, s, ra, rb, 0u, (const T*)g.part, g.ksplit,
+                                  batch, M, N, C, sC, beta.re, beta.im);
+            // the partials read once, C written (and read when beta != 0)
+            prof->kernel_done(PF_SPLIT_SUM, ra, rb, 2.0 * tot * g.ksplit,
+                              2.0 * sizeof(T) * tot * (g.ksplit + ((beta.re != 0 || beta.im != 0) ? 2 : 1)));
+        } else {
+            hipLaunchKernelGGL(csplit_reduce_kernel<T>, rg, dim3(256), 0, s, (const T*)g.part, g.ksplit, batch, M, N, C,
+                               sC, beta.re, beta.im);
+        }
     }
     return hipGetLastError();
 }

@@ -26,12 +26,12 @@ EXPORTS = (
     "mpdo_init_product_state", "mpdo_apply_gate", "mpdo_apply_gate_kraus", "mpdo_apply_gate_crosstalk",
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_expect2", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_set_state", "mpdo_canonical_centre", "mpdo_move_centre", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
-    "mpdo_profile_enable", "mpdo_profile_enable_mask", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
+    "mpdo_profile_enable", "mpdo_profile_enable_mask", "mpdo_profile_stride", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
     "mpdo_cgemm",
 )
 
 PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other",
-                 "tri_reduce", "tri_solve", "tri_back", "theta", "pchol")
+                 "tri_reduce", "tri_solve", "tri_back", "theta", "pchol", "split_sum")
 
 
 class Config(C.Structure):
@@ -115,6 +115,7 @@ def load_library() -> C.CDLL:
     lib.mpdo_version.restype = C.c_char_p
     lib.mpdo_profile_enable.argtypes = [ctx, C.c_int]
     lib.mpdo_profile_enable_mask.argtypes = [ctx, C.c_uint]
+    lib.mpdo_profile_stride.argtypes = [ctx, C.c_int]
     lib.mpdo_batch_workspace_bytes.argtypes = [C.POINTER(Circuit), C.c_int]
     lib.mpdo_batch_workspace_bytes.restype = C.c_size_t
     lib.mpdo_run_batch.argtypes = [C.POINTER(Circuit), C.c_int, C.c_int, C.c_void_p, C.c_size_t]
@@ -296,6 +297,10 @@ class MPDO:
         for nm in names:
             mask |= 1 << PROF_FAMILIES.index(nm)
         self._check(self.lib.mpdo_profile_enable_mask(self.ctx, mask))
+
+    def profile_stride(self, stride: int):
+        """Stamp only every stride-th launch of the GEMM families while recording."""
+        self._check(self.lib.mpdo_profile_stride(self.ctx, int(stride)))
 
     def profile_read(self) -> dict:
         nf = len(PROF_FAMILIES)

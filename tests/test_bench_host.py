@@ -26,14 +26,18 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert res.stdout.strip() == ""
 
 
-def test_roofline_family_prefers_long_launches():
-    prof = {"gemm": _fam(20000, 200.0), "tri_reduce": _fam(700, 300.0), "other": _fam(5000, 40.0),
+def test_roofline_family_prefers_long_or_stamped_launches():
+    prof = {"pchol": _fam(20000, 200.0), "tri_reduce": _fam(700, 150.0), "other": _fam(5000, 40.0),
             "tri_back": _fam(700, 50.0)}
-    # gemm averages 10 us per launch (below the long-launch limit), so tri_reduce wins
+    # pchol averages 10 us per launch (below the long-launch limit for a bracketed family), so
+    # tri_reduce wins
     assert bench.roofline_family(prof) == "tri_reduce"
-    # with no long-launch family the largest total wins
-    short = {"gemm": _fam(20000, 200.0), "other": _fam(5000, 40.0)}
-    assert bench.roofline_family(short) == "gemm"
+    # the GEMM kernels carry their own stamps: a short average is still kernel time
+    stamped = dict(prof, gemm=_fam(20000, 180.0))
+    assert bench.roofline_family(stamped) == "gemm"
+    # with no eligible family the largest total wins
+    short = {"pchol": _fam(20000, 200.0), "other": _fam(5000, 40.0)}
+    assert bench.roofline_family(short) == "pchol"
 
 
 def test_roofline_record_fields_and_fraction():
@@ -60,7 +64,7 @@ def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch)
     assert bench._traffic("tri_reduce") == entry["bytes_per_launch"]
     monkeypatch.setitem(bench.TRAFFIC, "tri_reduce", dict(entry, sha256_16="0" * 16))
     assert bench._traffic("tri_reduce") is None
-    assert bench._traffic("gemm") is None
+    assert bench._traffic("eig_small") is None    # no entry: never measured
 
 
 def test_truncation_summary():
