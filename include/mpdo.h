@@ -351,6 +351,24 @@ mpdo_status mpdo_profile_read(mpdo_ctx ctx, double* out, int n_families);
 /* Block until all work of the context has finished. */
 mpdo_status mpdo_synchronize(mpdo_ctx ctx);
 
+/* The FP64 Hermitian eigensolver that replaces the SVD in the split of Sec. III.A (the
+ * spectrum is cut to the largest Schmidt values, Sec. III.A and III.D), on a host matrix, so
+ * that tests can check it element by element here: the eigenpairs of the Hermitian part of H
+ * that one deflation level of the update accepts, i.e. the largest eigenvalues above
+ * tau * lambda_max (and above 0), at most cap of them, through the update's own kernels and
+ * order dispatch: one-workgroup Jacobi for n <= 32; for 33 <= n <= 1024 the Householder
+ * tridiagonal reduction, multisection for the accepted eigenvalues, inverse iteration with
+ * Gram-Schmidt inside clusters closer than 1e-12 ||T|| and the back-transformation.
+ * H: host complex128 n x n, row-major, interleaved (re, im), read only.  Outputs: *m = the
+ * accepted count; evals[0..m) descending; V: host complex128 n x cap, row-major, whose columns
+ * 0..m) receive the unit eigenvectors (the other columns are left as they are).  Eigenvectors
+ * are unique up to a phase (and within a subspace of equal eigenvalues).  Synchronous on the
+ * null stream of the current device; allocates and frees its device buffers.  E_ARG for
+ * n < 1 or n > 1024, cap < 0 or cap > n, tau < 0 or NaN, or a null pointer; E_NOMEM /
+ * E_DEVICE for a failed allocation or HIP call; E_NUMERIC if Jacobi does not converge
+ * (message: mpdo_last_error(NULL)). */
+mpdo_status mpdo_eigh(int n, const double* H, double tau, int cap, int* m, double* evals, double* V);
+
 /* C = alpha op(A) op(B) + beta C on the library's matrix-core product kernels: every
  * contraction of the update (the merge and gate of Sec. III.A, Fig. 2(c); the Gram products
  * and rebuilds that replace the SVD) runs through them, and tests check them element by

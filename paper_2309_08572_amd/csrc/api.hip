@@ -1894,6 +1894,69 @@ void run_cgemm(bool x3, int M, int N, int K, const double* alpha, const double* 
     for (size_t i = 0; i < t.size(); ++i) C[i] = (double)t[i];
 }
 
+// The split's eigensolver on a host matrix (mpdo_eigh): the order dispatch of Engine::eig_cut
+// for orders up to TRI_MAX, on the null stream, with device buffers of its own.
+void run_eigh(int n, const double* H, double tau, int cap, int* m, double* evals, double* V) {
+    struct Buf {
+        void* p = nullptr;
+        ~Buf() {
+            if (p) (void)hipFree(p);
+        }
+    } dH, dV, dl, dst, dcnt, dw;
+    struct Pinned {
+        int* p = nullptr;
+        ~Pinned() {
+            if (p) (void)hipHostFree(p);
+        }
+    } hint;
+    const size_t n2 = (size_t)n * n;
+    auto alloc = [](Buf& b, size_t bytes) {
+        if (hipMalloc(&b.p, std::max(bytes, (size_t)256)) != hipSuccess) throw Fail{MPDO_E_NOMEM, "device allocation failed"};
+    };
+    alloc(dH, n2 * 2 * sizeof(double));
+    alloc(dV, n2 * 2 * sizeof(double));
+    alloc(dl, (size_t)n * sizeof(double));
+    alloc(dst, 64 * sizeof(double));
+    alloc(dcnt, 64 * sizeof(int));
+    alloc(dw, std::max(eigh_work_bytes(n), tri_work_bytes(n)));
+    if (hipHostMalloc((void**)&hint.p, 4 * sizeof(int)) != hipSuccess) throw Fail{MPDO_E_NOMEM, "pinned allocation failed"};
+    if (hipMemcpy(dH.p, H, n2 * 2 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(dst.p, 0, 64 * sizeof(double)) != hipSuccess || hipMemset(dcnt.p, 0, 64 * sizeof(int)) != hipSuccess)
+        throw Fail{MPDO_E_DEVICE, "copy to the device failed"};
+    double* Hd = (double*)dH.p;
+    double* Vd = (double*)dV.p;
+    double* lam = (double*)dl.p;
+    double* st = (double*)dst.p;
+    int* cnt = (int*)dcnt.p;
+    if (n <= EIG_JACOBI_MAX) {
+        int sw = 0;
+        if (eigh(0, n, Hd, n, Vd, n, lam, dw.p, EIG_MAX_SWEEPS, &sw, hint.p) != hipSuccess)
+            throw Fail{MPDO_E_DEVICE, "eigensolver launch failed"};
+        if (sw >= EIG_MAX_SWEEPS) throw Fail{MPDO_E_NUMERIC, "Jacobi eigensolver did not converge"};
+        if (spectrum_cut(0, lam, n, 0, 0.0, 0.0, tau, cap, st, cnt, nullptr, nullptr) != hipSuccess)
+            throw Fail{MPDO_E_DEVICE, "spectrum cut launch failed"};
+    } else {
+        if (eigh_top(0, n, Hd, n, 0, 0.0, 0.0, tau, cap, st, cnt, lam, nullptr, nullptr, Vd, n, dw.p) != hipSuccess)
+            throw Fail{MPDO_E_DEVICE, "eigensolver launch failed"};
+    }
+    if (hipDeviceSynchronize() != hipSuccess) throw Fail{MPDO_E_DEVICE, "eigensolver failed"};
+    int acc = 0;
+    if (hipMemcpy(&acc, cnt, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        throw Fail{MPDO_E_DEVICE, "copy to the host failed"};
+    if (acc < 0 || acc > cap) throw Fail{MPDO_E_NUMERIC, "accepted count out of range"};
+    *m = acc;
+    if (acc == 0) return;
+    std::vector<double> v(n2 * 2);
+    if (hipMemcpy(evals, lam, (size_t)acc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(v.data(), Vd, n2 * 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        throw Fail{MPDO_E_DEVICE, "copy to the host failed"};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < acc; ++j) {
+            V[2 * ((size_t)i * cap + j)] = v[2 * ((size_t)i * n + j)];
+            V[2 * ((size_t)i * cap + j) + 1] = v[2 * ((size_t)i * n + j) + 1];
+        }
+}
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -2481,6 +2544,22 @@ mpdo_status mpdo_cgemm(int precision, int M, int N, int K, const double* alpha, 
     try {
         if (precision == MPDO_FP64) run_cgemm<double>(false, M, N, K, alpha, A, op_a, B, op_b, beta, C, split_k);
         else run_cgemm<float>(precision == MPDO_BF16X3, M, N, K, alpha, A, op_a, B, op_b, beta, C, split_k);
+    } catch (const Fail& f) {
+        g_create_err = f.msg;
+        return f.st;
+    }
+    return MPDO_OK;
+}
+
+mpdo_status mpdo_eigh(int n, const double* H, double tau, int cap, int* m, double* evals, double* V) {
+    if (n < 1 || n > TRI_MAX || cap < 0 || cap > n || !(tau >= 0.0) || !H || !m || !evals || (cap > 0 && !V)) {
+        g_create_err = "bad eigensolver arguments";
+        return MPDO_E_ARG;
+    }
+    *m = 0;
+    if (cap == 0) return MPDO_OK;
+    try {
+        run_eigh(n, H, tau, cap, m, evals, V);
     } catch (const Fail& f) {
         g_create_err = f.msg;
         return f.st;

@@ -27,7 +27,7 @@ EXPORTS = (
     "mpdo_apply_channel", "mpdo_truncate", "mpdo_expect", "mpdo_expect2", "mpdo_trace", "mpdo_bond_dims",
     "mpdo_get_site", "mpdo_set_state", "mpdo_canonical_centre", "mpdo_move_centre", "mpdo_synchronize", "mpdo_last_error", "mpdo_version",
     "mpdo_profile_enable", "mpdo_profile_enable_mask", "mpdo_profile_stride", "mpdo_profile_read", "mpdo_batch_workspace_bytes", "mpdo_run_batch",
-    "mpdo_cgemm",
+    "mpdo_cgemm", "mpdo_eigh",
 )
 
 PROF_FAMILIES = ("gemm", "eig_pair", "eig_rotate", "eig_small", "phys", "transfer", "other",
@@ -121,6 +121,7 @@ def load_library() -> C.CDLL:
     lib.mpdo_run_batch.argtypes = [C.POINTER(Circuit), C.c_int, C.c_int, C.c_void_p, C.c_size_t]
     lib.mpdo_profile_read.argtypes = [ctx, dp, C.c_int]
     lib.mpdo_cgemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_int, dp, dp, C.c_int]
+    lib.mpdo_eigh.argtypes = [C.c_int, dp, C.c_double, C.c_int, ip, dp, dp]
     for name in EXPORTS:
         if name not in ("mpdo_workspace_bytes", "mpdo_last_error", "mpdo_version",
                         "mpdo_batch_workspace_bytes"):
@@ -337,6 +338,27 @@ def cgemm(precision: int, A, B, op_a: int = 0, op_b: int = 0, alpha=1.0, beta=0.
     if st != 0:
         raise MpdoError(st, lib.mpdo_last_error(None).decode())
     return Cm
+
+
+def eigh(H, tau: float = 0.0, cap: Optional[int] = None, device: int = 0):
+    """The update's FP64 eigensolver on a host Hermitian matrix (mpdo_eigh): the eigenpairs
+    above tau * lambda_max, at most cap, largest first -> (evals (m,), V (n, m))."""
+    import torch
+    lib = load_library()
+    torch.cuda.set_device(device)
+    H = _cplx(H)
+    n = H.shape[0]
+    if H.shape != (n, n):
+        raise ValueError("H must be square")
+    cap = n if cap is None else int(cap)
+    m = np.zeros(1, dtype=np.int32)
+    ev = np.zeros(max(cap, 1))
+    V = np.zeros((n, max(cap, 1)), dtype=np.complex128)
+    st = lib.mpdo_eigh(n, _dptr(H), float(tau), cap, m.ctypes.data_as(C.POINTER(C.c_int)), _dptr(ev), _dptr(V))
+    if st != 0:
+        raise MpdoError(st, lib.mpdo_last_error(None).decode())
+    k = int(m[0])
+    return ev[:k].copy(), V[:, :k].copy()
 
 
 def run_batch(descs, n_workers: int = 8, device: int = 0):
