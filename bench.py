@@ -515,9 +515,9 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3", "both"], default="both")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-circuits", type=int, default=32,
+    ap.add_argument("--batch-circuits", type=int, default=256,
                     help="also time this many circuits of the 256-circuit batch workload "
-                         "(one per worker stream vs one at a time)")
+                         "(on worker streams vs one at a time; all 256 take about a minute)")
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--saturated-layers", type=int, default=8,
                     help="at most this many untimed layers before the saturated chi=512 updates are timed "
