@@ -2516,9 +2516,8 @@ mpdo_status mpdo_profile_enable_mask(mpdo_ctx c, unsigned family_mask) {
 mpdo_status mpdo_profile_stride(mpdo_ctx c, int stride) {
     if (!c || stride < 1) return MPDO_E_ARG;
     if (c->prof) {
-        EventProf* p = static_cast<EventProf*>(c->prof.get());
-        p->stride = (unsigned)stride;
-        for (auto& x : p->seen) x = 0;
+        c->prof->stride = (unsigned)stride;
+        for (auto& x : c->prof->seen) x = 0;
     }
     return MPDO_OK;
 }
