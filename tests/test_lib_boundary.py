@@ -122,3 +122,31 @@ def test_product_kraus_inputs_are_channels():
             np.testing.assert_allclose(sum(k.conj().T @ k for k in ks), np.eye(dim), atol=1e-14)
     assert pc.bond_order(6) == [0, 2, 4, 3, 1]
     assert pc.bond_order(7) == [0, 2, 4, 5, 3, 1]
+
+
+def test_eigh_and_profile_stride_argument_checks_without_gpu(lib):
+    """mpdo_eigh and mpdo_profile_stride refuse bad arguments before any device work."""
+    from paper_2309_08572_amd.mpdo import Config
+    dp = C.POINTER(C.c_double)
+    H = np.eye(2, dtype=np.complex128)
+    ev = np.zeros(2)
+    V = np.zeros((2, 2), dtype=np.complex128)
+    m = C.c_int(-1)
+
+    def eigh(n, tau, cap):
+        return lib.mpdo_eigh(n, H.ctypes.data_as(dp), tau, cap, C.byref(m), ev.ctypes.data_as(dp),
+                             V.ctypes.data_as(dp))
+    for n, tau, cap in [(0, 0.0, 0), (1025, 0.0, 1), (2, -1.0, 2), (2, float("nan"), 2), (2, 0.0, 3),
+                        (2, 0.0, -1)]:
+        assert eigh(n, tau, cap) == 1, (n, tau, cap)
+        assert lib.mpdo_last_error(None)
+    assert eigh(2, 0.0, 0) == 0 and m.value == 0          # nothing asked for: no device work
+    ctx = C.c_void_p()
+    good = Config(6, 3, 81, 0, 0.0, 1, 0, None)
+    assert lib.mpdo_create(C.byref(good), C.byref(ctx)) == 0
+    assert lib.mpdo_profile_stride(ctx, 0) == 1
+    assert lib.mpdo_profile_stride(ctx, 4) == 0             # not recording: no effect
+    assert lib.mpdo_profile_enable_mask(ctx, 1) == 0
+    assert lib.mpdo_profile_stride(ctx, 4) == 0
+    assert lib.mpdo_profile_enable_mask(ctx, 0) == 0
+    assert lib.mpdo_destroy(ctx) == 0
