@@ -292,10 +292,13 @@ size_t mpdo_batch_workspace_bytes(const mpdo_circuit* circuits, int n_circuits);
 /* Run n_circuits circuits on n_workers host threads, each with its own HIP stream and
  * context (default stream priority), taking circuits from a shared queue ordered by bond cap
  * and then by estimated cost (two-site updates x chi_max^3), largest first; the kernels of
- * different circuits overlap on the GPU.  device_workspace: NULL (the library allocates
- * n_workers * mpdo_batch_workspace_bytes with hipMalloc) or a caller buffer of at least
- * that size.  Per-circuit failures are reported in circuits[i].status; the call returns
- * MPDO_E_ARG for bad arguments and otherwise the first failing circuit's status. */
+ * different circuits overlap on the GPU.  The smallest circuit runs first, alone, in the
+ * calling thread, so that the library's first use in a process is not made by many threads
+ * at once.  device_workspace: NULL (the library allocates n_workers *
+ * mpdo_batch_workspace_bytes with hipMalloc) or a caller buffer of at least that size.
+ * Per-circuit failures are reported in circuits[i].status; the call returns MPDO_E_ARG for
+ * bad arguments and otherwise the first failing circuit's status, with the message of the
+ * first failure in mpdo_last_error(NULL) ("circuit i: ..."). */
 mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers, void* device_workspace,
                            size_t workspace_bytes);
 

@@ -368,6 +368,12 @@ struct mpdo_ctx_s {
 
 static thread_local std::string g_create_err;
 
+namespace mpdo {
+// Sets the calling thread's context-free message (mpdo_last_error(NULL)); the batch runner
+// passes a worker's failure on to the thread that called it.
+void set_thread_error(const std::string& msg) { g_create_err = msg; }
+}  // namespace mpdo
+
 namespace {
 
 // ====================================================================== generic helpers

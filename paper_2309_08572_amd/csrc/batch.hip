@@ -16,11 +16,17 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <string.h>
+#include <string>
 #include <thread>
 #include <vector>
 
 #include "../../include/mpdo.h"
+
+namespace mpdo {
+void set_thread_error(const std::string& msg);
+}
 
 namespace {
 
@@ -57,11 +63,25 @@ double cost_of(const mpdo_circuit& c) {
     return (double)two * chi * chi * chi;
 }
 
-mpdo_status run_one(mpdo_circuit& c, hipStream_t stream, char* ws, size_t ws_bytes) {
+// The first failure of a batch and its message (passed to the calling thread's
+// mpdo_last_error(NULL) when the batch returns).
+struct FirstError {
+    std::mutex mu;
+    std::string msg;
+    void note(int circuit, const char* what) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (msg.empty()) msg = "circuit " + std::to_string(circuit) + ": " + (what ? what : "");
+    }
+};
+
+mpdo_status run_one(mpdo_circuit& c, hipStream_t stream, char* ws, size_t ws_bytes, int index, FirstError& fe) {
     mpdo_config cfg = config_of(c, (void*)stream);
     mpdo_ctx ctx = nullptr;
     mpdo_status st = mpdo_create(&cfg, &ctx);
-    if (st != MPDO_OK) return st;
+    if (st != MPDO_OK) {
+        fe.note(index, mpdo_last_error(nullptr));
+        return st;
+    }
     st = mpdo_bind_workspace(ctx, ws, ws_bytes);
     if (st == MPDO_OK) st = mpdo_init_product_state(ctx, c.rho0);
     int k = 0;
@@ -81,6 +101,7 @@ mpdo_status run_one(mpdo_circuit& c, hipStream_t stream, char* ws, size_t ws_byt
         st = mpdo_expect(ctx, c.n_terms, c.term_first, c.term_len, c.term_ops, 1, c.out);
     if (st == MPDO_OK && c.out_trace) st = mpdo_trace(ctx, c.out_trace);
     if (st == MPDO_OK && c.out_bonds) st = mpdo_bond_dims(ctx, c.out_bonds);
+    if (st != MPDO_OK) fe.note(index, mpdo_last_error(ctx));
     mpdo_destroy(ctx);
     return st;
 }
@@ -130,9 +151,32 @@ mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers
         if (circuits[a].chi_max != circuits[b].chi_max) return circuits[a].chi_max > circuits[b].chi_max;
         return cost[a] > cost[b];
     });
+    FirstError fe;
+    auto run_on = [&](int i, hipStream_t stream, char* ws) {
+        const auto t0 = std::chrono::steady_clock::now();
+        circuits[i].status = run_one(circuits[i], stream, ws, per, i, fe);
+        const auto t1 = std::chrono::steady_clock::now();
+        circuits[i].seconds = std::chrono::duration<double>(t1 - t0).count();
+    };
+    // The smallest circuit runs alone in the calling thread before the workers start, so the
+    // library's first use in the process (the runtime loading its code objects, per-thread
+    // runtime state) is not made by many threads at once.
+    const int first = order.back();
+    order.pop_back();
+    {
+        hipStream_t s0 = nullptr;
+        if (hipStreamCreateWithFlags(&s0, hipStreamNonBlocking) != hipSuccess) {
+            fe.note(first, "stream creation failed");
+            circuits[first].status = MPDO_E_DEVICE;
+        } else {
+            run_on(first, s0, base);
+            (void)hipStreamDestroy(s0);
+        }
+    }
+    const int n_rest = (int)order.size();
     std::atomic<int> next(0);
     std::vector<std::thread> pool;
-    for (int w = 0; w < n_workers; ++w) {
+    for (int w = 0; w < std::min(n_workers, std::max(n_rest, 1)); ++w) {
         pool.emplace_back([&, w]() {
             (void)hipSetDevice(device);
             hipStream_t stream = nullptr;
@@ -140,12 +184,14 @@ mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers
             char* ws = base + per * (size_t)w;
             for (;;) {
                 const int q = next.fetch_add(1);
-                if (q >= n_circuits) break;
+                if (q >= n_rest) break;
                 const int i = order[q];
-                const auto t0 = std::chrono::steady_clock::now();
-                circuits[i].status = stream ? run_one(circuits[i], stream, ws, per) : MPDO_E_DEVICE;
-                const auto t1 = std::chrono::steady_clock::now();
-                circuits[i].seconds = std::chrono::duration<double>(t1 - t0).count();
+                if (stream) {
+                    run_on(i, stream, ws);
+                } else {
+                    fe.note(i, "stream creation failed");
+                    circuits[i].status = MPDO_E_DEVICE;
+                }
             }
             if (stream) (void)hipStreamDestroy(stream);
         });
@@ -153,7 +199,10 @@ mpdo_status mpdo_run_batch(mpdo_circuit* circuits, int n_circuits, int n_workers
     for (auto& t : pool) t.join();
     if (own) (void)hipFree(base);
     for (int i = 0; i < n_circuits; ++i)
-        if (circuits[i].status != MPDO_OK) return (mpdo_status)circuits[i].status;
+        if (circuits[i].status != MPDO_OK) {
+            mpdo::set_thread_error(fe.msg);
+            return (mpdo_status)circuits[i].status;
+        }
     return MPDO_OK;
 }
 

@@ -419,5 +419,5 @@ def run_batch(descs, n_workers: int = 8, device: int = 0):
     del ws
     if status != 0:
         bad = [i for i in range(n) if arr[i].status != 0]
-        raise MpdoError(status, f"batch circuits failed: {bad[:8]}")
+        raise MpdoError(status, f"batch circuits failed: {bad[:8]}; first: {lib.mpdo_last_error(None).decode()}")
     return res

@@ -46,6 +46,24 @@ def test_batch_rejects_bad_circuit():
         mpdo.run_batch([d], n_workers=1)
 
 
+def test_batch_reports_the_first_failure_message():
+    """A circuit that fails while it runs (a gate on a site past the chain) reports its own
+    status, the others still run, and the batch's error names the failing circuit with the
+    context's message."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08572_amd import circuits, mpdo
+    d0, d1 = circuits.describe(config_m0(0)), circuits.describe(config_m0(1))
+    sites = np.array(d1["op_site"]).copy()
+    sites[0] = 99
+    d1["op_site"] = sites
+    with pytest.raises(mpdo.MpdoError) as err:
+        mpdo.run_batch([d0, d1], n_workers=2)
+    print(f"[gpu] {err.value}", flush=True)
+    assert "circuit 1:" in str(err.value)
+
+
 def test_batch_of_m2_circuits_matches_oracle_and_single_runs():
     """The first 8 circuits of the 256-circuit batch workload (N 23..91, chi 64/128/256, p 1..3,
     rates log-uniform in [1e-4, 1e-2]) through mpdo_run_batch on 4 worker streams: each must
