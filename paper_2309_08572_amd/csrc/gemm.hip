@@ -826,8 +826,12 @@ double plan_cost(int M, int N, int K, int batch, bool fp64, Plan p, bool x3 = fa
     tile_dims(fp64, p.wm, bm, bn);
     const double W = (double)tiles_of(M, N, batch, p.wm, fp64) * p.ks;
     const int chunk = p.ks > 1 ? chunk_of(K, p.ks) : K;
-    // per unit of k a 16x16 tile costs 64 (FP64), 32 (FP32) or 6 (split-BF16) cycles
-    const double cyc = (x3 ? 6.0 : fp64 ? 64.0 : 32.0) * (bm / 32) * (bn / 32) * chunk;
+    // per unit of k a 16x16 tile costs 64 (FP64), 32 (FP32) or 6 (split-BF16) cycles, but a
+    // k-step of 32 takes at least the k-loop's own latency (the next tile's loads, the LDS
+    // round trip, two barriers), about 2048 cycles: the matrix work of a 32 x 32 FP64 tile.
+    // FP32 32 x 32 tiles are bound by it (measured per launch on the M3 products: slower than
+    // FP64's when planned at half the cost), the larger tiles by their matrix work.
+    const double cyc = std::max((x3 ? 6.0 : fp64 ? 64.0 : 32.0) * (bm / 32) * (bn / 32), 64.0) * chunk;
     const double mfma_us = std::ceil(W / 256.0) * cyc / 2400.0;
     const double bytes = W * chunk * (double)(bm + bn) * 2.0 * tsz;
     const double part_us = p.ks > 1 ? 2.0 * W * (double)bm * bn * 2.0 * tsz / 4e6 : 0.0;
