@@ -423,8 +423,8 @@ TRAFFIC = {
     # the complex GEMM kernels of the FP64 command (36562 dispatches, 32 x 32 tiles; plain and
     # with operand transforms): FETCH_SIZE 396.89 KiB, WRITE_SIZE 308.29 KiB per dispatch.  The
     # writes hold the k-split partial tiles, the fetches the A and B panels read once per XCD
-    "gemm": {"source": "paper_2309_08572_amd/csrc/gemm.hip", "sha256_16": "439d768b37f56d6d",
-             "bytes_per_launch": 1128419.0},
+    "gemm": {"source": "paper_2309_08572_amd/csrc/gemm.hip", "sha256_16": "75cf86fb53f0c4b7",
+             "bytes_per_launch": 1128412.0},
     # the timed family is the on-chip reduction of the core splits (orders 33..192; the range
     # bases take the pivoted Cholesky, the gate factorisations are cached after the warm-up):
     # 486 dispatches, FETCH_SIZE 73.96 KiB, WRITE_SIZE 54.04 KiB
